@@ -1,0 +1,209 @@
+/*
+ * raks.h -- C ABI of the MI355X (gfx950) library for radial pattern keyword
+ * search on knowledge graphs (RAKS; Yang & Tung, "Efficient Radial Pattern
+ * Keyword Search on Knowledge Graphs in Parallel").
+ *
+ * Every call returns RAKS_OK (0) or a negative error code; no exception
+ * crosses the ABI.  raks_last_error() gives a message for the last failing
+ * call on the calling thread.  All pointers in descriptors are HOST pointers
+ * unless stated otherwise; the library copies what it needs before returning
+ * and never keeps a caller pointer.  One context owns one graph and its device
+ * state on one GPU; calls on one context must come from one thread at a time.
+ *
+ * The arithmetic is integer once the activation levels are set; every result
+ * is bit-for-bit deterministic.
+ */
+#ifndef RAKS_H
+#define RAKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RAKS_OK 0
+#define RAKS_EINVAL (-1)  /* invalid argument or graph contract violated */
+#define RAKS_ENOMEM (-2)  /* device or host allocation failed / budget exceeded */
+#define RAKS_EDEVICE (-3) /* HIP runtime error or no usable gfx950 device */
+#define RAKS_ESTATE (-4)  /* call not valid in the context's current state */
+#define RAKS_EAGAIN (-5)  /* result not ready yet */
+
+#define RAKS_ACT_EDGE 0   /* activation per arc from label frequencies (Section 3.1) */
+#define RAKS_ACT_NODE 1   /* activation per node from node weights (same Eqs. 1-3) */
+
+/* Bit flags of raks_results.status */
+#define RAKS_STATUS_CG_LEVEL_BOUND 1   /* central run hit max_level with fewer than w CGs */
+#define RAKS_STATUS_RPG_LEVEL_BOUND 2  /* marginal run hit max_level before a stop rule */
+
+/* End reasons of a run (raks_query_stats.end_reason) */
+#define RAKS_END_NONE 0           /* run not executed */
+#define RAKS_END_EXHAUSTED 1      /* frontier became empty */
+#define RAKS_END_STOP 2           /* >= w CGs (central run); Theorem 4 or every CG has an RPG (marginal run) */
+#define RAKS_END_LEVEL_BOUND 3    /* the level bound was reached */
+#define RAKS_END_EMPTY_KEYWORD 4  /* a keyword of the run has no node */
+
+typedef struct raks_ctx raks_ctx;
+
+/* Optional device allocator: returns a device pointer of at least `bytes`
+ * bytes aligned to 256, or NULL.  Used for every device buffer the context
+ * owns.  Both callbacks may be NULL (then hipMalloc/hipFree are used). */
+typedef void* (*raks_alloc_fn)(size_t bytes, void* user);
+typedef void (*raks_free_fn)(void* ptr, size_t bytes, void* user);
+
+typedef struct {
+    int32_t device;         /* HIP device ordinal */
+    void* stream;           /* hipStream_t to run on, or NULL for a library-owned stream */
+    raks_alloc_fn alloc;    /* optional device allocator (see above) */
+    raks_free_fn free;
+    void* alloc_user;
+    uint64_t mem_budget;    /* bytes of device memory the context may hold; 0 = no limit */
+} raks_ctx_opts;
+
+/* Creates a context on opts->device (opts may be NULL: device 0, own stream,
+ * hipMalloc).  Fails with RAKS_EDEVICE when the device is not gfx950.
+ * *out is owned by the caller until raks_destroy. */
+int raks_create(raks_ctx** out, const raks_ctx_opts* opts);
+
+/* Frees every device and host resource of the context (NULL-safe). */
+int raks_destroy(raks_ctx* ctx);
+
+/* Graph input (Section 2: a bi-directed labelled knowledge graph stored as
+ * CSR, Section 4.1).  Contract, checked on the device (RAKS_EINVAL if broken):
+ *   - row_ptr[0] = 0, non-decreasing, row_ptr[n_nodes] = n_arcs < 2^32;
+ *   - 0 <= col[e] < n_nodes, no self-loops;
+ *   - each row sorted strictly increasing by (label, col);
+ *   - bi-directed: for every arc (u -> v, l) the arc (v -> u, l) exists;
+ *   - keyword t owns kw_nodes[kw_ptr[t] .. kw_ptr[t+1]), strictly increasing
+ *     node ids (the keyword -> node mapping of Section 4.1);
+ *   - 0 < a_bar <= 100 (average shortest hop count, Section 3.1),
+ *     0 < alpha < 1 (Eqs. 1-2).
+ * node_weight may be NULL in RAKS_ACT_EDGE mode.  Arrays are copied; the
+ * caller may free them on return.  Replaces a previously loaded graph. */
+typedef struct {
+    int32_t n_nodes;
+    int64_t n_arcs;
+    const int64_t* row_ptr;      /* [n_nodes + 1] */
+    const int32_t* col;          /* [n_arcs] */
+    const uint16_t* label;       /* [n_arcs] */
+    const uint8_t* node_weight;  /* [n_nodes] (RAKS_ACT_NODE) */
+    int32_t n_keywords;
+    const int64_t* kw_ptr;       /* [n_keywords + 1] */
+    const int32_t* kw_nodes;     /* [kw_ptr[n_keywords]] */
+    double a_bar;
+    double alpha;
+    int32_t act_mode;            /* RAKS_ACT_EDGE or RAKS_ACT_NODE */
+} raks_graph_desc;
+
+/* Loads the graph and computes activation levels on the GPU (Section 3.1,
+ * Eqs. 1-3): EDGE mode per arc from c = |arcs of src with the label| +
+ * |arcs into dst with the label|, rescaled log weights, reward/penalty around
+ * a_bar, round half up; NODE mode per node from node_weight min-max rescaled.
+ * Errors: RAKS_EINVAL (contract), RAKS_ENOMEM, RAKS_EDEVICE. */
+int raks_load_graph(raks_ctx* ctx, const raks_graph_desc* g);
+
+/* Recomputes the activation levels for a new alpha (users adjust the search
+ * granularity with alpha, Section 3.1).  RAKS_ESTATE without a graph. */
+int raks_set_alpha(raks_ctx* ctx, double alpha);
+
+/* Copies the per-arc activation levels (uint8 [n_arcs]) to host memory
+ * `out`.  In NODE mode the level of arc u -> v is that of node v. */
+int raks_get_activations(raks_ctx* ctx, uint8_t* out, int64_t n);
+
+/* A radial pattern query (Definition 1) and its parameters (Table 2).
+ *   central: 1..16 distinct keyword ids; marginal: 0..16 distinct ids, none
+ *   central.  k >= 1 results, beam width w >= k (0 = k) and w <= 256
+ *   (Section 3.4); gamma = gamma_num/gamma_den in [0,1] (Eq. 6; 0/0 = 1/2);
+ *   max_level in 1..250 (0 = 20, the paper's level bound).
+ * Violations give RAKS_EINVAL.  A keyword with no node gives no results. */
+typedef struct {
+    const int32_t* central;
+    int32_t n_central;
+    const int32_t* marginal;
+    int32_t n_marginal;
+    int32_t k;
+    int32_t w;
+    int32_t gamma_num;
+    int32_t gamma_den;
+    int32_t max_level;
+} raks_query_desc;
+
+typedef struct {
+    int32_t src, dst, label;
+} raks_arc;
+
+/* One result subgraph: a radial pattern graph (Definition 5) or, without
+ * marginal keywords, a central graph (Definition 4).  score_c = S^c (Eq. 4),
+ * score_m = S^m (Eq. 5), key = gamma_num*S^c + (gamma_den-gamma_num)*S^m,
+ * i.e. gamma_den * S^r (Eq. 6).  nodes ascending; arcs in CSR order, i.e. by
+ * (src, label, dst); each arc points along the search direction (from a
+ * keyword node towards the central node / the central-keyword nodes). */
+typedef struct {
+    int32_t central_node;
+    int32_t score_c;
+    int32_t score_m;
+    int64_t key;
+    int32_t n_nodes;
+    const int32_t* nodes;
+    int32_t n_arcs;
+    const raks_arc* arcs;
+} raks_result;
+
+/* Per-run work counters ([0] central run, [1] marginal run). */
+typedef struct {
+    int32_t levels[2];       /* levels processed (identification passes) */
+    int32_t end_reason[2];   /* RAKS_END_* */
+    int64_t frontier[2];     /* sum over levels of |frontier| */
+    int64_t e_arc[2];        /* arcs scanned: degrees of expanding frontiers */
+    int64_t e_alg[2];        /* arcs scanned per (frontier, keyword) pair, as Algorithm 1 counts */
+    int64_t gate_pass[2];    /* scanned arcs whose level allowed expansion */
+    int64_t h_writes[2];     /* node-keyword matrix entries written */
+    int32_t n_cg;            /* central graphs identified by the central run */
+    double device_ms;        /* wall time of the query on the device stream */
+} raks_query_stats;
+
+typedef struct {
+    int32_t n;               /* number of results (<= k) */
+    raks_result* r;          /* ranked by (key, score_c, CG rank) */
+    raks_query_stats stats;
+    int32_t status;          /* RAKS_STATUS_* bits */
+} raks_results;
+
+/* Runs one query (both runs of Section 4.1 on the GPU: exploration,
+ * identification, top-w selection, recovery, marginal run, ranking) and
+ * returns its results.  *out is library-owned until raks_results_free. */
+int raks_query(raks_ctx* ctx, const raks_query_desc* q, raks_results** out);
+
+/* Runs n queries; outs[i] receives the results of qs[i] (each owned
+ * independently).  On error no output is left allocated. */
+int raks_query_batch(raks_ctx* ctx, const raks_query_desc* qs, int32_t n, raks_results** outs);
+
+/* Frees results (NULL-safe). */
+void raks_results_free(raks_results* r);
+
+/* Per-kernel device time, accumulated while timing is enabled
+ * (raks_set_timing).  kernel ids: 0 expansion (Algorithm 1), 1 frontier
+ * scan/enqueue, 2 identification/control, 3 recovery, 4 other. */
+typedef struct {
+    int64_t launches;
+    double ms;               /* summed event-measured duration */
+    double bytes;            /* algorithmic bytes moved (expansion only) */
+} raks_kernel_timing;
+
+/* Enables (1) or disables (0) per-launch event timing; enabling resets the
+ * accumulators. */
+int raks_set_timing(raks_ctx* ctx, int32_t enable);
+int raks_get_timing(raks_ctx* ctx, int32_t kernel, raks_kernel_timing* out);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* raks_last_error(void);
+
+/* Library version string. */
+const char* raks_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAKS_H */

@@ -1,0 +1,258 @@
+"""Radial pattern keyword search (RAKS) on MI355X / gfx950.
+
+Thin ctypes binding of ``libraks.so`` (C ABI in ``include/raks.h``): it only
+marshals arguments; every step of a query runs in the library's HIP kernels.
+PyTorch provides device memory (its caching allocator) and the HIP stream.
+There is no CPU fallback: without the built library every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libraks.so")
+
+RAKS_ACT_EDGE, RAKS_ACT_NODE = 0, 1
+END_NAMES = {0: "none", 1: "exhausted", 2: "stop", 3: "level_bound", 4: "empty_keyword"}
+TIMER_EXPAND, TIMER_SCAN, TIMER_CONTROL, TIMER_RECOVER, TIMER_OTHER = range(5)
+
+_ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+
+
+class CtxOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("alloc", _ALLOC),
+                ("free", _FREE), ("alloc_user", ctypes.c_void_p), ("mem_budget", ctypes.c_uint64)]
+
+
+class GraphDesc(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int32), ("n_arcs", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("label", ctypes.c_void_p), ("node_weight", ctypes.c_void_p),
+                ("n_keywords", ctypes.c_int32), ("kw_ptr", ctypes.c_void_p),
+                ("kw_nodes", ctypes.c_void_p), ("a_bar", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("act_mode", ctypes.c_int32)]
+
+
+class QueryDesc(ctypes.Structure):
+    _fields_ = [("central", ctypes.c_void_p), ("n_central", ctypes.c_int32),
+                ("marginal", ctypes.c_void_p), ("n_marginal", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("w", ctypes.c_int32), ("gamma_num", ctypes.c_int32),
+                ("gamma_den", ctypes.c_int32), ("max_level", ctypes.c_int32)]
+
+
+class Arc(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_int32), ("dst", ctypes.c_int32), ("label", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("central_node", ctypes.c_int32), ("score_c", ctypes.c_int32),
+                ("score_m", ctypes.c_int32), ("key", ctypes.c_int64),
+                ("n_nodes", ctypes.c_int32), ("nodes", ctypes.POINTER(ctypes.c_int32)),
+                ("n_arcs", ctypes.c_int32), ("arcs", ctypes.POINTER(Arc))]
+
+
+class QueryStats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32 * 2), ("end_reason", ctypes.c_int32 * 2),
+                ("frontier", ctypes.c_int64 * 2), ("e_arc", ctypes.c_int64 * 2),
+                ("e_alg", ctypes.c_int64 * 2), ("gate_pass", ctypes.c_int64 * 2),
+                ("h_writes", ctypes.c_int64 * 2), ("n_cg", ctypes.c_int32),
+                ("device_ms", ctypes.c_double)]
+
+
+class Results(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("r", ctypes.POINTER(Result)), ("stats", QueryStats),
+                ("status", ctypes.c_int32)]
+
+
+class KernelTiming(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+class RaksError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"raks error {code}: {msg}")
+        self.code = code
+
+
+_lib_handle = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.raks_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(CtxOpts)]
+        L.raks_destroy.argtypes = [ctypes.c_void_p]
+        L.raks_load_graph.argtypes = [ctypes.c_void_p, ctypes.POINTER(GraphDesc)]
+        L.raks_set_alpha.argtypes = [ctypes.c_void_p, ctypes.c_double]
+        L.raks_get_activations.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+        L.raks_query.argtypes = [ctypes.c_void_p, ctypes.POINTER(QueryDesc),
+                                 ctypes.POINTER(ctypes.POINTER(Results))]
+        L.raks_query_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(QueryDesc), ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.POINTER(Results))]
+        L.raks_results_free.argtypes = [ctypes.POINTER(Results)]
+        L.raks_results_free.restype = None
+        L.raks_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+        L.raks_get_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(KernelTiming)]
+        L.raks_last_error.restype = ctypes.c_char_p
+        L.raks_version.restype = ctypes.c_char_p
+        _lib_handle = L
+    return _lib_handle
+
+
+EXPORTED = ("raks_create", "raks_destroy", "raks_load_graph", "raks_set_alpha",
+            "raks_get_activations", "raks_query", "raks_query_batch", "raks_results_free",
+            "raks_set_timing", "raks_get_timing", "raks_last_error", "raks_version")
+
+
+def _check(rc):
+    if rc != 0:
+        raise RaksError(rc, lib().raks_last_error().decode())
+
+
+def _results_to_dict(res: Results) -> dict:
+    st = res.stats
+    stats = []
+    for k in range(2):
+        d = {"levels": int(st.levels[k]), "end_reason": int(st.end_reason[k]),
+             "frontier": int(st.frontier[k]), "e_arc": int(st.e_arc[k]),
+             "e_alg": int(st.e_alg[k]), "gate_pass": int(st.gate_pass[k]),
+             "h_writes": int(st.h_writes[k])}
+        d["end"] = END_NAMES.get(d["end_reason"], "?")
+        stats.append(d)
+    out = {"status": int(res.status), "n_cg": int(st.n_cg), "stats": stats, "results": [],
+           "device_ms": float(st.device_ms)}
+    for i in range(res.n):
+        r = res.r[i]
+        nodes = np.ctypeslib.as_array(r.nodes, shape=(r.n_nodes,)) if r.n_nodes else np.empty(0, np.int32)
+        arcs = (np.ctypeslib.as_array(ctypes.cast(r.arcs, ctypes.POINTER(ctypes.c_int32)),
+                                      shape=(r.n_arcs * 3,)).reshape(-1, 3)
+                if r.n_arcs else np.empty((0, 3), np.int32))
+        out["results"].append({"central": int(r.central_node), "score_c": int(r.score_c),
+                               "score_m": int(r.score_m), "key": int(r.key),
+                               "nodes": tuple(int(x) for x in nodes),
+                               "arcs": tuple((int(a), int(b), int(c)) for a, b, c in arcs)})
+    return out
+
+
+class Context:
+    """One GPU context holding one graph (``raks_ctx``)."""
+
+    def __init__(self, device: int = 0, use_torch: bool = True, mem_budget: int = 0):
+        self._keep = []
+        opts = CtxOpts()
+        opts.device = device
+        opts.mem_budget = mem_budget
+        if use_torch:
+            import torch
+            if not torch.cuda.is_available():
+                raise RuntimeError("no GPU visible to torch")
+            dev = torch.device("cuda", device)
+            stream = torch.cuda.current_stream(dev)
+            opts.stream = ctypes.c_void_p(stream.cuda_stream)
+
+            def _alloc(size, _user, _torch=torch, _dev=device, _s=stream):
+                try:
+                    return _torch.cuda.caching_allocator_alloc(size, _dev, _s)
+                except Exception:
+                    return None
+
+            def _free(ptr, _size, _user, _torch=torch):
+                _torch.cuda.caching_allocator_delete(ptr)
+
+            opts.alloc = _ALLOC(_alloc)
+            opts.free = _FREE(_free)
+            self._keep += [opts.alloc, opts.free, stream]
+        self._h = ctypes.c_void_p()
+        _check(lib().raks_create(ctypes.byref(self._h), ctypes.byref(opts)))
+
+    def close(self):
+        if self._h:
+            lib().raks_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def load_graph(self, g, alpha: float = 0.5, mode: int = RAKS_ACT_EDGE, abar: float = None):
+        """``g``: arrays of a bi-directed CSR graph (``synth.Graph`` or alike)."""
+        arrs = [np.ascontiguousarray(g.row_ptr, np.int64), np.ascontiguousarray(g.col, np.int32),
+                np.ascontiguousarray(g.label, np.uint16),
+                np.ascontiguousarray(g.node_weight, np.uint8),
+                np.ascontiguousarray(g.kw_ptr, np.int64), np.ascontiguousarray(g.kw_nodes, np.int32)]
+        rp, col, lab, nw, kp, kn = arrs
+        d = GraphDesc(int(g.n_nodes), int(col.shape[0]), rp.ctypes.data, col.ctypes.data,
+                      lab.ctypes.data, nw.ctypes.data, int(kp.shape[0] - 1), kp.ctypes.data,
+                      kn.ctypes.data, float(g.abar if abar is None else abar), float(alpha), int(mode))
+        _check(lib().raks_load_graph(self._h, ctypes.byref(d)))
+        self.n_arcs = int(col.shape[0])
+
+    def set_alpha(self, alpha: float):
+        _check(lib().raks_set_alpha(self._h, float(alpha)))
+
+    def activations(self) -> np.ndarray:
+        out = np.empty(self.n_arcs, np.uint8)
+        _check(lib().raks_get_activations(self._h, out.ctypes.data, self.n_arcs))
+        return out
+
+    @staticmethod
+    def _desc(q, keep):
+        c = np.ascontiguousarray(q.central, np.int32)
+        m = np.ascontiguousarray(q.marginal if len(q.marginal) else [0], np.int32)
+        keep += [c, m]
+        return QueryDesc(c.ctypes.data, len(q.central), m.ctypes.data, len(q.marginal), q.k, q.w,
+                         getattr(q, "gamma_num", 1), getattr(q, "gamma_den", 2),
+                         getattr(q, "max_level", 20))
+
+    def query(self, q) -> dict:
+        keep = []
+        d = self._desc(q, keep)
+        out = ctypes.POINTER(Results)()
+        _check(lib().raks_query(self._h, ctypes.byref(d), ctypes.byref(out)))
+        try:
+            return _results_to_dict(out.contents)
+        finally:
+            lib().raks_results_free(out)
+
+    def query_batch(self, qs) -> list:
+        keep = []
+        arr = (QueryDesc * len(qs))(*[self._desc(q, keep) for q in qs])
+        outs = (ctypes.POINTER(Results) * len(qs))()
+        _check(lib().raks_query_batch(self._h, arr, len(qs), outs))
+        res = []
+        try:
+            for o in outs:
+                res.append(_results_to_dict(o.contents))
+        finally:
+            for o in outs:
+                lib().raks_results_free(o)
+        return res
+
+    def set_timing(self, enable: bool):
+        _check(lib().raks_set_timing(self._h, int(enable)))
+
+    def timing(self, kernel: int) -> dict:
+        t = KernelTiming()
+        _check(lib().raks_get_timing(self._h, kernel, ctypes.byref(t)))
+        return {"launches": int(t.launches), "ms": float(t.ms), "bytes": float(t.bytes)}
+
+
+def version() -> str:
+    return lib().raks_version().decode()

@@ -1,0 +1,572 @@
+// explore.hip -- exploration phase (Section 4.2) on gfx950.
+//
+// One level of a run is four launches:
+//   k_front_count   frontier scan: every workgroup takes 4096 frontier flags
+//                   (16 per thread, one 16-byte load), inspects the H rows of
+//                   flagged nodes (complete row -> central node / PTC block,
+//                   keywords with h <= level, degree) and writes its totals;
+//   k_front_control one workgroup: scans the totals, applies the run's
+//                   identification and termination rules (Theorem identifyCG,
+//                   >= w CGs; the RPG check over each CG's V_C rows and
+//                   Theorem 4), and decides whether this level expands;
+//   k_front_write   Frontier Enqueue: writes the expansion queue in node order
+//                   (node, row start, keyword mask, degree prefix), records
+//                   the identified central nodes and clears F;
+//   k_expand        Algorithm 1 for every (frontier, arc) pair, balanced by
+//                   arcs: each workgroup takes tiles of 1024 consecutive arcs
+//                   of the concatenated frontier rows, so a hub's arcs spread
+//                   over many workgroups; one H-row gather serves all keywords
+//                   of the frontier at once.
+// Writes need no atomics (Theorem "lockfree"): every H write of a level
+// stores level+1 into a byte that was INF, every F write stores 1.  The
+// joining flag array is implied by H: a node is blocked exactly when its row
+// is complete, and it is identified at the level equal to its row maximum.
+#include <climits>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace raks {
+
+template <int TP> struct RowVec;
+template <> struct RowVec<4> { using T = uint32_t; };
+template <> struct RowVec<8> { using T = uint2; };
+template <> struct RowVec<16> { using T = uint4; };
+
+template <int TP>
+__device__ inline void load_row(const uint8_t* H, int64_t v, uint8_t (&b)[TP]) {
+  using V = typename RowVec<TP>::T;
+  V x = *reinterpret_cast<const V*>(H + v * TP);
+  __builtin_memcpy(b, &x, TP);
+}
+
+// ------------------------------------------------------------- run init ---
+
+__global__ void k_run_reset(RunStatus* st, int32_t empty) {
+  RunStatus s = {};
+  s.end_level = empty ? -1 : INT32_MAX;
+  s.end_reason = empty ? END_EMPTY_KEYWORD : END_NONE;
+  *st = s;
+}
+
+template <int TP>
+__global__ __launch_bounds__(kBlock) void k_init_rows(uint8_t* H, uint8_t* F, int32_t n,
+                                                      int32_t n_pad, int32_t T) {
+  uint8_t b[TP];
+#pragma unroll
+  for (int i = 0; i < TP; ++i) b[i] = i < T ? kInf : 0;
+  typename RowVec<TP>::T pat;
+  __builtin_memcpy(&pat, b, TP);
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n_pad; v += stride) {
+    reinterpret_cast<typename RowVec<TP>::T*>(H)[v] = pat;
+    if (v < n_pad / 16) reinterpret_cast<uint4*>(F)[v] = make_uint4(0, 0, 0, 0);
+  }
+}
+
+template <int TP>
+__global__ __launch_bounds__(kBlock) void k_seed(uint8_t* H, uint8_t* F, const int32_t* kw_nodes,
+                                                 SeedList s) {
+  const uint32_t total = s.prefix[s.T];
+  for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < total; p += gridDim.x * kBlock) {
+    int i = 0;
+    while (p >= s.prefix[i + 1]) ++i;
+    const int32_t v = kw_nodes[s.start[i] + (p - s.prefix[i])];
+    H[(int64_t)v * TP + i] = 0;   // keyword nodes are at distance 0
+    F[v] = 1;                     // and form the first frontier
+  }
+}
+
+// --------------------------------------------------------- frontier scan ---
+
+struct NodeInfo {
+  uint32_t mask, deg;
+  bool active, cand;
+  uint64_t key;
+};
+
+template <int TP>
+__device__ inline NodeInfo inspect_node(const RunView& r, const uint32_t* row_ptr, int32_t v,
+                                        int level) {
+  uint8_t b[TP];
+  load_row<TP>(r.H, v, b);
+  bool complete = true;
+  uint32_t m = 0, mx = 0, sum = 0;
+#pragma unroll
+  for (int i = 0; i < TP; ++i) {
+    const uint32_t h = b[i];
+    const bool inf = h == kInf;
+    complete &= !inf;
+    if (h <= (uint32_t)level) m |= 1u << i;
+    mx = (!inf && h > mx) ? h : mx;
+    sum += inf ? 0u : h;
+  }
+  m &= r.tmask;
+  NodeInfo o;
+  const bool blocked = r.block_rule && complete;
+  const uint32_t d = row_ptr[v + 1] - row_ptr[v];
+  o.active = !blocked && m != 0 && d > 0;
+  o.mask = m;
+  o.deg = o.active ? d : 0;
+  o.cand = (r.kind == RUN_CENTRAL) && complete && mx == (uint32_t)level;
+  o.key = ((uint64_t)mx << 48) | ((uint64_t)sum << 32) | (uint32_t)v;
+  return o;
+}
+
+template <int TP>
+__global__ __launch_bounds__(kBlock) void k_front_count(RunView r, const uint32_t* row_ptr,
+                                                        int level) {
+  if (level > r.st->end_level) return;
+  __shared__ uint32_t s32[kBlock / kWave + 1];
+  __shared__ uint64_t s64[kBlock / kWave + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanNodes + threadIdx.x * 16;
+  const uint4 fw = *reinterpret_cast<const uint4*>(r.F + base);
+  uint32_t nf = 0, na = 0, nc = 0, dg = 0;
+  uint64_t dk = 0;
+  if (fw.x | fw.y | fw.z | fw.w) {
+    uint8_t fb[16];
+    __builtin_memcpy(fb, &fw, 16);
+    for (int k = 0; k < 16; ++k) {
+      if (!fb[k]) continue;
+      const NodeInfo o = inspect_node<TP>(r, row_ptr, (int32_t)(base + k), level);
+      ++nf;
+      if (o.active) { ++na; dg += o.deg; dk += (uint64_t)o.deg * __popc(o.mask); }
+      nc += o.cand;
+    }
+  }
+  nf = block_sum<uint32_t, kBlock>(nf, s32);
+  na = block_sum<uint32_t, kBlock>(na, s32);
+  nc = block_sum<uint32_t, kBlock>(nc, s32);
+  dg = block_sum<uint32_t, kBlock>(dg, s32);
+  dk = block_sum<uint64_t, kBlock>(dk, s64);
+  if (threadIdx.x == 0) {
+    ScanTot t;
+    t.nfront = nf; t.nactive = na; t.ncand = nc; t.deg = dg; t.degk = dk;
+    r.tot[blockIdx.x] = t;
+  }
+}
+
+constexpr int kCtl = 1024;
+
+// Marginal run identification (Section 4.2.3): for every selected CG without
+// an RPG, D_j = min over its central-keyword nodes of h_j; all finite -> RPG
+// with S^m = max_j D_j (Eq. 5) and key gamma_num*S^c + (gamma_den-gamma_num)*S^m
+// (Eq. 6 scaled by gamma_den).  Then the stop rules: every CG has an RPG, or
+// Theorem 4 with the k-th RPG in (key, S^c, CG rank) order.
+template <int TP>
+__device__ int rpg_identify(const RunView& r, RunStatus* st, int level) {
+  __shared__ uint32_t s_dm[kMaxW * kMaxKw];
+  __shared__ int32_t s_has[kMaxW], s_sm[kMaxW];
+  __shared__ int64_t s_key[kMaxW];
+  __shared__ int32_t s_new, s_nrpg, s_kth, s_minsc, s_stop;
+  const int nsel = r.nsel, M = r.T;
+  const int64_t gn = r.gamma_num, gd = r.gamma_den;
+  for (int i = threadIdx.x; i < nsel * kMaxKw; i += kCtl) s_dm[i] = kInf;
+  for (int i = threadIdx.x; i < nsel; i += kCtl) {
+    s_has[i] = r.has_rpg[i]; s_sm[i] = r.sm[i]; s_key[i] = r.key[i];
+  }
+  if (threadIdx.x == 0) { s_new = 0; s_kth = -1; s_minsc = INT32_MAX; s_stop = 0; }
+  __syncthreads();
+  const uint32_t total = r.vc_off[nsel];
+  for (uint32_t p = threadIdx.x; p < total; p += kCtl) {
+    const int rr = upper_index<uint32_t>(r.vc_off, 0, nsel + 1, p);
+    if (s_has[rr]) continue;
+    uint8_t b[TP];
+    load_row<TP>(r.H, r.vc_nodes[p], b);
+#pragma unroll
+    for (int j = 0; j < TP; ++j)
+      if (j < M) atomicMin(&s_dm[rr * kMaxKw + j], (uint32_t)b[j]);
+  }
+  __syncthreads();
+  for (int rr = threadIdx.x; rr < nsel; rr += kCtl) {
+    if (s_has[rr]) continue;
+    bool all = true;
+    int smax = 0;
+    for (int j = 0; j < M; ++j) {
+      const int d = (int)s_dm[rr * kMaxKw + j];
+      r.dmin[rr * kMaxKw + j] = (uint8_t)d;
+      all &= d != kInf;
+      smax = d > smax ? d : smax;
+    }
+    if (all) {
+      s_has[rr] = 1;
+      s_sm[rr] = smax;
+      s_key[rr] = gn * r.sel_sc[rr] + (gd - gn) * smax;
+      atomicAdd(&s_new, 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) { s_nrpg = (int)st->nrpg + s_new; st->nrpg = (uint32_t)s_nrpg; }
+  __syncthreads();
+  const int nrpg = s_nrpg;
+  if (nrpg == nsel) {
+    s_stop = 1;
+  } else if (nrpg >= r.k) {
+    for (int rr = threadIdx.x; rr < nsel; rr += kCtl) {
+      if (s_has[rr]) {
+        int rank = 0;
+        for (int o = 0; o < nsel; ++o) {
+          if (!s_has[o]) continue;
+          const bool less = s_key[o] < s_key[rr] ||
+                            (s_key[o] == s_key[rr] && (r.sel_sc[o] < r.sel_sc[rr] ||
+                                                       (r.sel_sc[o] == r.sel_sc[rr] && o < rr)));
+          rank += less;
+        }
+        if (rank == r.k - 1) s_kth = rr;
+      } else {
+        atomicMin(&s_minsc, r.sel_sc[rr]);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int kth = s_kth;
+      if (s_key[kth] <= gn * (int64_t)s_minsc + (gd - gn) * (int64_t)s_sm[kth]) s_stop = 1;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nsel; i += kCtl) {
+    r.has_rpg[i] = s_has[i]; r.sm[i] = s_sm[i]; r.key[i] = s_key[i];
+  }
+  return s_stop;
+}
+
+template <int TP>
+__global__ __launch_bounds__(kCtl) void k_front_control(RunView r, int level) {
+  RunStatus* st = r.st;
+  if (level > st->end_level) return;
+  __shared__ uint32_t s32[kCtl / kWave + 1];
+  __shared__ uint64_t s64[kCtl / kWave + 1];
+  __shared__ int32_t s_end;
+  const int nb = r.nblocks;
+  const int per = (nb + kCtl - 1) / kCtl;
+  const int b0 = min(nb, (int)threadIdx.x * per), b1 = min(nb, b0 + per);
+  uint32_t nf = 0, na = 0, nc = 0, dg = 0;
+  uint64_t dk = 0;
+  for (int b = b0; b < b1; ++b) {
+    const ScanTot t = r.tot[b];
+    nf += t.nfront; na += t.nactive; nc += t.ncand; dg += t.deg; dk += t.degk;
+  }
+  uint32_t tnf, tna, tnc, tdg;
+  uint64_t tdk;
+  (void)block_exclusive_scan<uint32_t, kCtl>(nf, s32, &tnf);
+  uint32_t xa = block_exclusive_scan<uint32_t, kCtl>(na, s32, &tna);
+  uint32_t xc = block_exclusive_scan<uint32_t, kCtl>(nc, s32, &tnc);
+  uint32_t xd = block_exclusive_scan<uint32_t, kCtl>(dg, s32, &tdg);
+  (void)block_exclusive_scan<uint64_t, kCtl>(dk, s64, &tdk);
+  for (int b = b0; b < b1; ++b) {
+    const ScanTot t = r.tot[b];
+    ScanOff o;
+    o.active = xa; o.deg = xd; o.cand = xc; o.pad = 0;
+    r.off[b] = o;
+    xa += t.nactive; xd += t.deg; xc += t.ncand;
+  }
+  if (threadIdx.x == 0) {
+    st->levels = level + 1;
+    st->nfront = tnf;
+    st->nactive = tna;
+    st->W = tdg;
+    st->ncand_level = tnc;
+    st->frontier_sum += tnf;
+    r.q_off[tna] = tdg;
+    s_end = END_NONE;
+    if (tnf == 0) {
+      s_end = END_EXHAUSTED;
+    } else if (r.kind == RUN_CENTRAL) {
+      st->ncand_total += tnc;
+      if (st->ncand_total >= (uint32_t)r.w) s_end = END_STOP;
+    }
+  }
+  __syncthreads();
+  if (s_end == END_NONE && r.kind == RUN_MARGINAL) {
+    if (rpg_identify<TP>(r, st, level) && threadIdx.x == 0) s_end = END_STOP;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (s_end == END_NONE && level >= r.max_level) s_end = END_LEVEL_BOUND;
+    if (s_end != END_NONE) {
+      st->end_level = level;
+      st->end_reason = s_end;
+      st->expand_on = 0;
+    } else {
+      st->expand_on = 1;
+      st->e_arc += tdg;
+      st->e_alg += tdk;
+    }
+  }
+}
+
+template <int TP>
+__global__ __launch_bounds__(kBlock) void k_front_write(RunView r, const uint32_t* row_ptr,
+                                                        int level) {
+  const RunStatus* st = r.st;
+  if (level > st->end_level) return;
+  __shared__ uint32_t s32[kBlock / kWave + 1];
+  const bool expand = st->expand_on != 0;
+  const int64_t base = (int64_t)blockIdx.x * kScanNodes + threadIdx.x * 16;
+  const uint4 fw = *reinterpret_cast<const uint4*>(r.F + base);
+  const bool any = (fw.x | fw.y | fw.z | fw.w) != 0;
+  uint8_t fb[16];
+  __builtin_memcpy(fb, &fw, 16);
+  uint32_t na = 0, nc = 0, dg = 0;
+  if (any) {
+    for (int k = 0; k < 16; ++k) {
+      if (!fb[k]) continue;
+      const NodeInfo o = inspect_node<TP>(r, row_ptr, (int32_t)(base + k), level);
+      na += o.active; nc += o.cand; dg += o.deg;
+    }
+  }
+  uint32_t t;
+  const uint32_t xa = block_exclusive_scan<uint32_t, kBlock>(na, s32, &t);
+  const uint32_t xc = block_exclusive_scan<uint32_t, kBlock>(nc, s32, &t);
+  const uint32_t xd = block_exclusive_scan<uint32_t, kBlock>(dg, s32, &t);
+  if (!any) return;
+  const ScanOff bo = r.off[blockIdx.x];
+  uint32_t apos = bo.active + xa, dpos = bo.deg + xd;
+  uint32_t cpos = (st->ncand_total - st->ncand_level) + bo.cand + xc;
+  for (int k = 0; k < 16; ++k) {
+    if (!fb[k]) continue;
+    const int32_t v = (int32_t)(base + k);
+    const NodeInfo o = inspect_node<TP>(r, row_ptr, v, level);
+    if (o.active && expand) {
+      r.q_node[apos] = v;
+      r.q_off[apos] = dpos;
+      r.q_rs[apos] = row_ptr[v];
+      r.q_mask[apos] = o.mask;
+      ++apos;
+      dpos += o.deg;
+    }
+    if (o.cand) r.cand[cpos++] = o.key;
+  }
+  *reinterpret_cast<uint4*>(r.F + base) = make_uint4(0, 0, 0, 0);
+}
+
+// Algorithm 1 at Glevel `level`, balanced over the arcs of the expanding
+// frontiers.  For arc f -> n with level a: a > level keeps f in the frontier
+// (line 10-11); otherwise every keyword i that f expands for and that has not
+// reached n gets h_ni = level + 1 and n becomes a frontier (lines 13-17).
+template <int TP>
+__global__ __launch_bounds__(kBlock) void k_expand(RunView r, DevGraphView g, int level) {
+  RunStatus* st = r.st;
+  if (level > st->end_level || !st->expand_on) return;
+  const uint32_t W = st->W, nact = st->nactive;
+  __shared__ uint32_t s_off[kExpandTile], s_rs[kExpandTile], s_mask[kExpandTile];
+  __shared__ int32_t s_node[kExpandTile];
+  __shared__ uint8_t s_ret[kExpandTile];
+  __shared__ int32_t s_e0, s_cnt;
+  uint64_t pass = 0;
+  for (uint32_t tile = blockIdx.x; (uint64_t)tile * kExpandTile < W; tile += gridDim.x) {
+    const uint32_t w0 = tile * kExpandTile;
+    const uint32_t w1 = min(W, w0 + (uint32_t)kExpandTile);
+    if (threadIdx.x == 0) {
+      const int e0 = upper_index<uint32_t>(r.q_off, 0, (int)nact, w0);
+      const int e1 = upper_index<uint32_t>(r.q_off, e0, (int)nact, w1 - 1);
+      s_e0 = e0;
+      s_cnt = e1 - e0 + 1;
+    }
+    __syncthreads();
+    const int e0 = s_e0, cnt = s_cnt;
+    for (int j = threadIdx.x; j < cnt; j += kBlock) {
+      s_off[j] = r.q_off[e0 + j];
+      s_rs[j] = r.q_rs[e0 + j];
+      s_mask[j] = r.q_mask[e0 + j];
+      s_node[j] = r.q_node[e0 + j];
+      s_ret[j] = 0;
+    }
+    __syncthreads();
+    for (uint32_t wi = w0 + threadIdx.x; wi < w1; wi += kBlock) {
+      const int j = upper_index<uint32_t>(s_off, 0, cnt, wi);
+      const uint32_t e = s_rs[j] + (wi - s_off[j]);
+      const uint32_t a = g.act[e];
+      if (a > (uint32_t)level) { s_ret[j] = 1; continue; }
+      const int32_t nb = g.col[e];
+      uint8_t b[TP];
+      load_row<TP>(r.H, nb, b);
+      uint32_t m = 0;
+#pragma unroll
+      for (int i = 0; i < TP; ++i) m |= (b[i] == kInf ? 1u : 0u) << i;
+      m &= s_mask[j];
+      if (m) {
+#pragma unroll
+        for (int i = 0; i < TP; ++i)
+          if ((m >> i) & 1u) r.H[(int64_t)nb * TP + i] = (uint8_t)(level + 1);
+        r.F[nb] = 1;
+      }
+      ++pass;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < cnt; j += kBlock)
+      if (s_ret[j]) r.F[s_node[j]] = 1;
+    __syncthreads();
+  }
+  pass = wave_sum(pass);
+  if (lane_id() == 0 && pass) atomicAdd((unsigned long long*)&st->gate_pass, (unsigned long long)pass);
+}
+
+template <int TP>
+__global__ __launch_bounds__(kBlock) void k_count_writes(const uint8_t* H, int32_t n, RunStatus* st) {
+  uint64_t c = 0;
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
+    uint8_t b[TP];
+    load_row<TP>(H, v, b);
+#pragma unroll
+    for (int i = 0; i < TP; ++i) c += (b[i] != 0 && b[i] != kInf) ? 1 : 0;
+  }
+  c = wave_sum(c);
+  if (lane_id() == 0 && c) atomicAdd((unsigned long long*)&st->h_writes, (unsigned long long)c);
+}
+
+// -------------------------------------------------------------- top-w ---
+// Top-w central graphs by (S^c, sum of central levels, node id).  All CGs of
+// earlier levels are kept (they are fewer than w); the remaining slots go to
+// the last level's CGs with the smallest sums, ties to smaller node ids (the
+// candidate list of a level is in node order).
+__global__ __launch_bounds__(kCtl) void k_select(SelectView v) {
+  __shared__ uint64_t s_sel[kMaxW];
+  __shared__ uint32_t s_hist[4096];
+  __shared__ uint32_t s_scan[kCtl / kWave + 1];
+  __shared__ uint32_t s_cnt, s_thr, s_take, s_nsel;
+  const RunStatus* st = v.st;
+  const uint32_t total = st->ncand_total, last = st->ncand_level;
+  const uint32_t prev = total - last;
+  const uint32_t w = (uint32_t)v.w;
+  if (total <= w) {
+    for (uint32_t i = threadIdx.x; i < total; i += kCtl) s_sel[i] = v.cand[i];
+    if (threadIdx.x == 0) s_nsel = total;
+  } else {
+    const uint32_t need = w - prev;
+    for (uint32_t i = threadIdx.x; i < prev; i += kCtl) s_sel[i] = v.cand[i];
+    for (int i = threadIdx.x; i < 4096; i += kCtl) s_hist[i] = 0;
+    __syncthreads();
+    for (uint32_t i = prev + threadIdx.x; i < total; i += kCtl)
+      atomicAdd(&s_hist[(v.cand[i] >> 32) & 0xFFF], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t cum = 0, thr = 0;
+      for (uint32_t s = 0; s < 4096; ++s) {
+        if (cum + s_hist[s] >= need) { thr = s; break; }
+        cum += s_hist[s];
+      }
+      s_thr = thr;
+      s_take = need - cum;
+      s_cnt = prev;
+      s_nsel = w;
+    }
+    __syncthreads();
+    const uint32_t thr = s_thr, take = s_take;
+    uint32_t taken = 0;
+    for (uint32_t b = prev; b < total; b += kCtl) {
+      const uint32_t i = b + threadIdx.x;
+      const uint64_t key = i < total ? v.cand[i] : 0;
+      const uint32_t s = (uint32_t)(key >> 32) & 0xFFFF;
+      const bool lt = i < total && s < thr;
+      const uint32_t eq = (i < total && s == thr) ? 1u : 0u;
+      if (lt) s_sel[atomicAdd(&s_cnt, 1u)] = key;
+      uint32_t tot;
+      const uint32_t ex = block_exclusive_scan<uint32_t, kCtl>(eq, s_scan, &tot);
+      if (eq && taken + ex < take) s_sel[atomicAdd(&s_cnt, 1u)] = key;
+      taken += tot;
+    }
+  }
+  __syncthreads();
+  const uint32_t nsel = s_nsel;
+  for (uint32_t i = threadIdx.x; i < nsel; i += kCtl) {
+    const uint64_t key = s_sel[i];
+    uint32_t rank = 0;
+    for (uint32_t j = 0; j < nsel; ++j) rank += s_sel[j] < key;
+    v.sel_node[rank] = (int32_t)(key & 0xFFFFFFFFu);
+    v.sel_sc[rank] = (int32_t)(key >> 48);
+    v.sel_sumh[rank] = (int32_t)((key >> 32) & 0xFFFF);
+  }
+  if (threadIdx.x == 0) v.gst->nsel = (int32_t)nsel;
+}
+
+// Ranking of the results: RPGs by (key, S^c, CG rank); without marginal
+// keywords every selected CG is a result with S^m = 0.
+__global__ __launch_bounds__(kBlock) void k_rank(RankView v) {
+  __shared__ int32_t s_has[kMaxW];
+  __shared__ int64_t s_key[kMaxW];
+  __shared__ int32_t s_cnt;
+  const int nsel = v.nsel;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  for (int r = threadIdx.x; r < nsel; r += kBlock) {
+    if (v.M == 0) {
+      v.has_rpg[r] = 1;
+      v.sm[r] = 0;
+      v.key[r] = (int64_t)v.gamma_num * v.sel_sc[r];
+    }
+    s_has[r] = v.has_rpg[r];
+    s_key[r] = v.key[r];
+    if (s_has[r]) atomicAdd(&s_cnt, 1);
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < nsel; r += kBlock) {
+    if (!s_has[r]) continue;
+    int rank = 0;
+    for (int o = 0; o < nsel; ++o) {
+      if (!s_has[o]) continue;
+      rank += s_key[o] < s_key[r] ||
+              (s_key[o] == s_key[r] && (v.sel_sc[o] < v.sel_sc[r] ||
+                                        (v.sel_sc[o] == v.sel_sc[r] && o < r)));
+    }
+    if (rank < v.k) v.ranked[rank] = r;
+  }
+  if (threadIdx.x == 0) v.gst->nres = min(s_cnt, v.k);
+}
+
+__global__ void k_clear_rpg(int32_t* has, int32_t* sm, int64_t* key, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) { has[i] = 0; sm[i] = 0; key[i] = 0; }
+}
+
+// ------------------------------------------------------------ launchers ---
+
+#define RAKS_TP_DISPATCH(TP, ...)                         \
+  switch (TP) {                                           \
+    case 4: { constexpr int kTP = 4; __VA_ARGS__; } break;  \
+    case 8: { constexpr int kTP = 8; __VA_ARGS__; } break;  \
+    default: { constexpr int kTP = 16; __VA_ARGS__; } break; \
+  }
+
+void launch_run_init(const RunView& r, int TP, int32_t n, const int32_t* kw_nodes,
+                     const SeedList& seeds, hipStream_t s) {
+  int empty = 0;
+  for (int i = 0; i < seeds.T; ++i) empty |= seeds.count[i] == 0;
+  k_run_reset<<<1, 1, 0, s>>>(r.st, empty);
+  const unsigned g = (unsigned)std::min<int64_t>(8192, (r.n_pad + kBlock - 1) / kBlock);
+  RAKS_TP_DISPATCH(TP, k_init_rows<kTP><<<g, kBlock, 0, s>>>(r.H, r.F, n, r.n_pad, r.T));
+  const uint32_t total = seeds.prefix[seeds.T];
+  if (total > 0) {
+    const unsigned gs = (unsigned)std::min<uint32_t>(4096, (total + kBlock - 1) / kBlock);
+    RAKS_TP_DISPATCH(TP, k_seed<kTP><<<gs, kBlock, 0, s>>>(r.H, r.F, kw_nodes, seeds));
+  }
+  if (r.kind == RUN_MARGINAL && r.nsel > 0)
+    k_clear_rpg<<<1, kBlock, 0, s>>>(r.has_rpg, r.sm, r.key, r.nsel);
+}
+
+void launch_front_count(const RunView& r, int TP, const DevGraphView& g, int level, hipStream_t s) {
+  RAKS_TP_DISPATCH(TP, k_front_count<kTP><<<r.nblocks, kBlock, 0, s>>>(r, g.row_ptr, level));
+}
+
+void launch_front_control(const RunView& r, int TP, int level, hipStream_t s) {
+  RAKS_TP_DISPATCH(TP, k_front_control<kTP><<<1, kCtl, 0, s>>>(r, level));
+}
+
+void launch_front_write(const RunView& r, int TP, const DevGraphView& g, int level, hipStream_t s) {
+  RAKS_TP_DISPATCH(TP, k_front_write<kTP><<<r.nblocks, kBlock, 0, s>>>(r, g.row_ptr, level));
+}
+
+void launch_expand(const RunView& r, int TP, const DevGraphView& g, int level, int grid,
+                   hipStream_t s) {
+  RAKS_TP_DISPATCH(TP, k_expand<kTP><<<grid, kBlock, 0, s>>>(r, g, level));
+}
+
+void launch_count_writes(const RunView& r, int TP, int32_t n, hipStream_t s) {
+  const unsigned g = (unsigned)std::min<int64_t>(4096, (n + kBlock - 1) / kBlock);
+  RAKS_TP_DISPATCH(TP, k_count_writes<kTP><<<g, kBlock, 0, s>>>(r.H, n, r.st));
+}
+
+void launch_select(const SelectView& v, hipStream_t s) { k_select<<<1, kCtl, 0, s>>>(v); }
+
+void launch_rank(const RankView& v, hipStream_t s) { k_rank<<<1, kBlock, 0, s>>>(v); }
+
+}  // namespace raks

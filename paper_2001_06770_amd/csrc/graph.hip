@@ -1,0 +1,165 @@
+// graph.hip -- graph upload checks and activation levels (Section 3.1).
+//
+// EDGE mode: for arc e = (i -> j, l) the fine weight is the log of
+//   c_e = |arcs of i with label l| + |arcs into j with label l|
+// (on the bi-directed graph the arcs into j with label l are the reverses of
+// j's arcs with label l), min-max rescaled to x in [0,1], then coarsened by the
+// reward/penalty rule (Eqs. 1-3) around a_bar and rounded half up.
+// NODE mode: the node weights are min-max rescaled and coarsened the same way;
+// an arc u -> v gets the level of v.
+// Rows are sorted by (label, destination), so a label's arcs in a row are one
+// run found by binary search.  Built with -ffp-contract=off: the fp64
+// expressions are evaluated exactly as written.
+#include "common.h"
+#include "kernels.h"
+
+namespace raks {
+
+// number of arcs in row x with label lab
+__device__ inline uint32_t label_run(const uint32_t* row_ptr, const uint16_t* label, uint32_t x,
+                                     uint16_t lab) {
+  uint32_t lo = row_ptr[x], hi = row_ptr[x + 1];
+  uint32_t a = lo, b = hi;
+  while (a < b) { uint32_t m = (a + b) >> 1; if (label[m] < lab) a = m + 1; else b = m; }
+  const uint32_t first = a;
+  b = hi;
+  while (a < b) { uint32_t m = (a + b) >> 1; if (label[m] <= lab) a = m + 1; else b = m; }
+  return a - first;
+}
+
+// Checks every arc against the input contract and computes its label count c.
+__global__ __launch_bounds__(kBlock) void k_check_and_count(const uint32_t* row_ptr,
+                                                            const int32_t* col,
+                                                            const uint16_t* label, int32_t n,
+                                                            uint32_t A, uint32_t* c_out,
+                                                            Status* st) {
+  uint32_t err = 0;
+  uint64_t cmin = ~0ull, cmax = 0;
+  for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < A; e += gridDim.x * kBlock) {
+    const uint32_t i = row_of(row_ptr, n, e);
+    const int32_t j = col[e];
+    const uint16_t lab = label[e];
+    if (j < 0 || j >= n) { err |= 1; c_out[e] = 0; continue; }
+    if ((uint32_t)j == i) err |= 2;
+    if (e > row_ptr[i]) {
+      const uint16_t pl = label[e - 1];
+      const int32_t pc = col[e - 1];
+      if (pl > lab || (pl == lab && pc >= j)) err |= 4;
+    }
+    if (find_arc_dev(row_ptr, col, label, j, lab, (int32_t)i) == kEmpty) err |= 8;
+    const uint64_t c = (uint64_t)label_run(row_ptr, label, i, lab) + label_run(row_ptr, label, j, lab);
+    c_out[e] = (uint32_t)c;
+    cmin = c < cmin ? c : cmin;
+    cmax = c > cmax ? c : cmax;
+  }
+  // wave reductions, then one atomic per wave
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    uint64_t a = __shfl_xor(cmin, d, kWave), b = __shfl_xor(cmax, d, kWave);
+    cmin = a < cmin ? a : cmin;
+    cmax = b > cmax ? b : cmax;
+    err |= __shfl_xor(err, d, kWave);
+  }
+  if (lane_id() == 0) {
+    if (err) atomicOr(&st->err, (int32_t)err);
+    atomicMin((unsigned long long*)&st->cmin, (unsigned long long)cmin);
+    atomicMax((unsigned long long*)&st->cmax, (unsigned long long)cmax);
+  }
+}
+
+// Eqs. 1-3: reward below alpha, penalty above, round half up.
+__device__ inline uint8_t coarsen(double x, double abar, double alpha) {
+  double v;
+  if (x <= alpha) {
+    const double reward = abar * (alpha - x) / alpha;
+    v = abar - reward;
+  } else {
+    const double penalty = abar * (x - alpha) / (1.0 - alpha);
+    v = abar + penalty;
+  }
+  double r = floor(v + 0.5);
+  r = r < 0.0 ? 0.0 : (r > 254.0 ? 254.0 : r);
+  return (uint8_t)r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_act_edge(const uint32_t* c, uint32_t A,
+                                                     const Status* st, double abar,
+                                                     double alpha, uint8_t* act) {
+  const uint64_t cmin = st->cmin, cmax = st->cmax;
+  const double lmin = log((double)cmin), lmax = log((double)cmax);
+  for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < A; e += gridDim.x * kBlock) {
+    const double lc = log((double)c[e]);
+    const double x = (cmax == cmin) ? 0.0 : (lc - lmin) / (lmax - lmin);
+    act[e] = coarsen(x, abar, alpha);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_node_weight_range(const uint8_t* nw, int32_t n,
+                                                              Status* st) {
+  uint32_t mn = 255, mx = 0;
+  for (int32_t v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
+    mn = min(mn, (uint32_t)nw[v]);
+    mx = max(mx, (uint32_t)nw[v]);
+  }
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    mn = min(mn, (uint32_t)__shfl_xor(mn, d, kWave));
+    mx = max(mx, (uint32_t)__shfl_xor(mx, d, kWave));
+  }
+  if (lane_id() == 0) {
+    atomicMin((unsigned long long*)&st->cmin, (unsigned long long)mn);
+    atomicMax((unsigned long long*)&st->cmax, (unsigned long long)mx);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_act_node(const uint8_t* nw, int32_t n,
+                                                     const Status* st, double abar,
+                                                     double alpha, uint8_t* act_node) {
+  const double mn = (double)st->cmin, mx = (double)st->cmax;
+  for (int32_t v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
+    const double x = (st->cmax == st->cmin) ? 0.0 : ((double)nw[v] - mn) / (mx - mn);
+    act_node[v] = coarsen(x, abar, alpha);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_act_gather(const uint8_t* act_node,
+                                                       const int32_t* col, uint32_t A,
+                                                       uint8_t* act) {
+  for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < A; e += gridDim.x * kBlock)
+    act[e] = act_node[col[e]];
+}
+
+__global__ void k_status_reset_minmax(Status* st) {
+  st->cmin = ~0ull;
+  st->cmax = 0;
+  st->err = 0;
+}
+
+// ------------------------------------------------------------ launchers ---
+
+static unsigned grid_for(uint64_t items, unsigned cap = 8192) {
+  uint64_t g = (items + kBlock - 1) / kBlock;
+  if (g < 1) g = 1;
+  return (unsigned)(g > cap ? cap : g);
+}
+
+void launch_check_and_count(const DevGraphView& g, uint32_t* c_tmp, Status* st, hipStream_t s) {
+  k_status_reset_minmax<<<1, 1, 0, s>>>(st);
+  if (g.A > 0)
+    k_check_and_count<<<grid_for(g.A), kBlock, 0, s>>>(g.row_ptr, g.col, g.label, g.n, g.A, c_tmp, st);
+}
+
+void launch_act_edge(const DevGraphView& g, const uint32_t* c_tmp, const Status* st, double abar,
+                     double alpha, uint8_t* act, hipStream_t s) {
+  if (g.A > 0) k_act_edge<<<grid_for(g.A), kBlock, 0, s>>>(c_tmp, g.A, st, abar, alpha, act);
+}
+
+void launch_act_node(const DevGraphView& g, const uint8_t* nw, Status* st, double abar,
+                     double alpha, uint8_t* act_node, uint8_t* act, hipStream_t s) {
+  k_status_reset_minmax<<<1, 1, 0, s>>>(st);
+  k_node_weight_range<<<grid_for(g.n), kBlock, 0, s>>>(nw, g.n, st);
+  k_act_node<<<grid_for(g.n), kBlock, 0, s>>>(nw, g.n, st, abar, alpha, act_node);
+  if (g.A > 0) k_act_gather<<<grid_for(g.A), kBlock, 0, s>>>(act_node, g.col, g.A, act);
+}
+
+}  // namespace raks
