@@ -65,6 +65,9 @@ def main():
     ap.add_argument("--mode", default="edge", choices=["edge", "node"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (calibrates the "
+                         "profiler's FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -72,6 +75,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 4, "copies": 5}))
+        return
     import synth
     import paper_2001_06770_amd as raks
 
@@ -88,18 +100,19 @@ def main():
 
     for _ in range(args.warmup):
         for q in qs:
-            ctx.query(q)
+            ctx.query(q, lean=True)
     torch.cuda.synchronize()
 
     ctx.set_timing(True)
-    lat, arcs, nq = [], 0, 0
+    lat, dev_ms, arcs, nq = [], [], 0, 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
         for q in qs:
             a = time.perf_counter()
-            r = ctx.query(q)
+            r = ctx.query(q, lean=True)
             lat.append((time.perf_counter() - a) * 1e3)
+            dev_ms.append(r["device_ms"])
             arcs += r["stats"][0]["e_arc"] + r["stats"][1]["e_arc"]
             nq += 1
         print(f"# step {s + 1}/{args.steps} done", file=sys.stderr, flush=True)
@@ -129,6 +142,7 @@ def main():
         "qps": nq / dt,
         "p50_ms": percentile(lat, 50),
         "p99_ms": percentile(lat, 99),
+        "device_p50_ms": percentile(dev_ms, 50),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None,
                      "kernel": "k_expand", "launches": texp["launches"],

@@ -118,7 +118,9 @@ def _check(rc):
         raise RaksError(rc, lib().raks_last_error().decode())
 
 
-def _results_to_dict(res: Results) -> dict:
+def _results_to_dict(res: Results, lean: bool = False) -> dict:
+    """Results as a dict; nodes and arcs as tuples, or as numpy arrays when
+    ``lean`` (no per-element Python objects)."""
     st = res.stats
     stats = []
     for k in range(2):
@@ -132,14 +134,17 @@ def _results_to_dict(res: Results) -> dict:
            "device_ms": float(st.device_ms)}
     for i in range(res.n):
         r = res.r[i]
-        nodes = np.ctypeslib.as_array(r.nodes, shape=(r.n_nodes,)) if r.n_nodes else np.empty(0, np.int32)
+        nodes = (np.ctypeslib.as_array(r.nodes, shape=(r.n_nodes,)).copy() if r.n_nodes
+                 else np.empty(0, np.int32))
         arcs = (np.ctypeslib.as_array(ctypes.cast(r.arcs, ctypes.POINTER(ctypes.c_int32)),
-                                      shape=(r.n_arcs * 3,)).reshape(-1, 3)
+                                      shape=(r.n_arcs * 3,)).reshape(-1, 3).copy()
                 if r.n_arcs else np.empty((0, 3), np.int32))
+        if not lean:
+            nodes = tuple(nodes.tolist())
+            arcs = tuple(map(tuple, arcs.tolist()))
         out["results"].append({"central": int(r.central_node), "score_c": int(r.score_c),
                                "score_m": int(r.score_m), "key": int(r.key),
-                               "nodes": tuple(int(x) for x in nodes),
-                               "arcs": tuple((int(a), int(b), int(c)) for a, b, c in arcs)})
+                               "nodes": nodes, "arcs": arcs})
     return out
 
 
@@ -221,13 +226,13 @@ class Context:
                          getattr(q, "gamma_num", 1), getattr(q, "gamma_den", 2),
                          getattr(q, "max_level", 20))
 
-    def query(self, q) -> dict:
+    def query(self, q, lean: bool = False) -> dict:
         keep = []
         d = self._desc(q, keep)
         out = ctypes.POINTER(Results)()
         _check(lib().raks_query(self._h, ctypes.byref(d), ctypes.byref(out)))
         try:
-            return _results_to_dict(out.contents)
+            return _results_to_dict(out.contents, lean)
         finally:
             lib().raks_results_free(out)
 

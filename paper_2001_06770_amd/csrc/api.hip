@@ -57,6 +57,8 @@ struct DevBuf {
 };
 
 constexpr int kTimers = 5;
+constexpr size_t kSpecNodes = 1 << 16;   // output read back with the headers
+constexpr size_t kSpecArcs = 1 << 16;
 
 }  // namespace
 
@@ -78,26 +80,33 @@ struct raks_ctx {
   int32_t vocab = 0;
   int32_t mode = 0;
   double abar = 0, alpha = 0;
-  DevBuf row_ptr, col, label, act, act_node, nw, kw_nodes;
+  DevBuf row_ptr, col, label, act, act_node, nw, kw_nodes, col_s, act_s, eid_s, row_amax, bnd, arc_src;
+  int32_t nbnd = 1;
   std::vector<int64_t> kw_ptr;
 
   // workspace
   int32_t n_pad = 0, nblocks = 0;
-  DevBuf Hc, Hm, F, tot, off, q_node, q_off, q_rs, q_mask, cand;
+  DevBuf Hc, Hm, F, tot, off, q_off, q_rs, q_lo, q_mask, cand;
   DevBuf sel_node, sel_sc, sel_sumh, has_rpg, sm, key, dmin, ranked;
   DevBuf vc_cnt, vc_tmp, vc_off, vc_nodes;
-  DevBuf ht, nl, al, icnt, cg_nodes, cg_arcs, cg_cnt, sort_a, sort_b;
+  DevBuf ht, nl, al, icnt, cg_nodes, cg_arcs, cg_cnt, sort_a, sort_b, items, lcnt;
   DevBuf hdr, out_nodes, out_arcs;
   DevBuf status;
   Status* h_status = nullptr;   // pinned
+  RunStatus* h_run = nullptr;   // pinned [2]: per-level status, double-buffered
+  ResultHdr* h_hdr = nullptr;   // pinned [kMaxW]
+  int32_t* h_nodes = nullptr;   // pinned [kSpecNodes]
+  int32_t* h_arcs = nullptr;    // pinned [3 * kSpecArcs]
+  hipEvent_t lvl_ev[2] = {nullptr, nullptr};
   uint32_t nc = 4096, ac = 16384;  // recovery capacities per instance
+  uint32_t lcap = 1u << 16;        // recovery work chunks per layer
 
   // timing
   bool timing = false;
   raks_kernel_timing acc[kTimers] = {};
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
-  struct Pending { hipEvent_t a, b; int kind; double bytes; };
+  struct Pending { hipEvent_t a, b; int kind; double bytes; int level, run; };
   std::vector<Pending> pending;
   hipEvent_t q_start = nullptr, q_end = nullptr;
 };
@@ -154,6 +163,13 @@ DevGraphView graph_view(raks_ctx* c) {
   g.act = P<uint8_t>(c->act);
   g.act_node = c->mode ? P<uint8_t>(c->act_node) : nullptr;
   g.mode = c->mode;
+  g.col_s = P<int32_t>(c->col_s);
+  g.act_s = P<uint8_t>(c->act_s);
+  g.row_amax = P<uint8_t>(c->row_amax);
+  g.eid_s = P<uint32_t>(c->eid_s);
+  g.arc_src = P<int32_t>(c->arc_src);
+  g.bnd = P<uint32_t>(c->bnd);
+  g.nbnd = c->nbnd;
   return g;
 }
 
@@ -171,8 +187,10 @@ struct Timed {
   raks_ctx* c;
   int kind;
   double bytes;
+  int level, run;
   hipEvent_t a = nullptr;
-  Timed(raks_ctx* c_, int kind_, double bytes_ = 0) : c(c_), kind(kind_), bytes(bytes_) {
+  Timed(raks_ctx* c_, int kind_, double bytes_ = 0, int level_ = -1, int run_ = -1)
+      : c(c_), kind(kind_), bytes(bytes_), level(level_), run(run_) {
     if (c->timing) {
       a = next_event(c);
       if (a) (void)hipEventRecord(a, c->stream);
@@ -183,7 +201,7 @@ struct Timed {
       hipEvent_t b = next_event(c);
       if (b) {
         (void)hipEventRecord(b, c->stream);
-        c->pending.push_back({a, b, kind, bytes});
+        c->pending.push_back({a, b, kind, bytes, level, run});
       }
     }
   }
@@ -192,6 +210,7 @@ struct Timed {
 void harvest_timing(raks_ctx* c) {
   for (auto& p : c->pending) {
     float ms = 0;
+    if (p.kind < 0) continue;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       c->acc[p.kind].launches += 1;
       c->acc[p.kind].ms += ms;
@@ -207,10 +226,11 @@ void harvest_timing(raks_ctx* c) {
 int compute_activation(raks_ctx* c) {
   DevGraphView g = graph_view(c);
   Status* st = P<Status>(c->status);
+  RAKS_TRY(dev_alloc(c, c->arc_src, (size_t)std::max<uint32_t>(c->A, 1) * 4));
   if (c->mode == RAKS_ACT_EDGE) {
     DevBuf ctmp;
     RAKS_TRY(dev_alloc(c, ctmp, (size_t)std::max<uint32_t>(c->A, 1) * 4));
-    launch_check_and_count(g, P<uint32_t>(ctmp), st, c->stream);
+    launch_check_and_count(g, P<uint32_t>(ctmp), P<int32_t>(c->arc_src), st, c->stream);
     HIP_OK(hipMemcpyAsync(c->h_status, st, sizeof(Status), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
     if (c->h_status->err) {
@@ -227,7 +247,7 @@ int compute_activation(raks_ctx* c) {
   } else {
     DevBuf ctmp;
     RAKS_TRY(dev_alloc(c, ctmp, (size_t)std::max<uint32_t>(c->A, 1) * 4));
-    launch_check_and_count(g, P<uint32_t>(ctmp), st, c->stream);
+    launch_check_and_count(g, P<uint32_t>(ctmp), P<int32_t>(c->arc_src), st, c->stream);
     HIP_OK(hipMemcpyAsync(c->h_status, st, sizeof(Status), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
     dev_free(c, ctmp);
@@ -237,6 +257,19 @@ int compute_activation(raks_ctx* c) {
                     P<uint8_t>(c->act), c->stream);
     HIP_OK(hipStreamSynchronize(c->stream));
   }
+  // traversal copy sorted by activation level within each row
+  RAKS_TRY(dev_alloc(c, c->col_s, (size_t)std::max<uint32_t>(c->A, 1) * 4));
+  RAKS_TRY(dev_alloc(c, c->act_s, (size_t)std::max<uint32_t>(c->A, 1)));
+  RAKS_TRY(dev_alloc(c, c->eid_s, (size_t)std::max<uint32_t>(c->A, 1) * 4));
+  RAKS_TRY(dev_alloc(c, c->row_amax, (size_t)c->n));
+  // levels never exceed Round(2 * a_bar) (x <= 1 in Eqs. 1-3)
+  c->nbnd = (int32_t)std::min(16.0, std::floor(2.0 * c->abar + 0.5) + 1.0);
+  RAKS_TRY(dev_alloc(c, c->bnd, (size_t)c->n * c->nbnd * 4));
+  g = graph_view(c);
+  launch_sort_rows(g, P<int32_t>(c->col_s), P<uint8_t>(c->act_s), P<uint32_t>(c->eid_s),
+                   P<uint8_t>(c->row_amax), P<uint32_t>(c->bnd), c->nbnd, c->stream);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamSynchronize(c->stream));
   return RAKS_OK;
 }
 
@@ -286,9 +319,9 @@ int ensure_node_buffers(raks_ctx* c) {
   RAKS_TRY(dev_alloc(c, c->F, np));
   RAKS_TRY(dev_alloc(c, c->tot, (size_t)c->nblocks * sizeof(ScanTot)));
   RAKS_TRY(dev_alloc(c, c->off, (size_t)c->nblocks * sizeof(ScanOff)));
-  RAKS_TRY(dev_alloc(c, c->q_node, np * 4));
   RAKS_TRY(dev_alloc(c, c->q_off, (np + 1) * 4));
   RAKS_TRY(dev_alloc(c, c->q_rs, np * 4));
+  RAKS_TRY(dev_alloc(c, c->q_lo, np * 4));
   RAKS_TRY(dev_alloc(c, c->q_mask, np * 4));
   RAKS_TRY(dev_alloc(c, c->cand, np * 8));
   RAKS_TRY(dev_alloc(c, c->sel_node, kMaxW * 4));
@@ -318,7 +351,7 @@ SeedList seeds_for(raks_ctx* c, const std::vector<int32_t>& kws) {
   return s;
 }
 
-RunView run_view(raks_ctx* c, int kind, int T, DevBuf& H, const QueryPlan& p, int nsel) {
+RunView run_view(raks_ctx* c, int kind, int T, DevBuf& H, const QueryPlan& p) {
   RunView r = {};
   r.kind = kind;
   r.T = T;
@@ -331,7 +364,7 @@ RunView run_view(raks_ctx* c, int kind, int T, DevBuf& H, const QueryPlan& p, in
   r.tot = P<ScanTot>(c->tot);
   r.off = P<ScanOff>(c->off);
   r.nblocks = c->nblocks;
-  r.q_node = P<int32_t>(c->q_node);
+  r.q_lo = P<uint32_t>(c->q_lo);
   r.q_off = P<uint32_t>(c->q_off);
   r.q_rs = P<uint32_t>(c->q_rs);
   r.q_mask = P<uint32_t>(c->q_mask);
@@ -341,7 +374,7 @@ RunView run_view(raks_ctx* c, int kind, int T, DevBuf& H, const QueryPlan& p, in
   r.k = p.k;
   r.gamma_num = p.gn;
   r.gamma_den = p.gd;
-  r.nsel = nsel;
+  r.nsel = &P<Status>(c->status)->nsel;
   r.sel_sc = P<int32_t>(c->sel_sc);
   r.vc_off = P<uint32_t>(c->vc_off);
   r.vc_nodes = P<int32_t>(c->vc_nodes);
@@ -360,14 +393,12 @@ __global__ void k_query_reset(Status* st) {
   st->out_arcs = 0;
 }
 
-int read_status(raks_ctx* c) {
-  HIP_OK(hipMemcpyAsync(c->h_status, c->status.p, sizeof(Status), hipMemcpyDeviceToHost, c->stream));
-  HIP_OK(hipStreamSynchronize(c->stream));
-  return RAKS_OK;
-}
-
-// One exploration run: the level loop of Figure 3.
-int run_levels(raks_ctx* c, RunView& r, int TP, const std::vector<int32_t>& kws, int T) {
+// One exploration run: the level loop of Figure 3.  The host enqueues level
+// l+1 before it waits for the status of level l, so the GPU never idles on
+// the host's decision; the kernels of a level after the run's end return at
+// once.  Returns the run's final status in *last.
+int run_levels(raks_ctx* c, RunView& r, int TP, const std::vector<int32_t>& kws, int T,
+               RunStatus* last) {
   DevGraphView g = graph_view(c);
   const SeedList seeds = seeds_for(c, kws);
   {
@@ -375,55 +406,62 @@ int run_levels(raks_ctx* c, RunView& r, int TP, const std::vector<int32_t>& kws,
     launch_run_init(r, TP, c->n, P<int32_t>(c->kw_nodes), seeds, c->stream);
   }
   const int grid = c->num_cu * 8;
-  uint64_t pass_prev = 0;
-  for (int level = 0; level <= r.max_level; ++level) {
+  auto enqueue = [&](int level, int slot) -> int {
     {
-      Timed t(c, 1);
+      Timed t(c, 1, 0, level, r.kind);
       launch_front_count(r, TP, g, level, c->stream);
     }
     {
-      Timed t(c, 2);
+      Timed t(c, 2, 0, level, r.kind);
       launch_front_control(r, TP, level, c->stream);
     }
     {
-      Timed t(c, 1);
+      Timed t(c, 1, 0, level, r.kind);
       launch_front_write(r, TP, g, level, c->stream);
     }
     {
-      Timed t(c, 0);
+      Timed t(c, 0, 0, level, r.kind);
       launch_expand(r, TP, g, level, grid, c->stream);
     }
     HIP_OK(hipGetLastError());
-    RAKS_TRY(read_status(c));
-    const RunStatus& s = c->h_status->run[r.kind];
-    if (c->timing && !c->pending.empty() && c->pending.back().kind == 0) {
-      if (s.end_level == INT32_MAX) {
-        // algorithmic bytes of this expansion: 5 per scanned arc (col + level),
-        // T per gated-through arc (the neighbour's hitting levels), 16 per
-        // queue entry (node, row start, mask, offset)
-        const double passed = (double)(s.gate_pass - pass_prev);
-        c->pending.back().bytes = 5.0 * s.W + (double)T * passed + 16.0 * s.nactive;
-      } else {
-        c->pending.pop_back();   // the level ended before expanding: no work launched
+    HIP_OK(hipMemcpyAsync(&c->h_run[slot], r.st, sizeof(RunStatus), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipEventRecord(c->lvl_ev[slot], c->stream));
+    return RAKS_OK;
+  };
+  RAKS_TRY(enqueue(0, 0));
+  for (int level = 0;; ++level) {
+    const int slot = level & 1;
+    if (level + 1 <= r.max_level) RAKS_TRY(enqueue(level + 1, slot ^ 1));
+    HIP_OK(hipEventSynchronize(c->lvl_ev[slot]));
+    const RunStatus s = c->h_run[slot];
+    if (c->timing) {
+      for (auto& pe : c->pending) {
+        if (pe.kind != 0 || pe.level != level || pe.run != r.kind) continue;
+        if (s.end_level == INT32_MAX) {
+          // algorithmic bytes of this expansion: per examined arc the neighbour
+          // id (4) and its T hitting levels; per queue entry 16
+          pe.bytes = (4.0 + T) * s.W + 16.0 * s.nactive;
+        } else {
+          pe.kind = -1;   // the level ended before expanding: no work launched
+        }
       }
     }
-    pass_prev = s.gate_pass;
-    if (s.end_level != INT32_MAX) break;
+    if (s.end_level != INT32_MAX || level >= r.max_level) {
+      *last = s;
+      break;
+    }
   }
-  {
-    Timed t(c, 4);
-    launch_count_writes(r, TP, c->n, c->stream);
-  }
-  HIP_OK(hipGetLastError());
   return RAKS_OK;
 }
 
-int ensure_recovery(raks_ctx* c, int n_inst, int n_cg, int C, int M, int n_res) {
+int ensure_recovery(raks_ctx* c, int n_inst, int n_cg, int C, int M, int n_res, int max_level) {
   const uint32_t hc = [&] { uint32_t h = 1; while (h < 2 * c->nc) h <<= 1; return h; }();
   RAKS_TRY(dev_alloc(c, c->ht, (size_t)std::max(n_inst, 1) * hc * 4));
   RAKS_TRY(dev_alloc(c, c->nl, (size_t)std::max(n_inst, 1) * c->nc * 4));
   RAKS_TRY(dev_alloc(c, c->al, (size_t)std::max(n_inst, 1) * c->ac * 4));
   RAKS_TRY(dev_alloc(c, c->icnt, (size_t)std::max(n_inst, 1) * 8));
+  RAKS_TRY(dev_alloc(c, c->items, (size_t)(max_level + 1) * c->lcap * sizeof(RecItem)));
+  RAKS_TRY(dev_alloc(c, c->lcnt, (size_t)(max_level + 1) * 4));
   const size_t cg_ncap = (size_t)C * c->nc, cg_acap = (size_t)C * c->ac;
   RAKS_TRY(dev_alloc(c, c->cg_nodes, (size_t)std::max(n_cg, 1) * cg_ncap * 4));
   RAKS_TRY(dev_alloc(c, c->cg_arcs, (size_t)std::max(n_cg, 1) * cg_acap * 4));
@@ -434,17 +472,28 @@ int ensure_recovery(raks_ctx* c, int n_inst, int n_cg, int C, int M, int n_res) 
   const int nw = std::max(n_cg, n_res);
   RAKS_TRY(dev_alloc(c, c->sort_a, (size_t)std::max(nw, 1) * scap * 4));
   RAKS_TRY(dev_alloc(c, c->sort_b, (size_t)std::max(nw, 1) * scap * 4));
+  const size_t ncap = (size_t)n_res * ((size_t)C * c->nc + (size_t)M * c->nc);
+  const size_t acap = (size_t)n_res * ((size_t)C * c->ac + (size_t)M * c->ac);
+  RAKS_TRY(dev_alloc(c, c->hdr, (size_t)std::max(n_res, 1) * sizeof(ResultHdr)));
+  RAKS_TRY(dev_alloc(c, c->out_nodes, std::max<size_t>(ncap, 1) * 4));
+  RAKS_TRY(dev_alloc(c, c->out_arcs, std::max<size_t>(acap, 1) * 12));
   return RAKS_OK;
 }
 
-RecoverView recover_view(raks_ctx* c, int marginal, DevBuf& H, int TP, int T, int n_inst) {
+RecoverView recover_view(raks_ctx* c, int marginal, DevBuf& H, int TP, int T, int n_inst,
+                         const int32_t* n_valid, int max_layer) {
   RecoverView v = {};
+  v.items = P<RecItem>(c->items);
+  v.lcnt = P<uint32_t>(c->lcnt);
+  v.lcap = c->lcap;
+  v.max_layer = max_layer;
   v.g = graph_view(c);
   v.H = P<uint8_t>(H);
   v.TP = TP;
   v.T = T;
   v.marginal = marginal;
   v.n_inst = n_inst;
+  v.n_valid = n_valid;
   v.sel_node = P<int32_t>(c->sel_node);
   v.ranked = P<int32_t>(c->ranked);
   v.vc_off = P<uint32_t>(c->vc_off);
@@ -463,12 +512,14 @@ RecoverView recover_view(raks_ctx* c, int marginal, DevBuf& H, int TP, int T, in
   return v;
 }
 
-FinalizeView finalize_view(raks_ctx* c, int marginal, int T, int n_res, int C, int TPc, int M) {
+FinalizeView finalize_view(raks_ctx* c, int marginal, int T, int n_res, const int32_t* n_valid,
+                           int C, int TPc, int M) {
   FinalizeView v = {};
   v.g = graph_view(c);
   v.T = T;
   v.marginal = marginal;
   v.n_res = n_res;
+  v.n_valid = n_valid;
   v.sel_node = P<int32_t>(c->sel_node);
   v.ranked = P<int32_t>(c->ranked);
   v.nl = P<int32_t>(c->nl);
@@ -501,29 +552,18 @@ FinalizeView finalize_view(raks_ctx* c, int marginal, int T, int n_res, int C, i
   return v;
 }
 
-__global__ void k_clear_overflow(Status* st) {
-  st->overflow = 0;
-  st->out_nodes = 0;
-  st->out_arcs = 0;
-}
-
-int query_one(raks_ctx* c, const raks_query_desc* q, raks_results** out) {
-  if (!c) return fail(RAKS_EINVAL, "ctx is NULL");
-  if (!out) return fail(RAKS_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (!c->loaded) return fail(RAKS_ESTATE, "no graph loaded");
-  QueryPlan p;
-  RAKS_TRY(validate_query(c, q, p));
-  RAKS_TRY(ensure_node_buffers(c));
-  RAKS_TRY(dev_alloc(c, c->Hc, (size_t)c->n_pad * p.TPc));
-  if (p.M > 0) RAKS_TRY(dev_alloc(c, c->Hm, (size_t)c->n_pad * p.TPm));
+// One attempt at a query with the current recovery capacities; *overflow is
+// set when a capacity ran out (the caller grows them and repeats).
+int query_attempt(raks_ctx* c, const QueryPlan& p, raks_results** out, bool* overflow) {
+  *overflow = false;
   Status* st = P<Status>(c->status);
   HIP_OK(hipEventRecord(c->q_start, c->stream));
   k_query_reset<<<1, 1, 0, c->stream>>>(st);
 
-  // ---- central run
-  RunView r1 = run_view(c, RUN_CENTRAL, p.C, c->Hc, p, 0);
-  RAKS_TRY(run_levels(c, r1, p.TPc, p.central, p.C));
+  // ---- central run and top-w selection
+  RunView r1 = run_view(c, RUN_CENTRAL, p.C, c->Hc, p);
+  RunStatus s1 = {}, s2 = {};
+  RAKS_TRY(run_levels(c, r1, p.TPc, p.central, p.C, &s1));
   SelectView sv;
   sv.cand = P<uint64_t>(c->cand);
   sv.st = r1.st;
@@ -536,39 +576,32 @@ int query_one(raks_ctx* c, const raks_query_desc* q, raks_results** out) {
     Timed t(c, 2);
     launch_select(sv, c->stream);
   }
+
+  // ---- recovery of the selected CGs (instances beyond nsel exit at once)
+  const int top1 = std::max(0, s1.levels - 1);   // central levels are at most this
+  RAKS_TRY(ensure_recovery(c, std::max(p.w * p.C, p.k * p.M), p.w, p.C, p.M, p.k, p.L));
+  {
+    Timed t(c, 3);
+    launch_recover(recover_view(c, 0, c->Hc, p.TPc, p.C, p.w * p.C, &st->nsel, top1), c->stream);
+    launch_finalize(finalize_view(c, 0, p.C, p.w, &st->nsel, p.C, p.TPc, p.M), c->stream);
+    if (p.M > 0)
+      launch_pack_vc(P<uint32_t>(c->vc_cnt), P<int32_t>(c->vc_tmp), (uint32_t)p.C * c->nc,
+                     &st->nsel, P<uint32_t>(c->vc_off), P<int32_t>(c->vc_nodes), c->stream);
+  }
   HIP_OK(hipGetLastError());
-  RAKS_TRY(read_status(c));
-  const int nsel = c->h_status->nsel;
 
-  // ---- recovery of the selected CGs
-  for (int attempt = 0; nsel > 0; ++attempt) {
-    RAKS_TRY(ensure_recovery(c, nsel * p.C, nsel, p.C, p.M, p.k));
-    k_clear_overflow<<<1, 1, 0, c->stream>>>(st);
-    {
-      Timed t(c, 3);
-      launch_recover(recover_view(c, 0, c->Hc, p.TPc, p.C, nsel * p.C), c->stream);
-      launch_finalize(finalize_view(c, 0, p.C, nsel, p.C, p.TPc, p.M), c->stream);
-      launch_pack_vc(P<uint32_t>(c->vc_cnt), P<int32_t>(c->vc_tmp), (uint32_t)p.C * c->nc, nsel,
-                     P<uint32_t>(c->vc_off), P<int32_t>(c->vc_nodes), c->stream);
-    }
-    HIP_OK(hipGetLastError());
-    RAKS_TRY(read_status(c));
-    if (!c->h_status->overflow) break;
-    if (attempt > 8) return fail(RAKS_ENOMEM, "recovered central graphs exceed capacity");
-    c->nc *= 4;
-    c->ac *= 4;
+  // ---- marginal run (ends before level 0 when no CG was selected)
+  int top2 = 0;
+  if (p.M > 0) {
+    RunView r2 = run_view(c, RUN_MARGINAL, p.M, c->Hm, p);
+    RAKS_TRY(run_levels(c, r2, p.TPm, p.marginal, p.M, &s2));
+    top2 = std::max(0, s2.levels - 1);
   }
 
-  // ---- marginal run
-  if (p.M > 0 && nsel > 0) {
-    RunView r2 = run_view(c, RUN_MARGINAL, p.M, c->Hm, p, nsel);
-    RAKS_TRY(run_levels(c, r2, p.TPm, p.marginal, p.M));
-  }
-
-  // ---- ranking
+  // ---- ranking, marginal recovery, output
   RankView rv;
   rv.gst = st;
-  rv.nsel = nsel;
+  rv.nsel = &st->nsel;
   rv.M = p.M;
   rv.k = p.k;
   rv.gamma_num = p.gn;
@@ -578,99 +611,80 @@ int query_one(raks_ctx* c, const raks_query_desc* q, raks_results** out) {
   rv.sm = P<int32_t>(c->sm);
   rv.key = P<int64_t>(c->key);
   rv.ranked = P<int32_t>(c->ranked);
-  int nres = 0;
-  if (nsel > 0) {
-    if (p.M > 0 && c->h_status->run[RUN_MARGINAL].end_reason == END_EMPTY_KEYWORD) {
-      nres = 0;
-    } else {
-      {
-        Timed t(c, 2);
-        launch_rank(rv, c->stream);
-      }
-      RAKS_TRY(read_status(c));
-      nres = c->h_status->nres;
-    }
+  {
+    Timed t(c, 2);
+    launch_rank(rv, c->stream);
   }
-
-  // ---- marginal recovery and output
-  if (nres > 0) {
-    for (int attempt = 0;; ++attempt) {
-      RAKS_TRY(ensure_recovery(c, std::max(nsel * p.C, nres * p.M), nsel, p.C, p.M, nres));
-      const size_t ncap = (size_t)nres * ((size_t)p.C * c->nc + (size_t)p.M * c->nc);
-      const size_t acap = (size_t)nres * ((size_t)p.C * c->ac + (size_t)p.M * c->ac);
-      RAKS_TRY(dev_alloc(c, c->hdr, (size_t)nres * sizeof(ResultHdr)));
-      RAKS_TRY(dev_alloc(c, c->out_nodes, ncap * 4));
-      RAKS_TRY(dev_alloc(c, c->out_arcs, acap * 12));
-      k_clear_overflow<<<1, 1, 0, c->stream>>>(st);
-      {
-        Timed t(c, 3);
-        if (p.M > 0)
-          launch_recover(recover_view(c, 1, c->Hm, p.TPm, p.M, nres * p.M), c->stream);
-        FinalizeView fv = finalize_view(c, 1, p.M, nres, p.C, p.TPc, p.M);
-        fv.out_ncap = (uint32_t)std::min<size_t>(ncap, UINT32_MAX);
-        fv.out_acap = (uint32_t)std::min<size_t>(acap, UINT32_MAX);
-        launch_finalize(fv, c->stream);
-      }
-      HIP_OK(hipGetLastError());
-      RAKS_TRY(read_status(c));
-      if (!c->h_status->overflow) break;
-      if (attempt > 8) return fail(RAKS_ENOMEM, "recovered radial pattern graphs exceed capacity");
-      c->nc *= 4;
-      c->ac *= 4;
-      // the CG lists were built with the old capacities: rebuild them
-      RAKS_TRY(ensure_recovery(c, std::max(nsel * p.C, nres * p.M), nsel, p.C, p.M, nres));
-      k_clear_overflow<<<1, 1, 0, c->stream>>>(st);
-      launch_recover(recover_view(c, 0, c->Hc, p.TPc, p.C, nsel * p.C), c->stream);
-      launch_finalize(finalize_view(c, 0, p.C, nsel, p.C, p.TPc, p.M), c->stream);
-      launch_pack_vc(P<uint32_t>(c->vc_cnt), P<int32_t>(c->vc_tmp), (uint32_t)p.C * c->nc, nsel,
-                     P<uint32_t>(c->vc_off), P<int32_t>(c->vc_nodes), c->stream);
-      RAKS_TRY(read_status(c));
-      if (c->h_status->overflow) continue;
-    }
+  {
+    Timed t(c, 3);
+    if (p.M > 0)
+      launch_recover(recover_view(c, 1, c->Hm, p.TPm, p.M, p.k * p.M, &st->nres, top2), c->stream);
+    FinalizeView fv = finalize_view(c, 1, p.M, p.k, &st->nres, p.C, p.TPc, p.M);
+    fv.out_ncap = (uint32_t)std::min<size_t>(c->out_nodes.bytes / 4, UINT32_MAX);
+    fv.out_acap = (uint32_t)std::min<size_t>(c->out_arcs.bytes / 12, UINT32_MAX);
+    launch_finalize(fv, c->stream);
   }
+  HIP_OK(hipGetLastError());
   HIP_OK(hipEventRecord(c->q_end, c->stream));
 
-  // ---- results to the host
-  raks_results* res = (raks_results*)calloc(1, sizeof(raks_results));
-  if (!res) return fail(RAKS_ENOMEM, "host allocation failed");
-  std::vector<ResultHdr> hdr(nres);
-  const uint32_t tn = c->h_status->out_nodes, ta = c->h_status->out_arcs;
-  std::vector<int32_t> nodes(tn), arcs((size_t)ta * 3);
-  if (nres > 0) {
-    HIP_OK(hipMemcpyAsync(hdr.data(), c->hdr.p, sizeof(ResultHdr) * nres, hipMemcpyDeviceToHost, c->stream));
-    if (tn) HIP_OK(hipMemcpyAsync(nodes.data(), c->out_nodes.p, 4 * (size_t)tn, hipMemcpyDeviceToHost, c->stream));
-    if (ta) HIP_OK(hipMemcpyAsync(arcs.data(), c->out_arcs.p, 12 * (size_t)ta, hipMemcpyDeviceToHost, c->stream));
-  }
+  // ---- results to the host: status, headers and a first slice of the
+  // output in one round trip
+  HIP_OK(hipMemcpyAsync(c->h_status, st, sizeof(Status), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(hipMemcpyAsync(c->h_hdr, c->hdr.p, sizeof(ResultHdr) * p.k, hipMemcpyDeviceToHost, c->stream));
+  const size_t spec_n = std::min(c->out_nodes.bytes / 4, (size_t)kSpecNodes);
+  const size_t spec_a = std::min(c->out_arcs.bytes / 12, (size_t)kSpecArcs);
+  HIP_OK(hipMemcpyAsync(c->h_nodes, c->out_nodes.p, 4 * spec_n, hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(hipMemcpyAsync(c->h_arcs, c->out_arcs.p, 12 * spec_a, hipMemcpyDeviceToHost, c->stream));
   HIP_OK(hipStreamSynchronize(c->stream));
+  const Status hs = *c->h_status;
+  if (hs.overflow) {
+    *overflow = true;
+    if (c->timing) harvest_timing(c);
+    return RAKS_OK;
+  }
+  const int nres = hs.nres, nsel = hs.nsel;
+  const uint32_t tn = hs.out_nodes, ta = hs.out_arcs;
+  std::vector<int32_t> big_nodes, big_arcs;
+  const int32_t* nodes = c->h_nodes;
+  const int32_t* arcs = c->h_arcs;
+  if (tn > spec_n) {
+    big_nodes.resize(tn);
+    HIP_OK(hipMemcpyAsync(big_nodes.data(), c->out_nodes.p, 4 * (size_t)tn, hipMemcpyDeviceToHost, c->stream));
+    nodes = big_nodes.data();
+  }
+  if (ta > spec_a) {
+    big_arcs.resize((size_t)ta * 3);
+    HIP_OK(hipMemcpyAsync(big_arcs.data(), c->out_arcs.p, 12 * (size_t)ta, hipMemcpyDeviceToHost, c->stream));
+    arcs = big_arcs.data();
+  }
+  if (tn > spec_n || ta > spec_a) HIP_OK(hipStreamSynchronize(c->stream));
   float ms = 0;
   (void)hipEventElapsedTime(&ms, c->q_start, c->q_end);
   if (c->timing) harvest_timing(c);
 
-  const Status& hs = *c->h_status;
+  raks_results* res = (raks_results*)calloc(1, sizeof(raks_results));
+  if (!res) return fail(RAKS_ENOMEM, "host allocation failed");
   res->n = nres;
   res->r = (raks_result*)calloc(std::max(nres, 1), sizeof(raks_result));
   for (int t = 0; t < nres; ++t) {
     raks_result& o = res->r[t];
-    const ResultHdr& h = hdr[t];
+    const ResultHdr& h = c->h_hdr[t];
     o.central_node = h.central;
     o.score_c = h.score_c;
     o.score_m = h.score_m;
     o.key = h.key;
     o.n_nodes = (int32_t)h.n_nodes;
     int32_t* nd = (int32_t*)malloc(sizeof(int32_t) * std::max<uint32_t>(h.n_nodes, 1));
-    memcpy(nd, nodes.data() + h.node_off, sizeof(int32_t) * h.n_nodes);
+    memcpy(nd, nodes + h.node_off, sizeof(int32_t) * h.n_nodes);
     o.nodes = nd;
     o.n_arcs = (int32_t)h.n_arcs;
     raks_arc* ar = (raks_arc*)malloc(sizeof(raks_arc) * std::max<uint32_t>(h.n_arcs, 1));
-    for (uint32_t i = 0; i < h.n_arcs; ++i) {
-      ar[i].src = arcs[3 * (size_t)(h.arc_off + i)];
-      ar[i].dst = arcs[3 * (size_t)(h.arc_off + i) + 1];
-      ar[i].label = arcs[3 * (size_t)(h.arc_off + i) + 2];
-    }
+    memcpy(ar, arcs + 3 * (size_t)h.arc_off, sizeof(raks_arc) * h.n_arcs);
     o.arcs = ar;
   }
+  const RunStatus* rs2[2] = {&hs.run[0], &hs.run[1]};
   for (int k = 0; k < 2; ++k) {
-    const RunStatus& rs = hs.run[k];
+    const RunStatus& rs = *rs2[k];
     const bool ran = (k == 0) || (p.M > 0 && nsel > 0);
     res->stats.levels[k] = ran ? rs.levels : 0;
     res->stats.end_reason[k] = ran ? rs.end_reason : END_NONE;
@@ -688,6 +702,27 @@ int query_one(raks_ctx* c, const raks_query_desc* q, raks_results** out) {
   res->status = status;
   *out = res;
   return RAKS_OK;
+}
+
+int query_one(raks_ctx* c, const raks_query_desc* q, raks_results** out) {
+  if (!c) return fail(RAKS_EINVAL, "ctx is NULL");
+  if (!out) return fail(RAKS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!c->loaded) return fail(RAKS_ESTATE, "no graph loaded");
+  QueryPlan p;
+  RAKS_TRY(validate_query(c, q, p));
+  RAKS_TRY(ensure_node_buffers(c));
+  RAKS_TRY(dev_alloc(c, c->Hc, (size_t)c->n_pad * p.TPc));
+  if (p.M > 0) RAKS_TRY(dev_alloc(c, c->Hm, (size_t)c->n_pad * p.TPm));
+  for (int attempt = 0;; ++attempt) {
+    bool overflow = false;
+    RAKS_TRY(query_attempt(c, p, out, &overflow));
+    if (!overflow) return RAKS_OK;
+    if (attempt >= 6) return fail(RAKS_ENOMEM, "recovered subgraphs exceed the recovery capacity");
+    c->nc *= 4;
+    c->ac *= 4;
+    c->lcap *= 4;
+  }
 }
 
 }  // namespace
@@ -731,6 +766,11 @@ int raks_create(raks_ctx** out, const raks_ctx_opts* opts) {
     c->own_stream = true;
   }
   if (hipHostMalloc((void**)&c->h_status, sizeof(Status), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_run, 2 * sizeof(RunStatus), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_hdr, kMaxW * sizeof(ResultHdr), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_nodes, kSpecNodes * 4, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_arcs, kSpecArcs * 12, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreate(&c->lvl_ev[0]) != hipSuccess || hipEventCreate(&c->lvl_ev[1]) != hipSuccess ||
       hipEventCreate(&c->q_start) != hipSuccess || hipEventCreate(&c->q_end) != hipSuccess) {
     raks_destroy(c);
     return fail(RAKS_EDEVICE, "host status / event allocation failed");
@@ -746,17 +786,24 @@ int raks_destroy(raks_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   DevBuf* bufs[] = {&c->row_ptr, &c->col, &c->label, &c->act, &c->act_node, &c->nw, &c->kw_nodes,
-                    &c->Hc, &c->Hm, &c->F, &c->tot, &c->off, &c->q_node, &c->q_off, &c->q_rs,
+                    &c->col_s, &c->act_s, &c->eid_s, &c->row_amax, &c->bnd,
+                    &c->arc_src, &c->Hc, &c->Hm, &c->F, &c->tot, &c->off, &c->q_lo, &c->q_off, &c->q_rs,
                     &c->q_mask, &c->cand, &c->sel_node, &c->sel_sc, &c->sel_sumh, &c->has_rpg,
                     &c->sm, &c->key, &c->dmin, &c->ranked, &c->vc_cnt, &c->vc_tmp, &c->vc_off,
                     &c->vc_nodes, &c->ht, &c->nl, &c->al, &c->icnt, &c->cg_nodes, &c->cg_arcs,
-                    &c->cg_cnt, &c->sort_a, &c->sort_b, &c->hdr, &c->out_nodes, &c->out_arcs,
+                    &c->cg_cnt, &c->sort_a, &c->sort_b, &c->items, &c->lcnt, &c->hdr, &c->out_nodes, &c->out_arcs,
                     &c->status};
   for (DevBuf* b : bufs) dev_free(c, *b);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->q_start) (void)hipEventDestroy(c->q_start);
   if (c->q_end) (void)hipEventDestroy(c->q_end);
   if (c->h_status) (void)hipHostFree(c->h_status);
+  if (c->h_run) (void)hipHostFree(c->h_run);
+  if (c->h_hdr) (void)hipHostFree(c->h_hdr);
+  if (c->h_nodes) (void)hipHostFree(c->h_nodes);
+  if (c->h_arcs) (void)hipHostFree(c->h_arcs);
+  for (hipEvent_t e : c->lvl_ev)
+    if (e) (void)hipEventDestroy(e);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return RAKS_OK;

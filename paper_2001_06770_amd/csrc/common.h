@@ -10,8 +10,8 @@ namespace raks {
 
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kBlock = 256;        // threads per workgroup for most kernels
-constexpr int kScanNodes = 4096;   // nodes per frontier-scan workgroup (16 per thread)
-constexpr int kExpandTile = 1024;  // arcs per expansion tile
+constexpr int kScanNodes = 1024;   // nodes per frontier-scan workgroup (4 per thread)
+constexpr int kExpandTile = 2048;  // arcs per expansion tile
 constexpr int kMaxKw = 16;         // keywords per run
 constexpr int kMaxW = 256;         // beam width limit
 constexpr uint8_t kInf = 0xFF;     // "not reached" in the node-keyword matrix
@@ -29,8 +29,8 @@ struct RunStatus {
   int32_t expand_on;     // 1 if the expansion of the current level runs
   int32_t levels;        // identification passes made
   uint32_t nfront;       // |frontier| of the current level
-  uint32_t nactive;      // frontier entries that expand (unblocked, reached, degree > 0)
-  uint32_t W;            // arcs they scan (= sum of their degrees)
+  uint32_t nactive;      // queue entries (frontiers with arcs to examine at this level)
+  uint32_t W;            // arcs examined by the expansion of this level
   uint32_t ncand_level;  // central nodes identified at the current level
   uint32_t ncand_total;  // central nodes identified so far
   uint32_t nrpg;         // CGs with an RPG so far (marginal run)
@@ -50,12 +50,19 @@ struct Status {
 
 // Per-workgroup totals of the frontier scan.
 struct ScanTot {
-  uint32_t nfront, nactive, ncand, deg;
-  uint64_t degk;         // sum of degree * active keywords (Algorithm 1 work)
+  uint32_t nfront;       // flagged nodes
+  uint32_t nq;           // queue entries (nodes with arcs to examine at this level)
+  uint32_t ncand;        // central nodes identified
+  uint32_t work;         // arcs the GPU examines (sum of queue entry ranges)
+  uint32_t hw;           // hitting levels written by the previous expansion
+  uint32_t pad;
+  uint64_t deg;          // sum of degrees of expanding frontiers (Algorithm 1 scans)
+  uint64_t degk;         // sum of degree * expanding keywords
+  uint64_t gate;         // arcs with level <= l of expanding frontiers
 };
 
 struct ScanOff {
-  uint32_t active, deg, cand, pad;
+  uint32_t q, work, cand, pad;
 };
 
 // Output header of one result.
@@ -115,6 +122,79 @@ __device__ inline T block_sum(T v, T* scratch) {
   T tot;
   (void)block_exclusive_scan<T, NT>(v, scratch, &tot);
   return tot;
+}
+
+// Exclusive scans of N values at once over a block of NT threads: one LDS
+// exchange (two barriers) for all of them.  `scratch` holds (NT/64 + 1) * N
+// 64-bit words.  v[] is replaced by the exclusive prefixes, tot[] gets the
+// block totals.
+template <int N, int NT>
+__device__ inline void block_exclusive_scan_multi(uint64_t (&v)[N], uint64_t (&tot)[N],
+                                                  uint64_t* scratch) {
+  constexpr int NW = NT / kWave;
+  uint64_t inc[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) inc[k] = wave_inclusive_scan(v[k]);
+  if (lane_id() == kWave - 1)
+#pragma unroll
+    for (int k = 0; k < N; ++k) scratch[wave_id() * N + k] = inc[k];
+  __syncthreads();
+  if (threadIdx.x < N) {
+    const int k = threadIdx.x;
+    uint64_t acc = 0;
+    for (int w = 0; w < NW; ++w) { const uint64_t t = scratch[w * N + k]; scratch[w * N + k] = acc; acc += t; }
+    scratch[NW * N + k] = acc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const uint64_t x = v[k];
+    v[k] = scratch[wave_id() * N + k] + inc[k] - x;
+    tot[k] = scratch[NW * N + k];
+  }
+  __syncthreads();
+}
+
+// Exclusive max-scan over a block of kBlock threads of non-negative values;
+// `scratch` holds kBlock/64 + 1 words of LDS.  Contains __syncthreads.
+__device__ inline uint32_t block_exclusive_max(uint32_t v, uint32_t* scratch) {
+  const int lane = lane_id();
+  uint32_t inc = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t o = __shfl_up(inc, d, kWave);
+    if (lane >= d) inc = inc > o ? inc : o;
+  }
+  if (lane == kWave - 1) scratch[wave_id()] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int w = 0; w < kBlock / kWave; ++w) { const uint32_t t = scratch[w]; scratch[w] = acc; acc = acc > t ? acc : t; }
+  }
+  __syncthreads();
+  uint32_t ex = __shfl_up(inc, 1, kWave);
+  if (lane == 0) ex = 0;
+  const uint32_t w = scratch[wave_id()];
+  __syncthreads();
+  return ex > w ? ex : w;
+}
+
+// Last index j in [0, n) with a[j] <= x (a non-decreasing, a[0] <= x), found
+// by one wavefront: each round the 64 lanes probe 64 evenly spaced entries,
+// so the search takes ceil(log64 n) dependent memory round trips.
+__device__ inline int wave_search(const uint32_t* a, int n, uint32_t x) {
+  int lo = 0, hi = n;
+  const int lane = lane_id();
+  while (hi - lo > 1) {
+    const int step = (hi - lo + kWave - 1) / kWave;
+    const int idx = lo + lane * step;
+    const bool ok = idx < hi && a[idx] <= x;
+    const uint64_t b = __ballot(ok);
+    const int L = 63 - __clzll((long long)b);
+    lo += L * step;
+    hi = min(hi, lo + step);
+  }
+  return lo;
 }
 
 // Last index j in [lo, hi) with a[j] <= x, given a[lo] <= x (a non-decreasing).

@@ -13,7 +13,7 @@
 //                   (node, row start, keyword mask, degree prefix), records
 //                   the identified central nodes and clears F;
 //   k_expand        Algorithm 1 for every (frontier, arc) pair, balanced by
-//                   arcs: each workgroup takes tiles of 1024 consecutive arcs
+//                   arcs: each workgroup takes tiles of 2048 consecutive arcs
 //                   of the concatenated frontier rows, so a hub's arcs spread
 //                   over many workgroups; one H-row gather serves all keywords
 //                   of the frontier at once.
@@ -42,10 +42,13 @@ __device__ inline void load_row(const uint8_t* H, int64_t v, uint8_t (&b)[TP]) {
 
 // ------------------------------------------------------------- run init ---
 
-__global__ void k_run_reset(RunStatus* st, int32_t empty) {
+// A run with a keyword that has no node ends before level 0; the marginal
+// run does not run at all when the central run selected no CG.
+__global__ void k_run_reset(RunStatus* st, int32_t empty, const int32_t* nsel) {
   RunStatus s = {};
-  s.end_level = empty ? -1 : INT32_MAX;
-  s.end_reason = empty ? END_EMPTY_KEYWORD : END_NONE;
+  const bool skip = nsel != nullptr && *nsel == 0;
+  s.end_level = (skip || empty) ? -1 : INT32_MAX;
+  s.end_reason = skip ? END_NONE : (empty ? END_EMPTY_KEYWORD : END_NONE);
   *st = s;
 }
 
@@ -78,72 +81,102 @@ __global__ __launch_bounds__(kBlock) void k_seed(uint8_t* H, uint8_t* F, const i
 }
 
 // --------------------------------------------------------- frontier scan ---
+//
+// Work-efficient form of Algorithm 1 (same H, F and counters).  A frontier f
+// at level l is retained (line 11) exactly when it expands and its row has an
+// arc of level > l: a property of the row, precomputed as row_amax.  A keyword
+// i with h_fi < l expanded f at level l-1 over all arcs of level <= l-1, so
+// only arcs of level exactly l can reach new nodes for it; a keyword with
+// h_fi = l needs all arcs of level <= l.  With rows sorted by level these are
+// the row slices [lo, hi) and [0, hi), read from the per-node level table.
+// Every workgroup scans 1024 frontier flags, 4 per thread.
 
 struct NodeInfo {
-  uint32_t mask, deg;
-  bool active, cand;
+  uint32_t mask_new, mask_old;  // keywords with h == level / h < level
+  uint32_t deg;                 // row degree if the node expands (Algorithm 1 scans it)
+  uint32_t rs, lo, hi, start;   // row start; arcs of level < l end at lo, <= l end at hi
+  uint32_t work;                // hi - start if the node expands
+  uint32_t hw;                  // entries written at the previous level
+  bool active, cand, retain;
   uint64_t key;
 };
 
 template <int TP>
-__device__ inline NodeInfo inspect_node(const RunView& r, const uint32_t* row_ptr, int32_t v,
+__device__ inline NodeInfo inspect_node(const RunView& r, const DevGraphView& g, int32_t v,
                                         int level) {
   uint8_t b[TP];
   load_row<TP>(r.H, v, b);
   bool complete = true;
-  uint32_t m = 0, mx = 0, sum = 0;
+  uint32_t mn = 0, mo = 0, mx = 0, sum = 0;
 #pragma unroll
   for (int i = 0; i < TP; ++i) {
     const uint32_t h = b[i];
     const bool inf = h == kInf;
     complete &= !inf;
-    if (h <= (uint32_t)level) m |= 1u << i;
+    if (h == (uint32_t)level) mn |= 1u << i;
+    if (h < (uint32_t)level) mo |= 1u << i;
     mx = (!inf && h > mx) ? h : mx;
     sum += inf ? 0u : h;
   }
-  m &= r.tmask;
   NodeInfo o;
+  o.mask_new = mn & r.tmask;
+  o.mask_old = mo & r.tmask;
+  o.hw = level >= 1 ? __popc(o.mask_new) : 0;
   const bool blocked = r.block_rule && complete;
-  const uint32_t d = row_ptr[v + 1] - row_ptr[v];
-  o.active = !blocked && m != 0 && d > 0;
-  o.mask = m;
+  o.rs = g.row_ptr[v];
+  const uint32_t d = g.row_ptr[v + 1] - o.rs;
+  o.active = !blocked && (o.mask_new | o.mask_old) != 0 && d > 0;
   o.deg = o.active ? d : 0;
   o.cand = (r.kind == RUN_CENTRAL) && complete && mx == (uint32_t)level;
   o.key = ((uint64_t)mx << 48) | ((uint64_t)sum << 32) | (uint32_t)v;
+  o.lo = o.hi = o.start = o.work = 0;
+  o.retain = false;
+  if (o.active) {
+    o.lo = count_le(g, v, level - 1);
+    o.hi = count_le(g, v, level);
+    o.start = o.mask_new ? 0 : o.lo;
+    o.work = o.hi - o.start;
+    o.retain = g.row_amax[v] > (uint32_t)level;
+  }
   return o;
 }
 
 template <int TP>
-__global__ __launch_bounds__(kBlock) void k_front_count(RunView r, const uint32_t* row_ptr,
-                                                        int level) {
+__global__ __launch_bounds__(kBlock) void k_front_count(RunView r, DevGraphView g, int level) {
   if (level > r.st->end_level) return;
   __shared__ uint32_t s32[kBlock / kWave + 1];
   __shared__ uint64_t s64[kBlock / kWave + 1];
-  const int64_t base = (int64_t)blockIdx.x * kScanNodes + threadIdx.x * 16;
-  const uint4 fw = *reinterpret_cast<const uint4*>(r.F + base);
-  uint32_t nf = 0, na = 0, nc = 0, dg = 0;
-  uint64_t dk = 0;
-  if (fw.x | fw.y | fw.z | fw.w) {
-    uint8_t fb[16];
-    __builtin_memcpy(fb, &fw, 16);
-    for (int k = 0; k < 16; ++k) {
-      if (!fb[k]) continue;
-      const NodeInfo o = inspect_node<TP>(r, row_ptr, (int32_t)(base + k), level);
+  const int64_t base = (int64_t)blockIdx.x * kScanNodes + threadIdx.x * 4;
+  const uint32_t fw = *reinterpret_cast<const uint32_t*>(r.F + base);
+  uint32_t nf = 0, nq = 0, nc = 0, wk = 0, hw = 0;
+  uint64_t dg = 0, dk = 0, gt = 0;
+  if (fw) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (!((fw >> (8 * k)) & 0xFF)) continue;
+      const NodeInfo o = inspect_node<TP>(r, g, (int32_t)(base + k), level);
       ++nf;
-      if (o.active) { ++na; dg += o.deg; dk += (uint64_t)o.deg * __popc(o.mask); }
+      hw += o.hw;
       nc += o.cand;
+      if (o.active) {
+        dg += o.deg;
+        dk += (uint64_t)o.deg * __popc(o.mask_new | o.mask_old);
+        gt += o.hi;
+        if (o.work) { ++nq; wk += o.work; }
+      }
     }
   }
-  nf = block_sum<uint32_t, kBlock>(nf, s32);
-  na = block_sum<uint32_t, kBlock>(na, s32);
-  nc = block_sum<uint32_t, kBlock>(nc, s32);
-  dg = block_sum<uint32_t, kBlock>(dg, s32);
-  dk = block_sum<uint64_t, kBlock>(dk, s64);
-  if (threadIdx.x == 0) {
-    ScanTot t;
-    t.nfront = nf; t.nactive = na; t.ncand = nc; t.deg = dg; t.degk = dk;
-    r.tot[blockIdx.x] = t;
-  }
+  ScanTot t;
+  t.nfront = block_sum<uint32_t, kBlock>(nf, s32);
+  t.nq = block_sum<uint32_t, kBlock>(nq, s32);
+  t.ncand = block_sum<uint32_t, kBlock>(nc, s32);
+  t.work = block_sum<uint32_t, kBlock>(wk, s32);
+  t.hw = block_sum<uint32_t, kBlock>(hw, s32);
+  t.pad = 0;
+  t.deg = block_sum<uint64_t, kBlock>(dg, s64);
+  t.degk = block_sum<uint64_t, kBlock>(dk, s64);
+  t.gate = block_sum<uint64_t, kBlock>(gt, s64);
+  if (threadIdx.x == 0) r.tot[blockIdx.x] = t;
 }
 
 constexpr int kCtl = 1024;
@@ -159,7 +192,7 @@ __device__ int rpg_identify(const RunView& r, RunStatus* st, int level) {
   __shared__ int32_t s_has[kMaxW], s_sm[kMaxW];
   __shared__ int64_t s_key[kMaxW];
   __shared__ int32_t s_new, s_nrpg, s_kth, s_minsc, s_stop;
-  const int nsel = r.nsel, M = r.T;
+  const int nsel = *r.nsel, M = r.T;
   const int64_t gn = r.gamma_num, gd = r.gamma_den;
   for (int i = threadIdx.x; i < nsel * kMaxKw; i += kCtl) s_dm[i] = kInf;
   for (int i = threadIdx.x; i < nsel; i += kCtl) {
@@ -234,40 +267,42 @@ template <int TP>
 __global__ __launch_bounds__(kCtl) void k_front_control(RunView r, int level) {
   RunStatus* st = r.st;
   if (level > st->end_level) return;
-  __shared__ uint32_t s32[kCtl / kWave + 1];
-  __shared__ uint64_t s64[kCtl / kWave + 1];
   __shared__ int32_t s_end;
   const int nb = r.nblocks;
   const int per = (nb + kCtl - 1) / kCtl;
   const int b0 = min(nb, (int)threadIdx.x * per), b1 = min(nb, b0 + per);
-  uint32_t nf = 0, na = 0, nc = 0, dg = 0;
-  uint64_t dk = 0;
+  uint32_t nf = 0, nq = 0, nc = 0, wk = 0, hw = 0;
+  uint64_t dg = 0, dk = 0, gt = 0;
   for (int b = b0; b < b1; ++b) {
     const ScanTot t = r.tot[b];
-    nf += t.nfront; na += t.nactive; nc += t.ncand; dg += t.deg; dk += t.degk;
+    nf += t.nfront; nq += t.nq; nc += t.ncand; wk += t.work; hw += t.hw;
+    dg += t.deg; dk += t.degk; gt += t.gate;
   }
-  uint32_t tnf, tna, tnc, tdg;
-  uint64_t tdk;
-  (void)block_exclusive_scan<uint32_t, kCtl>(nf, s32, &tnf);
-  uint32_t xa = block_exclusive_scan<uint32_t, kCtl>(na, s32, &tna);
-  uint32_t xc = block_exclusive_scan<uint32_t, kCtl>(nc, s32, &tnc);
-  uint32_t xd = block_exclusive_scan<uint32_t, kCtl>(dg, s32, &tdg);
-  (void)block_exclusive_scan<uint64_t, kCtl>(dk, s64, &tdk);
+  // one pass for all eight values: q, work, cand prefixes; the rest totals
+  __shared__ uint64_t s_multi[(kCtl / kWave + 1) * 8];
+  uint64_t vals[8] = {nq, wk, nc, nf, hw, dg, dk, gt};
+  uint64_t tots[8];
+  block_exclusive_scan_multi<8, kCtl>(vals, tots, s_multi);
+  uint32_t xq = (uint32_t)vals[0], xw = (uint32_t)vals[1], xc = (uint32_t)vals[2];
+  const uint32_t tnq = (uint32_t)tots[0], twk = (uint32_t)tots[1], tnc = (uint32_t)tots[2];
+  const uint32_t tnf = (uint32_t)tots[3], thw = (uint32_t)tots[4];
+  const uint64_t tdg = tots[5], tdk = tots[6], tgt = tots[7];
   for (int b = b0; b < b1; ++b) {
     const ScanTot t = r.tot[b];
     ScanOff o;
-    o.active = xa; o.deg = xd; o.cand = xc; o.pad = 0;
+    o.q = xq; o.work = xw; o.cand = xc; o.pad = 0;
     r.off[b] = o;
-    xa += t.nactive; xd += t.deg; xc += t.ncand;
+    xq += t.nq; xw += t.work; xc += t.ncand;
   }
   if (threadIdx.x == 0) {
     st->levels = level + 1;
     st->nfront = tnf;
-    st->nactive = tna;
-    st->W = tdg;
+    st->nactive = tnq;
+    st->W = twk;
     st->ncand_level = tnc;
     st->frontier_sum += tnf;
-    r.q_off[tna] = tdg;
+    st->h_writes += thw;
+    r.q_off[tnq] = twk;
     s_end = END_NONE;
     if (tnf == 0) {
       s_end = END_EXHAUSTED;
@@ -291,128 +326,136 @@ __global__ __launch_bounds__(kCtl) void k_front_control(RunView r, int level) {
       st->expand_on = 1;
       st->e_arc += tdg;
       st->e_alg += tdk;
+      st->gate_pass += tgt;
     }
   }
 }
 
 template <int TP>
-__global__ __launch_bounds__(kBlock) void k_front_write(RunView r, const uint32_t* row_ptr,
-                                                        int level) {
+__global__ __launch_bounds__(kBlock) void k_front_write(RunView r, DevGraphView g, int level) {
   const RunStatus* st = r.st;
   if (level > st->end_level) return;
   __shared__ uint32_t s32[kBlock / kWave + 1];
   const bool expand = st->expand_on != 0;
-  const int64_t base = (int64_t)blockIdx.x * kScanNodes + threadIdx.x * 16;
-  const uint4 fw = *reinterpret_cast<const uint4*>(r.F + base);
-  const bool any = (fw.x | fw.y | fw.z | fw.w) != 0;
-  uint8_t fb[16];
-  __builtin_memcpy(fb, &fw, 16);
-  uint32_t na = 0, nc = 0, dg = 0;
-  if (any) {
-    for (int k = 0; k < 16; ++k) {
-      if (!fb[k]) continue;
-      const NodeInfo o = inspect_node<TP>(r, row_ptr, (int32_t)(base + k), level);
-      na += o.active; nc += o.cand; dg += o.deg;
-    }
+  const int64_t base = (int64_t)blockIdx.x * kScanNodes + threadIdx.x * 4;
+  const uint32_t fw = *reinterpret_cast<const uint32_t*>(r.F + base);
+  NodeInfo o[4];
+  uint32_t nq = 0, nc = 0, wk = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    o[k].work = 0;
+    o[k].cand = false;
+    o[k].retain = false;
+    if (!((fw >> (8 * k)) & 0xFF)) continue;
+    o[k] = inspect_node<TP>(r, g, (int32_t)(base + k), level);
+    nq += o[k].work != 0;
+    nc += o[k].cand;
+    wk += o[k].work;
   }
   uint32_t t;
-  const uint32_t xa = block_exclusive_scan<uint32_t, kBlock>(na, s32, &t);
+  const uint32_t xq = block_exclusive_scan<uint32_t, kBlock>(nq, s32, &t);
   const uint32_t xc = block_exclusive_scan<uint32_t, kBlock>(nc, s32, &t);
-  const uint32_t xd = block_exclusive_scan<uint32_t, kBlock>(dg, s32, &t);
-  if (!any) return;
+  const uint32_t xw = block_exclusive_scan<uint32_t, kBlock>(wk, s32, &t);
+  if (!fw) return;
   const ScanOff bo = r.off[blockIdx.x];
-  uint32_t apos = bo.active + xa, dpos = bo.deg + xd;
+  uint32_t qpos = bo.q + xq, wpos = bo.work + xw;
   uint32_t cpos = (st->ncand_total - st->ncand_level) + bo.cand + xc;
-  for (int k = 0; k < 16; ++k) {
-    if (!fb[k]) continue;
-    const int32_t v = (int32_t)(base + k);
-    const NodeInfo o = inspect_node<TP>(r, row_ptr, v, level);
-    if (o.active && expand) {
-      r.q_node[apos] = v;
-      r.q_off[apos] = dpos;
-      r.q_rs[apos] = row_ptr[v];
-      r.q_mask[apos] = o.mask;
-      ++apos;
-      dpos += o.deg;
+  uint32_t nf = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (expand) {
+      if (o[k].work) {
+        r.q_off[qpos] = wpos;
+        r.q_rs[qpos] = o[k].rs + o[k].start;
+        r.q_lo[qpos] = o[k].rs + o[k].lo;
+        r.q_mask[qpos] = o[k].mask_new | (o[k].mask_old << 16);
+        ++qpos;
+        wpos += o[k].work;
+      }
+      nf |= (o[k].retain ? 1u : 0u) << (8 * k);   // line 11: f stays a frontier
     }
-    if (o.cand) r.cand[cpos++] = o.key;
+    if (o[k].cand) r.cand[cpos++] = o[k].key;
   }
-  *reinterpret_cast<uint4*>(r.F + base) = make_uint4(0, 0, 0, 0);
+  *reinterpret_cast<uint32_t*>(r.F + base) = nf;
 }
 
-// Algorithm 1 at Glevel `level`, balanced over the arcs of the expanding
-// frontiers.  For arc f -> n with level a: a > level keeps f in the frontier
-// (line 10-11); otherwise every keyword i that f expands for and that has not
-// reached n gets h_ni = level + 1 and n becomes a frontier (lines 13-17).
+// Algorithm 1 at Glevel `level` over the queued row slices (all of them have
+// level <= l).  For arc f -> n every keyword i that f expands for and that has
+// not reached n gets h_ni = level + 1 and n becomes a frontier (lines 13-17).
+// One TP-byte row gather of the neighbour serves every keyword at once.
+// Tile of 2048 consecutive arcs of the concatenated slices: two
+// wavefronts find the first and last queue entry of the tile (64-ary
+// search), the entries go to LDS, each entry marks the tile item where it
+// starts and a block max-scan turns the marks into the owner entry of every
+// item; item i of the tile is handled by thread i mod 256, so consecutive
+// lanes read consecutive arcs.
 template <int TP>
 __global__ __launch_bounds__(kBlock) void k_expand(RunView r, DevGraphView g, int level) {
   RunStatus* st = r.st;
   if (level > st->end_level || !st->expand_on) return;
-  const uint32_t W = st->W, nact = st->nactive;
-  __shared__ uint32_t s_off[kExpandTile], s_rs[kExpandTile], s_mask[kExpandTile];
-  __shared__ int32_t s_node[kExpandTile];
-  __shared__ uint8_t s_ret[kExpandTile];
-  __shared__ int32_t s_e0, s_cnt;
-  uint64_t pass = 0;
+  constexpr int IPT = kExpandTile / kBlock;
+  const uint32_t W = st->W;
+  const int nq = (int)st->nactive;
+  __shared__ uint32_t s_base[kExpandTile];
+  __shared__ uint32_t s_lo[kExpandTile];
+  __shared__ uint32_t s_mask[kExpandTile];
+  __shared__ uint16_t s_own[kExpandTile];
+  __shared__ uint32_t s_scan[kBlock / kWave + 1];
+  __shared__ int32_t s_e[2];
   for (uint32_t tile = blockIdx.x; (uint64_t)tile * kExpandTile < W; tile += gridDim.x) {
     const uint32_t w0 = tile * kExpandTile;
     const uint32_t w1 = min(W, w0 + (uint32_t)kExpandTile);
-    if (threadIdx.x == 0) {
-      const int e0 = upper_index<uint32_t>(r.q_off, 0, (int)nact, w0);
-      const int e1 = upper_index<uint32_t>(r.q_off, e0, (int)nact, w1 - 1);
-      s_e0 = e0;
-      s_cnt = e1 - e0 + 1;
+    if (wave_id() < 2) {
+      const int j = wave_search(r.q_off, nq, wave_id() == 0 ? w0 : w1 - 1);
+      if (lane_id() == 0) s_e[wave_id()] = j;
     }
+    for (int i = threadIdx.x; i < kExpandTile; i += kBlock) s_own[i] = 0;
     __syncthreads();
-    const int e0 = s_e0, cnt = s_cnt;
+    const int e0 = s_e[0], cnt = s_e[1] - s_e[0] + 1;
     for (int j = threadIdx.x; j < cnt; j += kBlock) {
-      s_off[j] = r.q_off[e0 + j];
-      s_rs[j] = r.q_rs[e0 + j];
+      const uint32_t off = r.q_off[e0 + j];
+      s_base[j] = r.q_rs[e0 + j] - off + w0;   // arc of tile item i is s_base[j] + i
+      s_lo[j] = r.q_lo[e0 + j];
       s_mask[j] = r.q_mask[e0 + j];
-      s_node[j] = r.q_node[e0 + j];
-      s_ret[j] = 0;
+      s_own[off > w0 ? off - w0 : 0] = (uint16_t)j;
     }
     __syncthreads();
-    for (uint32_t wi = w0 + threadIdx.x; wi < w1; wi += kBlock) {
-      const int j = upper_index<uint32_t>(s_off, 0, cnt, wi);
-      const uint32_t e = s_rs[j] + (wi - s_off[j]);
-      const uint32_t a = g.act[e];
-      if (a > (uint32_t)level) { s_ret[j] = 1; continue; }
-      const int32_t nb = g.col[e];
+    uint32_t loc[IPT];
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      const uint32_t o = s_own[threadIdx.x * IPT + k];
+      m = o > m ? o : m;
+      loc[k] = m;
+    }
+    const uint32_t pre = block_exclusive_max(m, s_scan);
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) s_own[threadIdx.x * IPT + k] = (uint16_t)(pre > loc[k] ? pre : loc[k]);
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < IPT; ++k) {
+      const uint32_t i = k * kBlock + threadIdx.x;
+      if (w0 + i >= w1) break;
+      const int j = s_own[i];
+      const uint32_t e = s_base[j] + i;
+      const uint32_t mk = s_mask[j];
+      const uint32_t want = (e < s_lo[j]) ? (mk & 0xFFFFu) : ((mk & 0xFFFFu) | (mk >> 16));
+      const int32_t nb = g.col_s[e];
       uint8_t b[TP];
       load_row<TP>(r.H, nb, b);
-      uint32_t m = 0;
+      uint32_t mm = 0;
 #pragma unroll
-      for (int i = 0; i < TP; ++i) m |= (b[i] == kInf ? 1u : 0u) << i;
-      m &= s_mask[j];
-      if (m) {
+      for (int t = 0; t < TP; ++t) mm |= (b[t] == kInf ? 1u : 0u) << t;
+      mm &= want;
+      if (mm) {
 #pragma unroll
-        for (int i = 0; i < TP; ++i)
-          if ((m >> i) & 1u) r.H[(int64_t)nb * TP + i] = (uint8_t)(level + 1);
+        for (int t = 0; t < TP; ++t)
+          if ((mm >> t) & 1u) r.H[(int64_t)nb * TP + t] = (uint8_t)(level + 1);
         r.F[nb] = 1;
       }
-      ++pass;
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < cnt; j += kBlock)
-      if (s_ret[j]) r.F[s_node[j]] = 1;
-    __syncthreads();
   }
-  pass = wave_sum(pass);
-  if (lane_id() == 0 && pass) atomicAdd((unsigned long long*)&st->gate_pass, (unsigned long long)pass);
-}
-
-template <int TP>
-__global__ __launch_bounds__(kBlock) void k_count_writes(const uint8_t* H, int32_t n, RunStatus* st) {
-  uint64_t c = 0;
-  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
-    uint8_t b[TP];
-    load_row<TP>(H, v, b);
-#pragma unroll
-    for (int i = 0; i < TP; ++i) c += (b[i] != 0 && b[i] != kInf) ? 1 : 0;
-  }
-  c = wave_sum(c);
-  if (lane_id() == 0 && c) atomicAdd((unsigned long long*)&st->h_writes, (unsigned long long)c);
 }
 
 // -------------------------------------------------------------- top-w ---
@@ -486,7 +529,7 @@ __global__ __launch_bounds__(kBlock) void k_rank(RankView v) {
   __shared__ int32_t s_has[kMaxW];
   __shared__ int64_t s_key[kMaxW];
   __shared__ int32_t s_cnt;
-  const int nsel = v.nsel;
+  const int nsel = *v.nsel;
   if (threadIdx.x == 0) s_cnt = 0;
   __syncthreads();
   for (int r = threadIdx.x; r < nsel; r += kBlock) {
@@ -531,7 +574,7 @@ void launch_run_init(const RunView& r, int TP, int32_t n, const int32_t* kw_node
                      const SeedList& seeds, hipStream_t s) {
   int empty = 0;
   for (int i = 0; i < seeds.T; ++i) empty |= seeds.count[i] == 0;
-  k_run_reset<<<1, 1, 0, s>>>(r.st, empty);
+  k_run_reset<<<1, 1, 0, s>>>(r.st, empty, r.kind == RUN_MARGINAL ? r.nsel : nullptr);
   const unsigned g = (unsigned)std::min<int64_t>(8192, (r.n_pad + kBlock - 1) / kBlock);
   RAKS_TP_DISPATCH(TP, k_init_rows<kTP><<<g, kBlock, 0, s>>>(r.H, r.F, n, r.n_pad, r.T));
   const uint32_t total = seeds.prefix[seeds.T];
@@ -539,12 +582,11 @@ void launch_run_init(const RunView& r, int TP, int32_t n, const int32_t* kw_node
     const unsigned gs = (unsigned)std::min<uint32_t>(4096, (total + kBlock - 1) / kBlock);
     RAKS_TP_DISPATCH(TP, k_seed<kTP><<<gs, kBlock, 0, s>>>(r.H, r.F, kw_nodes, seeds));
   }
-  if (r.kind == RUN_MARGINAL && r.nsel > 0)
-    k_clear_rpg<<<1, kBlock, 0, s>>>(r.has_rpg, r.sm, r.key, r.nsel);
+  if (r.kind == RUN_MARGINAL) k_clear_rpg<<<1, kBlock, 0, s>>>(r.has_rpg, r.sm, r.key, kMaxW);
 }
 
 void launch_front_count(const RunView& r, int TP, const DevGraphView& g, int level, hipStream_t s) {
-  RAKS_TP_DISPATCH(TP, k_front_count<kTP><<<r.nblocks, kBlock, 0, s>>>(r, g.row_ptr, level));
+  RAKS_TP_DISPATCH(TP, k_front_count<kTP><<<r.nblocks, kBlock, 0, s>>>(r, g, level));
 }
 
 void launch_front_control(const RunView& r, int TP, int level, hipStream_t s) {
@@ -552,17 +594,12 @@ void launch_front_control(const RunView& r, int TP, int level, hipStream_t s) {
 }
 
 void launch_front_write(const RunView& r, int TP, const DevGraphView& g, int level, hipStream_t s) {
-  RAKS_TP_DISPATCH(TP, k_front_write<kTP><<<r.nblocks, kBlock, 0, s>>>(r, g.row_ptr, level));
+  RAKS_TP_DISPATCH(TP, k_front_write<kTP><<<r.nblocks, kBlock, 0, s>>>(r, g, level));
 }
 
 void launch_expand(const RunView& r, int TP, const DevGraphView& g, int level, int grid,
                    hipStream_t s) {
   RAKS_TP_DISPATCH(TP, k_expand<kTP><<<grid, kBlock, 0, s>>>(r, g, level));
-}
-
-void launch_count_writes(const RunView& r, int TP, int32_t n, hipStream_t s) {
-  const unsigned g = (unsigned)std::min<int64_t>(4096, (n + kBlock - 1) / kBlock);
-  RAKS_TP_DISPATCH(TP, k_count_writes<kTP><<<g, kBlock, 0, s>>>(r.H, n, r.st));
 }
 
 void launch_select(const SelectView& v, hipStream_t s) { k_select<<<1, kCtl, 0, s>>>(v); }

@@ -32,11 +32,12 @@ __global__ __launch_bounds__(kBlock) void k_check_and_count(const uint32_t* row_
                                                             const int32_t* col,
                                                             const uint16_t* label, int32_t n,
                                                             uint32_t A, uint32_t* c_out,
-                                                            Status* st) {
+                                                            int32_t* arc_src, Status* st) {
   uint32_t err = 0;
   uint64_t cmin = ~0ull, cmax = 0;
   for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < A; e += gridDim.x * kBlock) {
     const uint32_t i = row_of(row_ptr, n, e);
+    arc_src[e] = (int32_t)i;
     const int32_t j = col[e];
     const uint16_t lab = label[e];
     if (j < 0 || j >= n) { err |= 1; c_out[e] = 0; continue; }
@@ -129,6 +130,65 @@ __global__ __launch_bounds__(kBlock) void k_act_gather(const uint8_t* act_node,
     act[e] = act_node[col[e]];
 }
 
+// Traversal copy of the graph: each row's arcs re-ordered by activation level
+// (counting sort per row, one wavefront per row), plus the row's largest
+// level.  At level l a frontier's arcs with level <= l form a row prefix.
+__global__ __launch_bounds__(kBlock) void k_sort_rows(const uint32_t* row_ptr, const int32_t* col,
+                                                      const uint8_t* act, int32_t n,
+                                                      int32_t* col_s, uint8_t* act_s,
+                                                      uint32_t* eid_s, uint8_t* row_amax,
+                                                      uint32_t* bnd, int32_t nbnd) {
+  __shared__ uint32_t s_hist[kBlock / kWave][256];
+  uint32_t* hist = s_hist[wave_id()];
+  const int lane = lane_id();
+  const int waves = gridDim.x * (kBlock / kWave);
+  for (int32_t v = blockIdx.x * (kBlock / kWave) + wave_id(); v < n; v += waves) {
+    const uint32_t rs = row_ptr[v], re = row_ptr[v + 1];
+    for (int b = lane; b < 256; b += kWave) hist[b] = 0;
+    __builtin_amdgcn_wave_barrier();
+    uint32_t amax = 0;
+    for (uint32_t e = rs + lane; e < re; e += kWave) {
+      const uint32_t a = act[e];
+      atomicAdd(&hist[a], 1u);
+      amax = a > amax ? a : amax;
+    }
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+      const uint32_t o = __shfl_xor(amax, d, kWave);
+      amax = o > amax ? o : amax;
+    }
+    __builtin_amdgcn_wave_barrier();
+    // exclusive prefix over the 256 bins: lane owns bins 4*lane .. 4*lane+3
+    uint32_t c0 = hist[4 * lane], c1 = hist[4 * lane + 1], c2 = hist[4 * lane + 2], c3 = hist[4 * lane + 3];
+    const uint32_t tot = c0 + c1 + c2 + c3;
+    const uint32_t ex = wave_inclusive_scan(tot) - tot;
+    hist[4 * lane] = ex;
+    hist[4 * lane + 1] = ex + c0;
+    hist[4 * lane + 2] = ex + c0 + c1;
+    hist[4 * lane + 3] = ex + c0 + c1 + c2;
+    __builtin_amdgcn_wave_barrier();
+    // arcs with level <= l = start of level l + 1
+    if (lane < nbnd) bnd[(size_t)v * nbnd + lane] = hist[lane + 1];
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t e = rs + lane; e < re; e += kWave) {
+      const uint32_t a = act[e];
+      const uint32_t pos = rs + atomicAdd(&hist[a], 1u);
+      col_s[pos] = col[e];
+      act_s[pos] = (uint8_t)a;
+      eid_s[pos] = e;
+    }
+    if (lane == 0) row_amax[v] = (uint8_t)amax;
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+void launch_sort_rows(const DevGraphView& g, int32_t* col_s, uint8_t* act_s, uint32_t* eid_s,
+                      uint8_t* row_amax, uint32_t* bnd, int32_t nbnd, hipStream_t s) {
+  const unsigned grid = (unsigned)std::min<int64_t>(16384, ((int64_t)g.n + 3) / 4);
+  k_sort_rows<<<grid, kBlock, 0, s>>>(g.row_ptr, g.col, g.act, g.n, col_s, act_s, eid_s, row_amax,
+                                      bnd, nbnd);
+}
+
 __global__ void k_status_reset_minmax(Status* st) {
   st->cmin = ~0ull;
   st->cmax = 0;
@@ -143,10 +203,12 @@ static unsigned grid_for(uint64_t items, unsigned cap = 8192) {
   return (unsigned)(g > cap ? cap : g);
 }
 
-void launch_check_and_count(const DevGraphView& g, uint32_t* c_tmp, Status* st, hipStream_t s) {
+void launch_check_and_count(const DevGraphView& g, uint32_t* c_tmp, int32_t* arc_src, Status* st,
+                            hipStream_t s) {
   k_status_reset_minmax<<<1, 1, 0, s>>>(st);
   if (g.A > 0)
-    k_check_and_count<<<grid_for(g.A), kBlock, 0, s>>>(g.row_ptr, g.col, g.label, g.n, g.A, c_tmp, st);
+    k_check_and_count<<<grid_for(g.A), kBlock, 0, s>>>(g.row_ptr, g.col, g.label, g.n, g.A, c_tmp,
+                                                        arc_src, st);
 }
 
 void launch_act_edge(const DevGraphView& g, const uint32_t* c_tmp, const Status* st, double abar,

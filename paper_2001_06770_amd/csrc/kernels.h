@@ -14,7 +14,29 @@ struct DevGraphView {
   const uint8_t* act;       // [A] activation level per arc
   const uint8_t* act_node;  // [n] NODE mode, else nullptr
   int32_t mode;             // 0 EDGE, 1 NODE
+  // traversal copy: every row re-ordered by activation level (ascending)
+  const int32_t* col_s;     // [A]
+  const uint8_t* act_s;     // [A]
+  const uint32_t* eid_s;    // [A] CSR position of the arc
+  const int32_t* arc_src;   // [A] source node of each arc (CSR order)
+  const uint8_t* row_amax;  // [n] largest activation level of the row (0 if empty)
+  const uint32_t* bnd;      // [n][nbnd] arcs of the row with level <= l, l < nbnd
+  int32_t nbnd;             // levels covered by bnd (1..16)
 };
+
+// Number of arcs of row v with activation level <= x (x may be negative).
+__device__ inline uint32_t count_le(const DevGraphView& g, int32_t v, int x) {
+  if (x < 0) return 0;
+  const uint32_t rs = g.row_ptr[v], re = g.row_ptr[v + 1];
+  if (x >= (int)g.row_amax[v]) return re - rs;
+  if (x < g.nbnd) return g.bnd[(size_t)v * g.nbnd + x];
+  uint32_t a = rs, b = re;
+  while (a < b) {
+    const uint32_t m = (a + b) >> 1;
+    if ((int)g.act_s[m] <= x) a = m + 1; else b = m;
+  }
+  return a - rs;
+}
 
 // State of one exploration run (Section 4.2), laid out for one query.
 struct RunView {
@@ -29,15 +51,15 @@ struct RunView {
   ScanTot* tot;          // [nblocks]
   ScanOff* off;          // [nblocks]
   int32_t nblocks;
-  int32_t* q_node;       // expansion queue: node
-  uint32_t* q_off;       // exclusive prefix of degrees [nactive+1]
-  uint32_t* q_rs;        // row start of the node
-  uint32_t* q_mask;      // keywords the node expands for
+  uint32_t* q_off;       // expansion queue: exclusive prefix of examined arcs [nactive+1]
+  uint32_t* q_rs;        // first examined arc (position in the level-sorted row)
+  uint32_t* q_lo;        // from here on the arcs have level == l: old keywords join
+  uint32_t* q_mask;      // keywords reached at level l | keywords reached before << 16
   uint64_t* cand;        // central run: identified central nodes (S<<48 | sum<<32 | node)
   int32_t max_level;
   int32_t w, k, gamma_num, gamma_den;
   // marginal run: RPG identification over the selected CGs
-  int32_t nsel;
+  const int32_t* nsel;       // device: number of selected CGs (marginal run)
   const int32_t* sel_sc;     // [nsel] S^c of the selected CGs, in CG rank order
   const uint32_t* vc_off;    // [nsel+1]
   const int32_t* vc_nodes;   // central-keyword nodes of each CG
@@ -66,7 +88,8 @@ struct SelectView {
 
 struct RankView {
   Status* gst;
-  int32_t nsel, M, k, gamma_num, gamma_den;
+  const int32_t* nsel;       // device: number of selected CGs
+  int32_t M, k, gamma_num, gamma_den;
   const int32_t* sel_sc;
   int32_t* has_rpg;
   int32_t* sm;
@@ -74,24 +97,39 @@ struct RankView {
   int32_t* ranked;     // [k] CG rank of result t
 };
 
-// Recovery (Algorithm 2) of one (result, keyword) instance per workgroup.
+// Recovery (Algorithm 2) of every (result, keyword) instance of a phase at
+// once, layer by layer (hitting level h from the largest down to 1).
+struct RecItem {
+  uint32_t inst;   // instance = result * T + keyword column
+  int32_t q;       // node whose in-arcs are examined
+  uint32_t start;  // first arc of the chunk (CSR position in q's row)
+  uint32_t len;    // arcs in the chunk (<= kRecChunk)
+};
+
+constexpr uint32_t kRecChunk = 256;
+
 struct RecoverView {
   DevGraphView g;
   const uint8_t* H;
   int32_t TP;
   int32_t T;            // keywords per result (instances per result)
   int32_t marginal;     // 0: start at the central node; 1: start at V_C nodes at distance D_j
-  int32_t n_inst;
+  int32_t n_inst;            // launched instances: results x T
+  const int32_t* n_valid;    // device: results that exist (instances of later ones exit)
   const int32_t* sel_node;   // central node of CG r
   const int32_t* ranked;     // marginal: CG rank of result t
   const uint32_t* vc_off;
   const int32_t* vc_nodes;
   const uint8_t* dmin;       // [nsel][kMaxKw]
-  uint32_t* ht;              // [n_inst][hc]
-  int32_t* nl;               // [n_inst][nc]
-  uint32_t* al;              // [n_inst][ac]
-  uint32_t* cnt;             // [n_inst][2]: nodes, arcs
+  uint32_t* ht;              // [n_inst][hc] node hash set per instance
+  int32_t* nl;               // [n_inst][nc] recovered nodes
+  uint32_t* al;              // [n_inst][ac] recovered arcs (CSR position of n -> q)
+  uint32_t* cnt;             // [n_inst][2] node / arc counters (may exceed capacity: overflow)
   uint32_t hc, nc, ac;
+  RecItem* items;            // [max_layer + 1][lcap] work chunks per layer
+  uint32_t* lcnt;            // [max_layer + 1]
+  uint32_t lcap;
+  int32_t max_layer;
   Status* gst;
 };
 
@@ -100,7 +138,8 @@ struct FinalizeView {
   DevGraphView g;
   int32_t T;                 // instances per result
   int32_t marginal;          // 1: merge the CG lists of ranked[t] first
-  int32_t n_res;
+  int32_t n_res;             // launched workgroups
+  const int32_t* n_valid;    // device: results that exist
   const int32_t* sel_node;
   const int32_t* ranked;
   const int32_t* nl;
@@ -151,11 +190,14 @@ __device__ inline uint32_t row_of(const uint32_t* row_ptr, int32_t n, uint32_t e
   return (uint32_t)upper_index<uint32_t>(row_ptr, 0, n + 1, e);
 }
 
-void launch_pack_vc(const uint32_t* vc_cnt, const int32_t* vc_tmp, uint32_t cg_ncap, int32_t nsel,
+void launch_pack_vc(const uint32_t* vc_cnt, const int32_t* vc_tmp, uint32_t cg_ncap, const int32_t* nsel,
                     uint32_t* vc_off, int32_t* vc_nodes, hipStream_t s);
-void launch_check_and_count(const DevGraphView& g, uint32_t* c_tmp, Status* st, hipStream_t s);
+void launch_check_and_count(const DevGraphView& g, uint32_t* c_tmp, int32_t* arc_src, Status* st,
+                            hipStream_t s);
 void launch_act_edge(const DevGraphView& g, const uint32_t* c_tmp, const Status* st, double abar,
                      double alpha, uint8_t* act, hipStream_t s);
+void launch_sort_rows(const DevGraphView& g, int32_t* col_s, uint8_t* act_s, uint32_t* eid_s,
+                      uint8_t* row_amax, uint32_t* bnd, int32_t nbnd, hipStream_t s);
 void launch_act_node(const DevGraphView& g, const uint8_t* nw, Status* st, double abar,
                      double alpha, uint8_t* act_node, uint8_t* act, hipStream_t s);
 
@@ -166,10 +208,9 @@ void launch_front_control(const RunView& r, int TP, int level, hipStream_t s);
 void launch_front_write(const RunView& r, int TP, const DevGraphView& g, int level, hipStream_t s);
 void launch_expand(const RunView& r, int TP, const DevGraphView& g, int level, int grid,
                    hipStream_t s);
-void launch_count_writes(const RunView& r, int TP, int32_t n, hipStream_t s);
 void launch_select(const SelectView& v, hipStream_t s);
 void launch_rank(const RankView& v, hipStream_t s);
-void launch_recover(const RecoverView& v, hipStream_t s);
+void launch_recover(const RecoverView& v, hipStream_t s);   // all layers of one phase
 void launch_finalize(const FinalizeView& v, hipStream_t s);
 
 }  // namespace raks

@@ -1,20 +1,26 @@
 // recover.hip -- recovering phase (Section 4.3, Algorithm 2, Lemma 1) on the
 // GPU, and the per-result union / sort / unique of the recovered subgraphs.
 //
-// One workgroup recovers one (result, keyword) instance: a backward search
-// from the start nodes over in-arcs n -> q (the reverses of q's arcs on the
-// bi-directed graph), keeping (n, e_nq) when h_q = 1 + max(a_nq, h_n) and
-// continuing from n unless h_n = 0.  Along a recovered arc h strictly drops,
-// so the search runs layer by layer from the largest level down to 1; every
-// node of a layer is discovered before its layer is processed.  A hash set in
-// global memory (open addressing) keeps each node once per instance; a
-// node's arcs are spread over the 256 lanes by a prefix sum over degrees.
-// Capacities are fixed per launch; running out sets a flag and the host
-// repeats the phase with larger buffers.
+// Every (result, keyword) instance of a phase is recovered at once: a
+// backward search from the start nodes over in-arcs n -> q (the reverses of
+// q's arcs on the bi-directed graph) keeps (n, e_nq) when
+// h_q = 1 + max(a_nq, h_n) and continues from n unless h_n = 0.  Along a
+// recovered arc h strictly drops, so the search runs layer by layer, h from
+// the largest level down to 1, one launch per layer: every node of layer h is
+// discovered while layers above h run.  A node's arcs are cut into chunks of
+// at most 256 that go to the work list of its layer; one wavefront takes a
+// chunk, so a hub's arcs spread over the whole GPU.  Only arcs of level below
+// the layer can qualify; they are a prefix of the node's level-sorted row, so
+// a hub whose arcs all have high levels costs nothing.  Each
+// instance has a hash set of nodes in global memory (open addressing), a node
+// list and an arc list; capacities are fixed per launch and running out sets
+// a flag on which the host repeats the phase with larger buffers.
 #include "common.h"
 #include "kernels.h"
 
 namespace raks {
+
+constexpr uint32_t kLdsSort = 4096;   // lists up to this size are sorted in LDS
 
 __device__ inline bool ht_insert(uint32_t* ht, uint32_t hc, uint32_t key, int* full) {
   uint32_t h = (key * 2654435761u) & (hc - 1);
@@ -28,100 +34,100 @@ __device__ inline bool ht_insert(uint32_t* ht, uint32_t hc, uint32_t key, int* f
   return false;
 }
 
+// Node n (hitting level hn in this instance's column) is recovered: record
+// it once per instance and queue its arcs on layer hn.
+__device__ inline void rec_discover(const RecoverView& v, uint32_t inst, int32_t n, uint32_t hn) {
+  int full = 0;
+  if (ht_insert(v.ht + (size_t)inst * v.hc, v.hc, (uint32_t)n, &full)) {
+    const uint32_t slot = atomicAdd(&v.cnt[inst * 2], 1u);
+    if (slot < v.nc) v.nl[(size_t)inst * v.nc + slot] = n;
+    else atomicOr(&v.gst->overflow, 1);
+    if (hn >= 1 && (int)hn <= v.max_layer) {
+      // in-arcs m -> n that can meet h_n = 1 + max(a, h_m) have a <= h_n - 1:
+      // a prefix of n's level-sorted row (EDGE), or all arcs when the node's
+      // own level is below h_n (NODE: every in-arc of n has the level of n)
+      const uint32_t rs = v.g.row_ptr[n];
+      const uint32_t deg = v.g.mode ? ((uint32_t)v.g.act_node[n] < hn ? v.g.row_ptr[n + 1] - rs : 0u)
+                                    : count_le(v.g, n, (int)hn - 1);
+      const uint32_t k = (deg + kRecChunk - 1) / kRecChunk;
+      if (k > 0) {
+        const uint32_t base = atomicAdd(&v.lcnt[hn], k);
+        if (base + k > v.lcap) {
+          atomicOr(&v.gst->overflow, 1);
+        } else {
+          RecItem* dst = v.items + (size_t)hn * v.lcap + base;
+          for (uint32_t c = 0; c < k; ++c) {
+            RecItem it;
+            it.inst = inst;
+            it.q = n;
+            it.start = rs + c * kRecChunk;
+            it.len = min(kRecChunk, deg - c * kRecChunk);
+            dst[c] = it;
+          }
+        }
+      }
+    }
+  }
+  if (full) atomicOr(&v.gst->overflow, 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_rec_clear(RecoverView v) {
+  const size_t live = (size_t)min(v.n_inst, *v.n_valid * v.T);
+  const size_t total = live * v.hc;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += stride) v.ht[i] = kEmpty;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < 2 * (size_t)v.n_inst; i += stride) v.cnt[i] = 0;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i <= (size_t)v.max_layer; i += stride) v.lcnt[i] = 0;
+}
+
+// Start nodes: the central node (central graphs), or the V_C nodes whose
+// level for the marginal keyword equals D_j (radial pattern graphs).
 template <int TP>
-__global__ __launch_bounds__(kBlock) void k_recover(RecoverView v) {
-  const int inst = blockIdx.x;
+__global__ __launch_bounds__(kBlock) void k_rec_seed(RecoverView v) {
+  const uint32_t inst = blockIdx.x;
   const int res = inst / v.T, col = inst % v.T;
-  uint32_t* ht = v.ht + (size_t)inst * v.hc;
-  int32_t* nl = v.nl + (size_t)inst * v.nc;
-  uint32_t* al = v.al + (size_t)inst * v.ac;
-  const uint8_t* H = v.H;
-  const DevGraphView& g = v.g;
-  __shared__ uint32_t s_nn, s_na;
-  __shared__ int s_over, s_hmax;
-  __shared__ int32_t s_q[kBlock];
-  __shared__ uint32_t s_off[kBlock], s_rs[kBlock];
-  __shared__ uint32_t s_scan[kBlock / kWave + 1];
-
-  for (uint32_t i = threadIdx.x; i < v.hc; i += kBlock) ht[i] = kEmpty;
-  if (threadIdx.x == 0) { s_nn = 0; s_na = 0; s_over = 0; s_hmax = 0; }
-  __syncthreads();
-
-  // start nodes
+  if (res >= *v.n_valid) return;
   if (!v.marginal) {
     if (threadIdx.x == 0) {
       const int32_t c = v.sel_node[res];
-      int full = 0;
-      ht_insert(ht, v.hc, (uint32_t)c, &full);
-      nl[0] = c;
-      s_nn = 1;
-      s_hmax = H[(int64_t)c * TP + col];
+      rec_discover(v, inst, c, v.H[(int64_t)c * TP + col]);
     }
   } else {
     const int r = v.ranked[res];
     const uint8_t d = v.dmin[r * kMaxKw + col];
     for (uint32_t p = v.vc_off[r] + threadIdx.x; p < v.vc_off[r + 1]; p += kBlock) {
       const int32_t x = v.vc_nodes[p];
-      if (H[(int64_t)x * TP + col] != d) continue;
-      int full = 0;
-      if (ht_insert(ht, v.hc, (uint32_t)x, &full)) {
-        const uint32_t slot = atomicAdd(&s_nn, 1u);
-        if (slot < v.nc) nl[slot] = x; else s_over = 1;
-      }
-      if (full) s_over = 1;
+      if (v.H[(int64_t)x * TP + col] == d) rec_discover(v, inst, x, d);
     }
-    if (threadIdx.x == 0) s_hmax = d;
   }
-  __syncthreads();
+}
 
-  for (int h = s_hmax; h >= 1 && !s_over; --h) {
-    const uint32_t total = min(s_nn, v.nc);
-    for (uint32_t c0 = 0; c0 < total; c0 += kBlock) {
-      const uint32_t idx = c0 + threadIdx.x;
-      int32_t q = -1;
-      uint32_t deg = 0, rs = 0;
-      if (idx < total) {
-        q = nl[idx];
-        if (H[(int64_t)q * TP + col] == h) {
-          rs = g.row_ptr[q];
-          deg = g.row_ptr[q + 1] - rs;
-        }
-      }
-      uint32_t tot;
-      const uint32_t ex = block_exclusive_scan<uint32_t, kBlock>(deg, s_scan, &tot);
-      s_q[threadIdx.x] = q;
-      s_off[threadIdx.x] = ex;
-      s_rs[threadIdx.x] = rs;
-      __syncthreads();
-      for (uint32_t k = threadIdx.x; k < tot; k += kBlock) {
-        const int j = upper_index<uint32_t>(s_off, 0, kBlock, k);
-        const int32_t qq = s_q[j];
-        const uint32_t e = s_rs[j] + (k - s_off[j]);
-        const int32_t n = g.col[e];
-        const uint32_t a = g.mode ? g.act_node[qq] : g.act[e];   // level of the in-arc n -> qq
-        const uint32_t hn = H[(int64_t)n * TP + col];
-        if ((uint32_t)h == 1u + (a > hn ? a : hn)) {
-          const uint32_t fwd = find_arc_dev(g.row_ptr, g.col, g.label, n, g.label[e], qq);
-          const uint32_t sa = atomicAdd(&s_na, 1u);
-          if (sa < v.ac) al[sa] = fwd; else s_over = 1;
-          int full = 0;
-          if (ht_insert(ht, v.hc, (uint32_t)n, &full)) {
-            const uint32_t sn = atomicAdd(&s_nn, 1u);
-            if (sn < v.nc) nl[sn] = n; else s_over = 1;
-          }
-          if (full) s_over = 1;
-        }
-      }
-      __syncthreads();
-      if (s_over) break;
+template <int TP>
+__global__ __launch_bounds__(kBlock) void k_rec_layer(RecoverView v, int h) {
+  const uint32_t n_items = min(v.lcnt[h], v.lcap);
+  const uint32_t waves = gridDim.x * (kBlock / kWave);
+  const int lane = lane_id();
+  const RecItem* list = v.items + (size_t)h * v.lcap;
+  const DevGraphView& g = v.g;
+  for (uint32_t it = blockIdx.x * (kBlock / kWave) + wave_id(); it < n_items; it += waves) {
+    const RecItem item = list[it];
+    const int col = item.inst % v.T;
+    const int32_t q = item.q;
+    const uint32_t aq = g.mode ? g.act_node[q] : 0u;   // NODE mode: level of the in-arc's target q
+    for (uint32_t k = lane; k < item.len; k += kWave) {
+      const uint32_t e = item.start + k;                   // position in q's level-sorted row
+      const uint32_t a = g.mode ? aq : g.act_s[e];         // EDGE: level of q -> n = level of n -> q
+      if (a >= (uint32_t)h) continue;
+      const int32_t n = g.col_s[e];
+      const uint32_t hn = v.H[(int64_t)n * TP + col];
+      if (hn >= (uint32_t)h) continue;
+      if (a + 1 != (uint32_t)h && hn + 1 != (uint32_t)h) continue;   // h = 1 + max(a, h_n)
+      const uint32_t fwd = find_arc_dev(g.row_ptr, g.col, g.label, n, g.label[g.eid_s[e]], q);
+      const uint32_t sa = atomicAdd(&v.cnt[item.inst * 2 + 1], 1u);
+      if (sa < v.ac) v.al[(size_t)item.inst * v.ac + sa] = fwd;
+      else atomicOr(&v.gst->overflow, 1);
+      rec_discover(v, item.inst, n, hn);
     }
-    __syncthreads();
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    v.cnt[inst * 2] = min(s_nn, v.nc);
-    v.cnt[inst * 2 + 1] = min(s_na, v.ac);
-    if (s_over) atomicOr(&v.gst->overflow, 1);
   }
 }
 
@@ -131,17 +137,25 @@ __global__ __launch_bounds__(kBlock) void k_recover(RecoverView v) {
 // output arena with their header; arcs are written as (src, dst, label).
 __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeView v) {
   const int t = blockIdx.x;
+  if (t >= *v.n_valid) return;
   __shared__ RadixLds lds;
-  __shared__ uint32_t s_n, s_off;
-  uint32_t* A = v.sort_a + (size_t)t * v.scap;
-  uint32_t* B = v.sort_b + (size_t)t * v.scap;
+  __shared__ uint32_t s_off;
+  __shared__ uint32_t s_sa[kLdsSort], s_sb[kLdsSort];
+  uint32_t* A_g = v.sort_a + (size_t)t * v.scap;
+  uint32_t* B_g = v.sort_b + (size_t)t * v.scap;
   const int r = v.marginal ? v.ranked[t] : t;
   const DevGraphView& g = v.g;
 
   for (int pass = 0; pass < 2; ++pass) {   // 0: nodes, 1: arcs
-    if (threadIdx.x == 0) s_n = 0;
+    // total input size first: small lists are sorted in LDS
+    uint32_t n = v.marginal ? v.cg_cnt[r * 2 + pass] : 0u;
+    for (int j = 0; j < v.T; ++j)
+      n += min(v.cnt[(t * v.T + j) * 2 + pass], pass == 0 ? v.nc : v.ac);
+    const bool small = n <= kLdsSort;
+    uint32_t* A = small ? s_sa : A_g;
+    uint32_t* B = small ? s_sb : B_g;
     __syncthreads();
-    uint32_t n = 0;
+    n = 0;
     if (v.marginal) {
       const uint32_t cnt = v.cg_cnt[r * 2 + pass];
       const uint32_t* src = pass == 0 ? v.cg_nodes + (size_t)r * v.cg_ncap
@@ -151,7 +165,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeView v) {
     }
     for (int j = 0; j < v.T; ++j) {
       const int inst = t * v.T + j;
-      const uint32_t cnt = v.cnt[inst * 2 + pass];
+      const uint32_t cnt = min(v.cnt[inst * 2 + pass], pass == 0 ? v.nc : v.ac);
       if (pass == 0) {
         const int32_t* src = v.nl + (size_t)inst * v.nc;
         for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) A[n + i] = (uint32_t)src[i];
@@ -219,7 +233,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeView v) {
           for (uint32_t i = threadIdx.x; i < m; i += kBlock) {
             const uint32_t e = uniq[i];
             int32_t* o = v.out_arcs + 3 * (size_t)(off + i);
-            o[0] = (int32_t)row_of(g.row_ptr, g.n, e);
+            o[0] = g.arc_src[e];
             o[1] = g.col[e];
             o[2] = g.label[e];
           }
@@ -231,9 +245,10 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeView v) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_pack_vc(const uint32_t* vc_cnt, const int32_t* vc_tmp,
-                                                    uint32_t cg_ncap, int32_t nsel,
+                                                    uint32_t cg_ncap, const int32_t* nsel_p,
                                                     uint32_t* vc_off, int32_t* vc_nodes) {
   __shared__ uint32_t s_off[kMaxW + 1];
+  const int nsel = *nsel_p;
   if (threadIdx.x == 0) {
     uint32_t acc = 0;
     for (int r = 0; r < nsel; ++r) { s_off[r] = acc; acc += vc_cnt[r]; }
@@ -249,10 +264,23 @@ __global__ __launch_bounds__(kBlock) void k_pack_vc(const uint32_t* vc_cnt, cons
 
 void launch_recover(const RecoverView& v, hipStream_t s) {
   if (v.n_inst <= 0) return;
+  const size_t clear_items = (size_t)v.n_inst * v.hc;
+  const unsigned gc = (unsigned)std::min<size_t>(2048, (clear_items + kBlock - 1) / kBlock + 1);
+  k_rec_clear<<<gc, kBlock, 0, s>>>(v);
+  const unsigned grid = 1024;
   switch (v.TP) {
-    case 4: k_recover<4><<<v.n_inst, kBlock, 0, s>>>(v); break;
-    case 8: k_recover<8><<<v.n_inst, kBlock, 0, s>>>(v); break;
-    default: k_recover<16><<<v.n_inst, kBlock, 0, s>>>(v); break;
+    case 4:
+      k_rec_seed<4><<<v.n_inst, kBlock, 0, s>>>(v);
+      for (int h = v.max_layer; h >= 1; --h) k_rec_layer<4><<<grid, kBlock, 0, s>>>(v, h);
+      break;
+    case 8:
+      k_rec_seed<8><<<v.n_inst, kBlock, 0, s>>>(v);
+      for (int h = v.max_layer; h >= 1; --h) k_rec_layer<8><<<grid, kBlock, 0, s>>>(v, h);
+      break;
+    default:
+      k_rec_seed<16><<<v.n_inst, kBlock, 0, s>>>(v);
+      for (int h = v.max_layer; h >= 1; --h) k_rec_layer<16><<<grid, kBlock, 0, s>>>(v, h);
+      break;
   }
 }
 
@@ -260,7 +288,7 @@ void launch_finalize(const FinalizeView& v, hipStream_t s) {
   if (v.n_res > 0) k_finalize<<<v.n_res, kBlock, 0, s>>>(v);
 }
 
-void launch_pack_vc(const uint32_t* vc_cnt, const int32_t* vc_tmp, uint32_t cg_ncap, int32_t nsel,
+void launch_pack_vc(const uint32_t* vc_cnt, const int32_t* vc_tmp, uint32_t cg_ncap, const int32_t* nsel,
                     uint32_t* vc_off, int32_t* vc_nodes, hipStream_t s) {
   k_pack_vc<<<1, kBlock, 0, s>>>(vc_cnt, vc_tmp, cg_ncap, nsel, vc_off, vc_nodes);
 }
