@@ -42,8 +42,8 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         src = os.path.join(_HERE, "synth.c")
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
-                               "-o", tmp, src, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared",
+                               "-ffp-contract=off", "-o", tmp, src, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 

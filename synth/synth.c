@@ -34,6 +34,11 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define N_CHUNKS 256   /* fixed random-stream chunks: output independent of thread count */
 
 /* ---------------------------------------------------------------- RNG --- */
 /* xoshiro256** 1.0 and splitmix64, as published by Blackman and Vigna. */
@@ -116,25 +121,52 @@ static void alias_free(alias_t* a) { free(a->prob); free(a->alias); }
 
 /* --------------------------------------------------------- radix sort --- */
 /* LSD radix sort of 64-bit keys, 8-bit digits; passes whose digit is
- * constant over all keys are skipped. */
+ * constant over all keys are skipped.  Parallel and stable: every thread
+ * counts its contiguous slice, offsets are laid out digit-major then by
+ * thread, and every thread scatters its slice in order, so the result does
+ * not depend on the thread count. */
 static int radix_sort_u64(uint64_t* keys, int64_t n, int key_bits) {
     if (n <= 1) return 0;
     uint64_t* tmp = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n);
     if (!tmp) return -1;
+    int nt = 1;
+#ifdef _OPENMP
+    nt = omp_get_max_threads();
+    if (nt > 64) nt = 64;
+#endif
+    int64_t (*cnt)[256] = (int64_t(*)[256])calloc((size_t)nt, sizeof(int64_t[256]));
+    if (!cnt) { free(tmp); return -1; }
     uint64_t* src = keys; uint64_t* dst = tmp;
     for (int shift = 0; shift < key_bits; shift += 8) {
-        int64_t cnt[256];
-        memset(cnt, 0, sizeof(cnt));
-        for (int64_t i = 0; i < n; ++i) cnt[(src[i] >> shift) & 0xff]++;
         int trivial = 0;
-        for (int d = 0; d < 256; ++d) if (cnt[d] == n) trivial = 1;
+#pragma omp parallel num_threads(nt)
+        {
+            int t = 0;
+#ifdef _OPENMP
+            t = omp_get_thread_num();
+#endif
+            const int64_t lo = n * t / nt, hi = n * (t + 1) / nt;
+            memset(cnt[t], 0, sizeof(cnt[t]));
+            for (int64_t i = lo; i < hi; ++i) cnt[t][(src[i] >> shift) & 0xff]++;
+#pragma omp barrier
+#pragma omp single
+            {
+                int64_t tot[256] = {0};
+                for (int d = 0; d < 256; ++d)
+                    for (int u = 0; u < nt; ++u) tot[d] += cnt[u][d];
+                for (int d = 0; d < 256; ++d) if (tot[d] == n) trivial = 1;
+                int64_t off = 0;
+                for (int d = 0; d < 256; ++d)
+                    for (int u = 0; u < nt; ++u) { int64_t c = cnt[u][d]; cnt[u][d] = off; off += c; }
+            }
+            if (!trivial)
+                for (int64_t i = lo; i < hi; ++i) dst[cnt[t][(src[i] >> shift) & 0xff]++] = src[i];
+        }
         if (trivial) continue;
-        int64_t off = 0;
-        for (int d = 0; d < 256; ++d) { int64_t c = cnt[d]; cnt[d] = off; off += c; }
-        for (int64_t i = 0; i < n; ++i) dst[cnt[(src[i] >> shift) & 0xff]++] = src[i];
         uint64_t* t = src; src = dst; dst = t;
     }
     if (src != keys) memcpy(keys, src, sizeof(uint64_t) * (size_t)n);
+    free(cnt);
     free(tmp);
     return 0;
 }
@@ -187,35 +219,44 @@ void synth_free(synth_graph* g) {
 
 static int64_t estimate_abar_x100(const synth_graph* g, const synth_params* p) {
     const int64_t n = g->n_nodes;
-    int32_t* dist = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
-    int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
-    if (!dist || !queue) { free(dist); free(queue); return -1; }
+    const int S = p->abar_sources;
+    /* roots first (sequential draws), then one BFS per root in parallel */
+    int64_t* roots = (int64_t*)malloc(sizeof(int64_t) * (size_t)(S > 0 ? S : 1));
+    if (!roots) return -1;
     rng_t r; rng_seed(&r, p->seed, 7);
-    int64_t hop_sum = 0, pairs = 0;
-    int tries = 0;
-    for (int s = 0; s < p->abar_sources && tries < 100000; ) {
-        ++tries;
+    int got = 0;
+    for (int tries = 0; got < S && tries < 1000000; ++tries) {
         int64_t src = (int64_t)rng_below(&r, (uint64_t)n);
         if (g->row_ptr[src + 1] == g->row_ptr[src]) continue;
-        for (int64_t i = 0; i < n; ++i) dist[i] = -1;
-        int64_t qh = 0, qt = 0;
-        dist[src] = 0; queue[qt++] = (int32_t)src;
-        while (qh < qt) {
-            int32_t u = queue[qh++];
-            for (int64_t e = g->row_ptr[u]; e < g->row_ptr[u + 1]; ++e) {
-                int32_t v = g->col[e];
-                if (dist[v] < 0) { dist[v] = dist[u] + 1; queue[qt++] = v; }
-            }
-        }
-        if (qt <= 1) continue;
-        for (int t = 0; t < p->abar_targets; ++t) {
-            int64_t idx = 1 + (int64_t)rng_below(&r, (uint64_t)(qt - 1));
-            hop_sum += dist[queue[idx]];
-            ++pairs;
-        }
-        ++s;
+        roots[got++] = src;
     }
-    free(dist); free(queue);
+    int64_t hop_sum = 0, pairs = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : hop_sum, pairs)
+    for (int s = 0; s < got; ++s) {
+        int32_t* dist = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+        int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+        if (dist && queue) {
+            for (int64_t i = 0; i < n; ++i) dist[i] = -1;
+            int64_t qh = 0, qt = 0;
+            dist[roots[s]] = 0; queue[qt++] = (int32_t)roots[s];
+            while (qh < qt) {
+                int32_t u = queue[qh++];
+                for (int64_t e = g->row_ptr[u]; e < g->row_ptr[u + 1]; ++e) {
+                    int32_t v = g->col[e];
+                    if (dist[v] < 0) { dist[v] = dist[u] + 1; queue[qt++] = v; }
+                }
+            }
+            rng_t rt; rng_seed(&rt, p->seed, 1000 + (uint64_t)s);
+            if (qt > 1)
+                for (int t = 0; t < p->abar_targets; ++t) {
+                    int64_t idx = 1 + (int64_t)rng_below(&rt, (uint64_t)(qt - 1));
+                    hop_sum += dist[queue[idx]];
+                    ++pairs;
+                }
+        }
+        free(dist); free(queue);
+    }
+    free(roots);
     if (pairs == 0) return -1;
     double mean = (double)hop_sum / (double)pairs;
     return (int64_t)floor(mean * 100.0 + 0.5);
@@ -294,12 +335,21 @@ synth_graph* synth_generate(const synth_params* p) {
             }
         }
         for (int iter = 0; ; ++iter) {
-            while (m < E) {
-                int64_t s = alias_draw(&src_al, &r), t = alias_draw(&dst_al, &r);
-                if (s == t) continue;
-                uint64_t l = rng_below(&r, (uint64_t)p->n_labels);
-                keys[m++] = ((uint64_t)s << sh_s) | (l << sh_l) | (uint64_t)t;
+            /* draw the missing E - m edges in N_CHUNKS independent streams */
+            const int64_t need = E - m, base = m;
+#pragma omp parallel for schedule(static)
+            for (int c = 0; c < N_CHUNKS; ++c) {
+                rng_t rc; rng_seed(&rc, p->seed, 100000 + (uint64_t)iter * N_CHUNKS + (uint64_t)c);
+                const int64_t lo = need * c / N_CHUNKS, hi = need * (c + 1) / N_CHUNKS;
+                for (int64_t i = lo; i < hi; ) {
+                    int64_t s0 = alias_draw(&src_al, &rc), t0 = alias_draw(&dst_al, &rc);
+                    if (s0 == t0) continue;
+                    uint64_t l = rng_below(&rc, (uint64_t)p->n_labels);
+                    keys[base + i] = ((uint64_t)s0 << sh_s) | (l << sh_l) | (uint64_t)t0;
+                    ++i;
+                }
             }
+            m = E;
             if (radix_sort_u64(keys, m, 2 * nb + lb)) goto fail;
             m = unique_sorted_u64(keys, m);
             if (m == E || iter > 1000) break;
