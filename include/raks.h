@@ -8,7 +8,9 @@
  * call on the calling thread.  All pointers in descriptors are HOST pointers
  * unless stated otherwise; the library copies what it needs before returning
  * and never keeps a caller pointer.  One context owns one graph and its device
- * state on one GPU; calls on one context must come from one thread at a time.
+ * state on one GPU.  Calls on one context must come from one thread at a
+ * time, except raks_submit / raks_poll / raks_wait, which any thread may call
+ * while serving runs.
  *
  * The arithmetic is integer once the activation levels are set; every result
  * is bit-for-bit deterministic.
@@ -59,11 +61,20 @@ typedef struct {
     raks_free_fn free;
     void* alloc_user;
     uint64_t mem_budget;    /* bytes of device memory the context may hold; 0 = no limit */
+    int32_t lanes;          /* query lanes, 0..32 (0 = 1); see raks_query_batch */
+    /* Initial recovery capacities per (result, keyword) instance (Algorithm 2):
+     * recovered nodes, recovered arcs, and work chunks of 256 arcs per layer
+     * (0 = 4096, 16384, 65536).  An instance that needs more is grown and its
+     * phase repeated, so these only trade memory against repeats. */
+    uint32_t rec_nodes, rec_arcs, rec_chunks;
 } raks_ctx_opts;
 
 /* Creates a context on opts->device (opts may be NULL: device 0, own stream,
- * hipMalloc).  Fails with RAKS_EDEVICE when the device is not gfx950.
- * *out is owned by the caller until raks_destroy. */
+ * hipMalloc, one lane).  A lane is one query's device workspace with its own
+ * stream (lane 0 uses opts->stream when given); lanes let the queries of a
+ * batch or of the serving loop run on the device at the same time.  Fails
+ * with RAKS_EDEVICE when the device is not gfx950.  *out is owned by the
+ * caller until raks_destroy. */
 int raks_create(raks_ctx** out, const raks_ctx_opts* opts);
 
 /* Frees every device and host resource of the context (NULL-safe). */
@@ -160,7 +171,9 @@ typedef struct {
     int64_t gate_pass[2];    /* scanned arcs whose level allowed expansion */
     int64_t h_writes[2];     /* node-keyword matrix entries written */
     int32_t n_cg;            /* central graphs identified by the central run */
-    double device_ms;        /* wall time of the query on the device stream */
+    double device_ms;        /* wall time of the query on its device stream */
+    double host_ms;          /* call (or submission) to results ready, host clock */
+    double queue_ms;         /* submission to start on a lane (serving; 0 otherwise) */
 } raks_query_stats;
 
 typedef struct {
@@ -175,9 +188,42 @@ typedef struct {
  * returns its results.  *out is library-owned until raks_results_free. */
 int raks_query(raks_ctx* ctx, const raks_query_desc* q, raks_results** out);
 
-/* Runs n queries; outs[i] receives the results of qs[i] (each owned
- * independently).  On error no output is left allocated. */
+/* Runs n queries on the context's lanes at once (each lane takes the next
+ * query when its previous one is done); outs[i] receives the results of
+ * qs[i], identical to those of raks_query(qs[i]), each owned independently.
+ * On error no output is left allocated. */
 int raks_query_batch(raks_ctx* ctx, const raks_query_desc* qs, int32_t n, raks_results** outs);
+
+/* Serving: a worker thread per lane runs submitted queries in arrival order
+ * as lanes become free (continuous admission; results as raks_query gives
+ * them).  While serving runs, raks_query / raks_query_batch / raks_load_graph
+ * / raks_set_alpha return RAKS_ESTATE. */
+typedef struct {
+    int32_t lanes;      /* 0 = as many as half of the free device memory holds, at most 8 */
+    int32_t queue_cap;  /* waiting queries allowed, 0 = unbounded */
+} raks_serve_opts;
+
+/* Starts serving (opts may be NULL).  RAKS_ESTATE without a graph or when
+ * serving already runs. */
+int raks_serve_start(raks_ctx* ctx, const raks_serve_opts* opts);
+
+/* Queues a query (its arrays are copied) and returns its ticket.  RAKS_EAGAIN
+ * when the queue is full; the query is validated when it runs, so invalid
+ * queries fail at raks_poll / raks_wait. */
+int raks_submit(raks_ctx* ctx, const raks_query_desc* q, uint64_t* ticket);
+
+/* Takes the results of a finished query: RAKS_EAGAIN while it still runs
+ * (the ticket stays valid), the query's own error code if it failed, and
+ * RAKS_EINVAL for an unknown or already taken ticket.  *out is owned by the
+ * caller (raks_results_free). */
+int raks_poll(raks_ctx* ctx, uint64_t ticket, raks_results** out);
+
+/* As raks_poll, but blocks until the query has finished. */
+int raks_wait(raks_ctx* ctx, uint64_t ticket, raks_results** out);
+
+/* Stops serving after every submitted query has run; results not taken are
+ * freed.  Also done by raks_destroy. */
+int raks_serve_stop(raks_ctx* ctx);
 
 /* Frees results (NULL-safe). */
 void raks_results_free(raks_results* r);
@@ -191,9 +237,11 @@ typedef struct {
     double bytes;            /* algorithmic bytes moved (expansion only) */
 } raks_kernel_timing;
 
-/* Enables (1) or disables (0) per-launch event timing; enabling resets the
- * accumulators. */
-int raks_set_timing(raks_ctx* ctx, int32_t enable);
+/* Enables per-launch event timing for the kernel ids whose bit is set in
+ * `mask` (bit k = kernel id k; 0 disables, 31 records all); a non-zero mask
+ * resets the accumulators.  Each timed launch is bracketed by two events on
+ * its lane's stream.  RAKS_EINVAL for mask outside 0..31. */
+int raks_set_timing(raks_ctx* ctx, int32_t mask);
 int raks_get_timing(raks_ctx* ctx, int32_t kernel, raks_kernel_timing* out);
 
 /* Message of the last failing call on this thread ("" if none). */

@@ -25,7 +25,13 @@ _FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p
 
 class CtxOpts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("alloc", _ALLOC),
-                ("free", _FREE), ("alloc_user", ctypes.c_void_p), ("mem_budget", ctypes.c_uint64)]
+                ("free", _FREE), ("alloc_user", ctypes.c_void_p), ("mem_budget", ctypes.c_uint64),
+                ("lanes", ctypes.c_int32), ("rec_nodes", ctypes.c_uint32),
+                ("rec_arcs", ctypes.c_uint32), ("rec_chunks", ctypes.c_uint32)]
+
+
+class ServeOpts(ctypes.Structure):
+    _fields_ = [("lanes", ctypes.c_int32), ("queue_cap", ctypes.c_int32)]
 
 
 class GraphDesc(ctypes.Structure):
@@ -60,7 +66,8 @@ class QueryStats(ctypes.Structure):
                 ("frontier", ctypes.c_int64 * 2), ("e_arc", ctypes.c_int64 * 2),
                 ("e_alg", ctypes.c_int64 * 2), ("gate_pass", ctypes.c_int64 * 2),
                 ("h_writes", ctypes.c_int64 * 2), ("n_cg", ctypes.c_int32),
-                ("device_ms", ctypes.c_double)]
+                ("device_ms", ctypes.c_double), ("host_ms", ctypes.c_double),
+                ("queue_ms", ctypes.c_double)]
 
 
 class Results(ctypes.Structure):
@@ -99,6 +106,14 @@ def lib():
         L.raks_query_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(QueryDesc), ctypes.c_int32,
                                        ctypes.POINTER(ctypes.POINTER(Results))]
         L.raks_results_free.argtypes = [ctypes.POINTER(Results)]
+        L.raks_serve_start.argtypes = [ctypes.c_void_p, ctypes.POINTER(ServeOpts)]
+        L.raks_submit.argtypes = [ctypes.c_void_p, ctypes.POINTER(QueryDesc),
+                                  ctypes.POINTER(ctypes.c_uint64)]
+        L.raks_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64,
+                                ctypes.POINTER(ctypes.POINTER(Results))]
+        L.raks_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64,
+                                ctypes.POINTER(ctypes.POINTER(Results))]
+        L.raks_serve_stop.argtypes = [ctypes.c_void_p]
         L.raks_results_free.restype = None
         L.raks_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
         L.raks_get_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(KernelTiming)]
@@ -110,7 +125,9 @@ def lib():
 
 EXPORTED = ("raks_create", "raks_destroy", "raks_load_graph", "raks_set_alpha",
             "raks_get_activations", "raks_query", "raks_query_batch", "raks_results_free",
+            "raks_serve_start", "raks_submit", "raks_poll", "raks_wait", "raks_serve_stop",
             "raks_set_timing", "raks_get_timing", "raks_last_error", "raks_version")
+RAKS_EAGAIN = -5
 
 
 def _check(rc):
@@ -131,7 +148,8 @@ def _results_to_dict(res: Results, lean: bool = False) -> dict:
         d["end"] = END_NAMES.get(d["end_reason"], "?")
         stats.append(d)
     out = {"status": int(res.status), "n_cg": int(st.n_cg), "stats": stats, "results": [],
-           "device_ms": float(st.device_ms)}
+           "device_ms": float(st.device_ms), "host_ms": float(st.host_ms),
+           "queue_ms": float(st.queue_ms)}
     for i in range(res.n):
         r = res.r[i]
         nodes = (np.ctypeslib.as_array(r.nodes, shape=(r.n_nodes,)).copy() if r.n_nodes
@@ -151,11 +169,14 @@ def _results_to_dict(res: Results, lean: bool = False) -> dict:
 class Context:
     """One GPU context holding one graph (``raks_ctx``)."""
 
-    def __init__(self, device: int = 0, use_torch: bool = True, mem_budget: int = 0):
+    def __init__(self, device: int = 0, use_torch: bool = True, mem_budget: int = 0,
+                 lanes: int = 1, rec_caps=(0, 0, 0)):
         self._keep = []
         opts = CtxOpts()
         opts.device = device
         opts.mem_budget = mem_budget
+        opts.lanes = lanes
+        opts.rec_nodes, opts.rec_arcs, opts.rec_chunks = (int(x) for x in rec_caps)
         if use_torch:
             import torch
             if not torch.cuda.is_available():
@@ -236,22 +257,60 @@ class Context:
         finally:
             lib().raks_results_free(out)
 
-    def query_batch(self, qs) -> list:
+    def query_batch(self, qs, lean: bool = False) -> list:
+        """Runs the queries on the context's lanes at once."""
         keep = []
-        arr = (QueryDesc * len(qs))(*[self._desc(q, keep) for q in qs])
-        outs = (ctypes.POINTER(Results) * len(qs))()
-        _check(lib().raks_query_batch(self._h, arr, len(qs), outs))
+        n = len(qs)
+        arr = (QueryDesc * max(n, 1))(*[self._desc(q, keep) for q in qs])
+        outs = (ctypes.POINTER(Results) * max(n, 1))()
+        _check(lib().raks_query_batch(self._h, arr, n, outs))
         res = []
         try:
-            for o in outs:
-                res.append(_results_to_dict(o.contents))
+            for i in range(n):
+                res.append(_results_to_dict(outs[i].contents, lean))
         finally:
-            for o in outs:
-                lib().raks_results_free(o)
+            for i in range(n):
+                lib().raks_results_free(outs[i])
         return res
 
-    def set_timing(self, enable: bool):
-        _check(lib().raks_set_timing(self._h, int(enable)))
+    # ---- serving
+
+    def serve_start(self, lanes: int = 0, queue_cap: int = 0):
+        o = ServeOpts(lanes, queue_cap)
+        _check(lib().raks_serve_start(self._h, ctypes.byref(o)))
+
+    def submit(self, q) -> int:
+        keep = []
+        d = self._desc(q, keep)
+        t = ctypes.c_uint64()
+        _check(lib().raks_submit(self._h, ctypes.byref(d), ctypes.byref(t)))
+        return int(t.value)
+
+    def _take(self, fn, ticket: int, lean: bool):
+        out = ctypes.POINTER(Results)()
+        rc = fn(self._h, ctypes.c_uint64(ticket), ctypes.byref(out))
+        if rc == RAKS_EAGAIN:
+            return None
+        _check(rc)
+        try:
+            return _results_to_dict(out.contents, lean)
+        finally:
+            lib().raks_results_free(out)
+
+    def poll(self, ticket: int, lean: bool = False):
+        """Results of a finished query, or None while it runs."""
+        return self._take(lib().raks_poll, ticket, lean)
+
+    def wait(self, ticket: int, lean: bool = False) -> dict:
+        return self._take(lib().raks_wait, ticket, lean)
+
+    def serve_stop(self):
+        _check(lib().raks_serve_stop(self._h))
+
+    def set_timing(self, enable=True):
+        """True: time every kernel group; False: off; an int: mask of timer ids."""
+        mask = 0x1F if enable is True else (0 if enable is False else int(enable))
+        _check(lib().raks_set_timing(self._h, mask))
 
     def timing(self, kernel: int) -> dict:
         t = KernelTiming()

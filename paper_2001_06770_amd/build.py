@@ -16,7 +16,7 @@ HIPCC_FLAGS = [
     "-ffp-contract=off",
     # no packed fp32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wno-unused-command-line-argument",
+    "-Wno-unused-command-line-argument", "-pthread",
 ]
 
 

@@ -1,7 +1,7 @@
 // api.hip -- host runtime and C ABI of the RAKS gfx950 library.
 //
-// A query runs both runs of the unified framework (Section 4.1) on one HIP
-// stream:
+// A query runs both runs of the unified framework (Section 4.1) on one lane
+// (one HIP stream and one workspace):
 //   central run   level loop (scan / control / enqueue / expand) until >= w
 //                 CGs, the level bound or an empty frontier; top-w selection;
 //   recovery      Algorithm 2 for every (CG, central keyword); union, sort,
@@ -10,24 +10,27 @@
 //   ranking       Eq. 6 order, top-k;
 //   recovery      Algorithm 2 for every (RPG, marginal keyword) from the V_C
 //                 nodes at distance D_j; union with the CG; output.
-// Only the small per-level status (a few dozen bytes) and the final results
-// cross to the host.
+// Only the per-level status (a few dozen bytes) and the final results cross
+// to the host.  A context holds the graph once and one or more lanes; batches
+// and the serving loop run queries on several lanes at once, so the kernels
+// of different queries overlap on the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <climits>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <mutex>
 #include <string>
 #include <vector>
 
-#include "../../include/raks.h"
-#include "common.h"
-#include "kernels.h"
+#include "runtime.h"
 
 using namespace raks;
+
+struct raks_ctx : public raks::Ctx {};
 
 namespace {
 
@@ -45,82 +48,29 @@ int fail(int code, const std::string& msg) {
       return fail(RAKS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));   \
   } while (0)
 
-#define RAKS_TRY(expr)          \
-  do {                          \
-    int _rc = (expr);           \
+#define RAKS_TRY(expr)              \
+  do {                              \
+    int _rc = (expr);               \
     if (_rc != RAKS_OK) return _rc; \
   } while (0)
 
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-};
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
-constexpr int kTimers = 5;
-constexpr size_t kSpecNodes = 1 << 16;   // output read back with the headers
-constexpr size_t kSpecArcs = 1 << 16;
+// ------------------------------------------------------------- memory ---
 
-}  // namespace
-
-struct raks_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  raks_alloc_fn alloc = nullptr;
-  raks_free_fn free_fn = nullptr;
-  void* alloc_user = nullptr;
-  uint64_t budget = 0;
-  uint64_t in_use = 0;
-  int num_cu = 256;
-
-  // graph
-  bool loaded = false;
-  int32_t n = 0;
-  uint32_t A = 0;
-  int32_t vocab = 0;
-  int32_t mode = 0;
-  double abar = 0, alpha = 0;
-  DevBuf row_ptr, col, label, act, act_node, nw, kw_nodes, col_s, act_s, eid_s, row_amax, bnd, arc_src;
-  int32_t nbnd = 1;
-  std::vector<int64_t> kw_ptr;
-
-  // workspace
-  int32_t n_pad = 0, nblocks = 0;
-  DevBuf Hc, Hm, F, tot, off, q_off, q_rs, q_lo, q_mask, cand;
-  DevBuf sel_node, sel_sc, sel_sumh, has_rpg, sm, key, dmin, ranked;
-  DevBuf vc_cnt, vc_tmp, vc_off, vc_nodes;
-  DevBuf ht, nl, al, icnt, cg_nodes, cg_arcs, cg_cnt, sort_a, sort_b, items, lcnt;
-  DevBuf hdr, out_nodes, out_arcs;
-  DevBuf status;
-  Status* h_status = nullptr;   // pinned
-  RunStatus* h_run = nullptr;   // pinned [2]: per-level status, double-buffered
-  ResultHdr* h_hdr = nullptr;   // pinned [kMaxW]
-  int32_t* h_nodes = nullptr;   // pinned [kSpecNodes]
-  int32_t* h_arcs = nullptr;    // pinned [3 * kSpecArcs]
-  hipEvent_t lvl_ev[2] = {nullptr, nullptr};
-  uint32_t nc = 4096, ac = 16384;  // recovery capacities per instance
-  uint32_t lcap = 1u << 16;        // recovery work chunks per layer
-
-  // timing
-  bool timing = false;
-  raks_kernel_timing acc[kTimers] = {};
-  std::vector<hipEvent_t> ev_pool;
-  size_t ev_used = 0;
-  struct Pending { hipEvent_t a, b; int kind; double bytes; int level, run; };
-  std::vector<Pending> pending;
-  hipEvent_t q_start = nullptr, q_end = nullptr;
-};
-
-namespace {
-
-int dev_alloc(raks_ctx* c, DevBuf& b, size_t bytes) {
+// Device buffers grow on demand and are kept.  The context's allocator and
+// budget are shared by all lanes, so allocation is serialised.
+int dev_alloc(Ctx* c, DevBuf& b, size_t bytes) {
   if (b.bytes >= bytes && b.p) return RAKS_OK;
+  std::lock_guard<std::mutex> lk(c->mem_mu);
   if (b.p) {
     if (c->free_fn) c->free_fn(b.p, b.bytes, c->alloc_user);
     else (void)hipFree(b.p);
     c->in_use -= b.bytes;
-    b.p = nullptr;
-    b.bytes = 0;
+    b = DevBuf();
   }
   if (bytes == 0) bytes = 256;
   bytes = (bytes + 255) & ~size_t(255);
@@ -140,20 +90,18 @@ int dev_alloc(raks_ctx* c, DevBuf& b, size_t bytes) {
   return RAKS_OK;
 }
 
-void dev_free(raks_ctx* c, DevBuf& b) {
+void dev_free(Ctx* c, DevBuf& b) {
   if (!b.p) return;
+  std::lock_guard<std::mutex> lk(c->mem_mu);
   if (c->free_fn) c->free_fn(b.p, b.bytes, c->alloc_user);
   else (void)hipFree(b.p);
   c->in_use -= b.bytes;
   b = DevBuf();
 }
 
-template <typename T>
-T* P(DevBuf& b) { return reinterpret_cast<T*>(b.p); }
-
 int tp_for(int T) { return T <= 4 ? 4 : (T <= 8 ? 8 : 16); }
 
-DevGraphView graph_view(raks_ctx* c) {
+DevGraphView graph_view(Ctx* c) {
   DevGraphView g;
   g.n = c->n;
   g.A = c->A;
@@ -173,90 +121,162 @@ DevGraphView graph_view(raks_ctx* c) {
   return g;
 }
 
-// ------------------------------------------------------------ timing ---
-hipEvent_t next_event(raks_ctx* c) {
-  if (c->ev_used == c->ev_pool.size()) {
-    hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    c->ev_pool.push_back(e);
+// -------------------------------------------------------------- lanes ---
+
+void lane_destroy(Ctx* c, Lane* L) {
+  if (!L) return;
+  if (L->stream) (void)hipStreamSynchronize(L->stream);
+  DevBuf* bufs[] = {&L->Hc, &L->Hm, &L->F, &L->R, &L->tot, &L->off, &L->q_off, &L->q_rs,
+                    &L->q_lo, &L->q_mask, &L->cand, &L->sel_node, &L->sel_sc, &L->sel_sumh,
+                    &L->has_rpg, &L->sm, &L->key, &L->dmin, &L->ranked, &L->vc_cnt, &L->vc_tmp,
+                    &L->vc_off, &L->vc_nodes, &L->hpool, &L->nl, &L->al, &L->items, &L->sort_a,
+                    &L->sort_b, &L->cg_nodes, &L->cg_arcs, &L->cg_cnt, &L->hdr, &L->out_nodes,
+                    &L->out_arcs, &L->status};
+  for (RecPhase& P : L->ph) {
+    DevBuf* pb[] = {&P.layout, &P.cnt, &P.iflag, &P.lcnt};
+    for (DevBuf* b : pb) dev_free(c, *b);
+    if (P.stage) (void)hipHostFree(P.stage);
+    P.stage = nullptr;
   }
-  return c->ev_pool[c->ev_used++];
+  for (DevBuf* b : bufs) dev_free(c, *b);
+  for (hipEvent_t e : L->ev_pool) (void)hipEventDestroy(e);
+  L->ev_pool.clear();
+  for (hipEvent_t& e : L->lvl_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (L->q_start) (void)hipEventDestroy(L->q_start);
+  if (L->q_end) (void)hipEventDestroy(L->q_end);
+  if (L->h_status) (void)hipHostFree(L->h_status);
+  if (L->h_run) (void)hipHostFree(L->h_run);
+  if (L->h_hdr) (void)hipHostFree(L->h_hdr);
+  if (L->h_nodes) (void)hipHostFree(L->h_nodes);
+  if (L->h_arcs) (void)hipHostFree(L->h_arcs);
+  if (L->own_stream && L->stream) (void)hipStreamDestroy(L->stream);
+  L->stream = nullptr;
 }
 
+// Lane 0 runs on the caller's stream when one was given; every other lane
+// owns a non-blocking stream of default priority.
+int lane_create(Ctx* c, int id, Lane** out) {
+  std::unique_ptr<Lane> L(new Lane());
+  L->ctx = c;
+  L->id = id;
+  if (id == 0 && c->user_stream) {
+    L->stream = c->user_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking) != hipSuccess)
+      return fail(RAKS_EDEVICE, "hipStreamCreate failed");
+    L->own_stream = true;
+  }
+  if (hipHostMalloc((void**)&L->h_status, sizeof(Status), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&L->h_run, 2 * sizeof(RunStatus), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&L->h_hdr, kMaxW * sizeof(ResultHdr), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&L->h_nodes, kSpecNodes * 4, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&L->h_arcs, kSpecArcs * 12, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreate(&L->lvl_ev[0]) != hipSuccess || hipEventCreate(&L->lvl_ev[1]) != hipSuccess ||
+      hipEventCreate(&L->q_start) != hipSuccess || hipEventCreate(&L->q_end) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&L->d_run, L->h_run, 0) != hipSuccess) {
+    lane_destroy(c, L.get());
+    return fail(RAKS_EDEVICE, "lane pinned memory / event allocation failed");
+  }
+  const int rc = dev_alloc(c, L->status, sizeof(Status));
+  if (rc) {
+    lane_destroy(c, L.get());
+    return rc;
+  }
+  *out = L.release();
+  return RAKS_OK;
+}
+
+int ensure_lanes(Ctx* c, int n) {
+  n = std::min(n, kMaxLanes);
+  while ((int)c->lanes.size() < n) {
+    Lane* L = nullptr;
+    RAKS_TRY(lane_create(c, (int)c->lanes.size(), &L));
+    c->lanes.emplace_back(L);
+  }
+  return RAKS_OK;
+}
+
+// ------------------------------------------------------------- timing ---
+
+hipEvent_t next_event(Lane* L) {
+  if (L->ev_used == L->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    L->ev_pool.push_back(e);
+  }
+  return L->ev_pool[L->ev_used++];
+}
+
+// Brackets the launches of its scope with events on the lane's stream while
+// timing is enabled.
 struct Timed {
-  raks_ctx* c;
-  int kind;
-  double bytes;
-  int level, run;
+  Lane* L;
+  int kind, level, run;
   hipEvent_t a = nullptr;
-  Timed(raks_ctx* c_, int kind_, double bytes_ = 0, int level_ = -1, int run_ = -1)
-      : c(c_), kind(kind_), bytes(bytes_), level(level_), run(run_) {
-    if (c->timing) {
-      a = next_event(c);
-      if (a) (void)hipEventRecord(a, c->stream);
+  Timed(Lane* L_, int kind_, int level_ = -1, int run_ = -1)
+      : L(L_), kind(kind_), level(level_), run(run_) {
+    if ((L->ctx->timing.load() >> kind) & 1u) {
+      a = next_event(L);
+      if (a) (void)hipEventRecord(a, L->stream);
     }
   }
   ~Timed() {
-    if (c->timing && a) {
-      hipEvent_t b = next_event(c);
-      if (b) {
-        (void)hipEventRecord(b, c->stream);
-        c->pending.push_back({a, b, kind, bytes, level, run});
-      }
+    if (!a) return;
+    hipEvent_t b = next_event(L);
+    if (b) {
+      (void)hipEventRecord(b, L->stream);
+      L->pending.push_back({a, b, kind, 0.0, level, run});
     }
   }
 };
 
-void harvest_timing(raks_ctx* c) {
-  for (auto& p : c->pending) {
-    float ms = 0;
-    if (p.kind < 0) continue;
-    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-      c->acc[p.kind].launches += 1;
-      c->acc[p.kind].ms += ms;
-      c->acc[p.kind].bytes += p.bytes;
+void harvest_timing(Lane* L) {
+  Ctx* c = L->ctx;
+  {
+    std::lock_guard<std::mutex> lk(c->timing_mu);
+    for (auto& p : L->pending) {
+      float ms = 0;
+      if (p.kind < 0) continue;
+      if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        c->acc[p.kind].launches += 1;
+        c->acc[p.kind].ms += ms;
+        c->acc[p.kind].bytes += p.bytes;
+      }
     }
   }
-  c->pending.clear();
-  c->ev_used = 0;
+  L->pending.clear();
+  L->ev_used = 0;
 }
 
 // -------------------------------------------------------------- graph ---
 
-int compute_activation(raks_ctx* c) {
-  DevGraphView g = graph_view(c);
-  Status* st = P<Status>(c->status);
+int compute_activation(Ctx* c, Lane* L) {
+  hipStream_t s = L->stream;
+  Status* st = P<Status>(L->status);
   RAKS_TRY(dev_alloc(c, c->arc_src, (size_t)std::max<uint32_t>(c->A, 1) * 4));
-  if (c->mode == RAKS_ACT_EDGE) {
-    DevBuf ctmp;
-    RAKS_TRY(dev_alloc(c, ctmp, (size_t)std::max<uint32_t>(c->A, 1) * 4));
-    launch_check_and_count(g, P<uint32_t>(ctmp), P<int32_t>(c->arc_src), st, c->stream);
-    HIP_OK(hipMemcpyAsync(c->h_status, st, sizeof(Status), hipMemcpyDeviceToHost, c->stream));
-    HIP_OK(hipStreamSynchronize(c->stream));
-    if (c->h_status->err) {
-      dev_free(c, ctmp);
-      char msg[160];
-      snprintf(msg, sizeof msg,
-               "graph violates the input contract (bits 0x%x: 1 col range, 2 self-loop, "
-               "4 row order, 8 missing reverse arc)", c->h_status->err);
-      return fail(RAKS_EINVAL, msg);
-    }
-    launch_act_edge(g, P<uint32_t>(ctmp), st, c->abar, c->alpha, P<uint8_t>(c->act), c->stream);
-    HIP_OK(hipStreamSynchronize(c->stream));
+  DevGraphView g = graph_view(c);
+  DevBuf ctmp;
+  RAKS_TRY(dev_alloc(c, ctmp, (size_t)std::max<uint32_t>(c->A, 1) * 4));
+  launch_check_and_count(g, P<uint32_t>(ctmp), P<int32_t>(c->arc_src), st, s);
+  HIP_OK(hipMemcpyAsync(L->h_status, st, sizeof(Status), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (L->h_status->err) {
     dev_free(c, ctmp);
-  } else {
-    DevBuf ctmp;
-    RAKS_TRY(dev_alloc(c, ctmp, (size_t)std::max<uint32_t>(c->A, 1) * 4));
-    launch_check_and_count(g, P<uint32_t>(ctmp), P<int32_t>(c->arc_src), st, c->stream);
-    HIP_OK(hipMemcpyAsync(c->h_status, st, sizeof(Status), hipMemcpyDeviceToHost, c->stream));
-    HIP_OK(hipStreamSynchronize(c->stream));
-    dev_free(c, ctmp);
-    if (c->h_status->err)
-      return fail(RAKS_EINVAL, "graph violates the input contract");
-    launch_act_node(g, P<uint8_t>(c->nw), st, c->abar, c->alpha, P<uint8_t>(c->act_node),
-                    P<uint8_t>(c->act), c->stream);
-    HIP_OK(hipStreamSynchronize(c->stream));
+    char msg[160];
+    snprintf(msg, sizeof msg,
+             "graph violates the input contract (bits 0x%x: 1 col range, 2 self-loop, "
+             "4 row order, 8 missing reverse arc)", L->h_status->err);
+    return fail(RAKS_EINVAL, msg);
   }
+  if (c->mode == RAKS_ACT_EDGE)
+    launch_act_edge(g, P<uint32_t>(ctmp), st, c->abar, c->alpha, P<uint8_t>(c->act), s);
+  else
+    launch_act_node(g, P<uint8_t>(c->nw), st, c->abar, c->alpha, P<uint8_t>(c->act_node),
+                    P<uint8_t>(c->act), s);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamSynchronize(s));
+  dev_free(c, ctmp);
   // traversal copy sorted by activation level within each row
   RAKS_TRY(dev_alloc(c, c->col_s, (size_t)std::max<uint32_t>(c->A, 1) * 4));
   RAKS_TRY(dev_alloc(c, c->act_s, (size_t)std::max<uint32_t>(c->A, 1)));
@@ -267,9 +287,9 @@ int compute_activation(raks_ctx* c) {
   RAKS_TRY(dev_alloc(c, c->bnd, (size_t)c->n * c->nbnd * 4));
   g = graph_view(c);
   launch_sort_rows(g, P<int32_t>(c->col_s), P<uint8_t>(c->act_s), P<uint32_t>(c->eid_s),
-                   P<uint8_t>(c->row_amax), P<uint32_t>(c->bnd), c->nbnd, c->stream);
+                   P<uint8_t>(c->row_amax), P<uint32_t>(c->bnd), c->nbnd, s);
   HIP_OK(hipGetLastError());
-  HIP_OK(hipStreamSynchronize(c->stream));
+  HIP_OK(hipStreamSynchronize(s));
   return RAKS_OK;
 }
 
@@ -280,7 +300,7 @@ struct QueryPlan {
   std::vector<int32_t> central, marginal;
 };
 
-int validate_query(raks_ctx* c, const raks_query_desc* q, QueryPlan& p) {
+int validate_query(Ctx* c, const raks_query_desc* q, QueryPlan& p) {
   if (!q) return fail(RAKS_EINVAL, "query descriptor is NULL");
   p.C = q->n_central;
   p.M = q->n_marginal;
@@ -288,7 +308,8 @@ int validate_query(raks_ctx* c, const raks_query_desc* q, QueryPlan& p) {
   if (p.M < 0 || p.M > kMaxKw) return fail(RAKS_EINVAL, "need 0..16 marginal keywords");
   if (!q->central || (p.M > 0 && !q->marginal)) return fail(RAKS_EINVAL, "keyword array is NULL");
   p.central.assign(q->central, q->central + p.C);
-  p.marginal.assign(q->marginal ? q->marginal : q->central, (q->marginal ? q->marginal : q->central) + p.M);
+  p.marginal.clear();
+  if (p.M > 0) p.marginal.assign(q->marginal, q->marginal + p.M);
   std::vector<int32_t> all = p.central;
   all.insert(all.end(), p.marginal.begin(), p.marginal.end());
   for (int32_t t : all)
@@ -312,32 +333,34 @@ int validate_query(raks_ctx* c, const raks_query_desc* q, QueryPlan& p) {
   return RAKS_OK;
 }
 
-int ensure_node_buffers(raks_ctx* c) {
-  c->n_pad = (int32_t)(((int64_t)c->n + kScanNodes - 1) / kScanNodes * kScanNodes);
-  c->nblocks = c->n_pad / kScanNodes;
-  const size_t np = (size_t)c->n_pad;
-  RAKS_TRY(dev_alloc(c, c->F, np));
-  RAKS_TRY(dev_alloc(c, c->tot, (size_t)c->nblocks * sizeof(ScanTot)));
-  RAKS_TRY(dev_alloc(c, c->off, (size_t)c->nblocks * sizeof(ScanOff)));
-  RAKS_TRY(dev_alloc(c, c->q_off, (np + 1) * 4));
-  RAKS_TRY(dev_alloc(c, c->q_rs, np * 4));
-  RAKS_TRY(dev_alloc(c, c->q_lo, np * 4));
-  RAKS_TRY(dev_alloc(c, c->q_mask, np * 4));
-  RAKS_TRY(dev_alloc(c, c->cand, np * 8));
-  RAKS_TRY(dev_alloc(c, c->sel_node, kMaxW * 4));
-  RAKS_TRY(dev_alloc(c, c->sel_sc, kMaxW * 4));
-  RAKS_TRY(dev_alloc(c, c->sel_sumh, kMaxW * 4));
-  RAKS_TRY(dev_alloc(c, c->has_rpg, kMaxW * 4));
-  RAKS_TRY(dev_alloc(c, c->sm, kMaxW * 4));
-  RAKS_TRY(dev_alloc(c, c->key, kMaxW * 8));
-  RAKS_TRY(dev_alloc(c, c->dmin, kMaxW * kMaxKw));
-  RAKS_TRY(dev_alloc(c, c->ranked, kMaxW * 4));
-  RAKS_TRY(dev_alloc(c, c->vc_cnt, kMaxW * 4));
-  RAKS_TRY(dev_alloc(c, c->vc_off, (kMaxW + 1) * 4));
+int ensure_node_buffers(Lane* L) {
+  Ctx* c = L->ctx;
+  L->n_pad = (int32_t)(((int64_t)c->n + kScanNodes - 1) / kScanNodes * kScanNodes);
+  L->nblocks = L->n_pad / kScanNodes;
+  const size_t np = (size_t)L->n_pad;
+  RAKS_TRY(dev_alloc(c, L->F, np));
+  RAKS_TRY(dev_alloc(c, L->R, np * 2));
+  RAKS_TRY(dev_alloc(c, L->tot, (size_t)L->nblocks * sizeof(ScanTot)));
+  RAKS_TRY(dev_alloc(c, L->off, (size_t)L->nblocks * sizeof(ScanOff)));
+  RAKS_TRY(dev_alloc(c, L->q_off, (np + 1) * 4));
+  RAKS_TRY(dev_alloc(c, L->q_rs, np * 4));
+  RAKS_TRY(dev_alloc(c, L->q_lo, np * 4));
+  RAKS_TRY(dev_alloc(c, L->q_mask, np * 4));
+  RAKS_TRY(dev_alloc(c, L->cand, np * 8));
+  RAKS_TRY(dev_alloc(c, L->sel_node, kMaxW * 4));
+  RAKS_TRY(dev_alloc(c, L->sel_sc, kMaxW * 4));
+  RAKS_TRY(dev_alloc(c, L->sel_sumh, kMaxW * 4));
+  RAKS_TRY(dev_alloc(c, L->has_rpg, kMaxW * 4));
+  RAKS_TRY(dev_alloc(c, L->sm, kMaxW * 4));
+  RAKS_TRY(dev_alloc(c, L->key, kMaxW * 8));
+  RAKS_TRY(dev_alloc(c, L->dmin, kMaxW * kMaxKw));
+  RAKS_TRY(dev_alloc(c, L->ranked, kMaxW * 4));
+  RAKS_TRY(dev_alloc(c, L->vc_cnt, kMaxW * 4));
+  RAKS_TRY(dev_alloc(c, L->vc_off, (kMaxW + 1) * 4));
   return RAKS_OK;
 }
 
-SeedList seeds_for(raks_ctx* c, const std::vector<int32_t>& kws) {
+SeedList seeds_for(Ctx* c, const std::vector<int32_t>& kws) {
   SeedList s = {};
   s.T = (int32_t)kws.size();
   uint32_t acc = 0;
@@ -351,37 +374,38 @@ SeedList seeds_for(raks_ctx* c, const std::vector<int32_t>& kws) {
   return s;
 }
 
-RunView run_view(raks_ctx* c, int kind, int T, DevBuf& H, const QueryPlan& p) {
+RunView run_view(Lane* L, int kind, int T, DevBuf& H, const QueryPlan& p) {
   RunView r = {};
   r.kind = kind;
   r.T = T;
   r.tmask = (T >= 32) ? 0xFFFFFFFFu : ((1u << T) - 1);
   r.block_rule = (kind == RUN_CENTRAL) ? 1 : (T >= 2 ? 1 : 0);
   r.H = P<uint8_t>(H);
-  r.F = P<uint8_t>(c->F);
-  r.n_pad = c->n_pad;
-  r.st = &P<Status>(c->status)->run[kind];
-  r.tot = P<ScanTot>(c->tot);
-  r.off = P<ScanOff>(c->off);
-  r.nblocks = c->nblocks;
-  r.q_lo = P<uint32_t>(c->q_lo);
-  r.q_off = P<uint32_t>(c->q_off);
-  r.q_rs = P<uint32_t>(c->q_rs);
-  r.q_mask = P<uint32_t>(c->q_mask);
-  r.cand = P<uint64_t>(c->cand);
+  r.F = P<uint8_t>(L->F);
+  r.R = L->R.p;
+  r.n_pad = L->n_pad;
+  r.st = &P<Status>(L->status)->run[kind];
+  r.tot = P<ScanTot>(L->tot);
+  r.off = P<ScanOff>(L->off);
+  r.nblocks = L->nblocks;
+  r.q_lo = P<uint32_t>(L->q_lo);
+  r.q_off = P<uint32_t>(L->q_off);
+  r.q_rs = P<uint32_t>(L->q_rs);
+  r.q_mask = P<uint32_t>(L->q_mask);
+  r.cand = P<uint64_t>(L->cand);
   r.max_level = p.L;
   r.w = p.w;
   r.k = p.k;
   r.gamma_num = p.gn;
   r.gamma_den = p.gd;
-  r.nsel = &P<Status>(c->status)->nsel;
-  r.sel_sc = P<int32_t>(c->sel_sc);
-  r.vc_off = P<uint32_t>(c->vc_off);
-  r.vc_nodes = P<int32_t>(c->vc_nodes);
-  r.has_rpg = P<int32_t>(c->has_rpg);
-  r.sm = P<int32_t>(c->sm);
-  r.key = P<int64_t>(c->key);
-  r.dmin = P<uint8_t>(c->dmin);
+  r.nsel = &P<Status>(L->status)->nsel;
+  r.sel_sc = P<int32_t>(L->sel_sc);
+  r.vc_off = P<uint32_t>(L->vc_off);
+  r.vc_nodes = P<int32_t>(L->vc_nodes);
+  r.has_rpg = P<int32_t>(L->has_rpg);
+  r.sm = P<int32_t>(L->sm);
+  r.key = P<int64_t>(L->key);
+  r.dmin = P<uint8_t>(L->dmin);
   return r;
 }
 
@@ -397,208 +421,386 @@ __global__ void k_query_reset(Status* st) {
 // l+1 before it waits for the status of level l, so the GPU never idles on
 // the host's decision; the kernels of a level after the run's end return at
 // once.  Returns the run's final status in *last.
-int run_levels(raks_ctx* c, RunView& r, int TP, const std::vector<int32_t>& kws, int T,
+int run_levels(Lane* L, RunView& r, int TP, const std::vector<int32_t>& kws, int T,
                RunStatus* last) {
+  Ctx* c = L->ctx;
+  hipStream_t s = L->stream;
   DevGraphView g = graph_view(c);
   const SeedList seeds = seeds_for(c, kws);
   {
-    Timed t(c, 4);
-    launch_run_init(r, TP, c->n, P<int32_t>(c->kw_nodes), seeds, c->stream);
+    Timed t(L, 4);
+    launch_run_init(r, TP, c->n, P<int32_t>(c->kw_nodes), seeds, s);
   }
   const int grid = c->num_cu * 8;
+  // The control kernel writes the level's status into the pinned slot; the
+  // slot's event follows it, so the host learns the decision while the
+  // level's expansion still runs.
   auto enqueue = [&](int level, int slot) -> int {
     {
-      Timed t(c, 1, 0, level, r.kind);
-      launch_front_count(r, TP, g, level, c->stream);
+      Timed t(L, 1, level, r.kind);
+      launch_front_count(r, TP, g, level, s);
     }
     {
-      Timed t(c, 2, 0, level, r.kind);
-      launch_front_control(r, TP, level, c->stream);
+      Timed t(L, 2, level, r.kind);
+      launch_front_control(r, TP, level, &L->d_run[slot], s);
+    }
+    HIP_OK(hipEventRecord(L->lvl_ev[slot], s));
+    {
+      Timed t(L, 1, level, r.kind);
+      launch_front_write(r, TP, g, level, s);
     }
     {
-      Timed t(c, 1, 0, level, r.kind);
-      launch_front_write(r, TP, g, level, c->stream);
-    }
-    {
-      Timed t(c, 0, 0, level, r.kind);
-      launch_expand(r, TP, g, level, grid, c->stream);
+      Timed t(L, 0, level, r.kind);
+      launch_expand(r, TP, g, level, grid, s);
     }
     HIP_OK(hipGetLastError());
-    HIP_OK(hipMemcpyAsync(&c->h_run[slot], r.st, sizeof(RunStatus), hipMemcpyDeviceToHost, c->stream));
-    HIP_OK(hipEventRecord(c->lvl_ev[slot], c->stream));
     return RAKS_OK;
   };
   RAKS_TRY(enqueue(0, 0));
   for (int level = 0;; ++level) {
     const int slot = level & 1;
     if (level + 1 <= r.max_level) RAKS_TRY(enqueue(level + 1, slot ^ 1));
-    HIP_OK(hipEventSynchronize(c->lvl_ev[slot]));
-    const RunStatus s = c->h_run[slot];
-    if (c->timing) {
-      for (auto& pe : c->pending) {
+    HIP_OK(hipEventSynchronize(L->lvl_ev[slot]));
+    const RunStatus rs = L->h_run[slot];
+    if (c->timing.load()) {
+      for (auto& pe : L->pending) {
         if (pe.kind != 0 || pe.level != level || pe.run != r.kind) continue;
-        if (s.end_level == INT32_MAX) {
+        if (rs.end_level == INT32_MAX) {
           // algorithmic bytes of this expansion: per examined arc the neighbour
           // id (4) and its T hitting levels; per queue entry 16
-          pe.bytes = (4.0 + T) * s.W + 16.0 * s.nactive;
+          pe.bytes = (4.0 + T) * rs.W + 16.0 * rs.nactive;
         } else {
           pe.kind = -1;   // the level ended before expanding: no work launched
         }
       }
     }
-    if (s.end_level != INT32_MAX || level >= r.max_level) {
-      *last = s;
+    if (rs.end_level != INT32_MAX || level >= r.max_level) {
+      *last = rs;
       break;
     }
   }
   return RAKS_OK;
 }
 
-int ensure_recovery(raks_ctx* c, int n_inst, int n_cg, int C, int M, int n_res, int max_level) {
-  const uint32_t hc = [&] { uint32_t h = 1; while (h < 2 * c->nc) h <<= 1; return h; }();
-  RAKS_TRY(dev_alloc(c, c->ht, (size_t)std::max(n_inst, 1) * hc * 4));
-  RAKS_TRY(dev_alloc(c, c->nl, (size_t)std::max(n_inst, 1) * c->nc * 4));
-  RAKS_TRY(dev_alloc(c, c->al, (size_t)std::max(n_inst, 1) * c->ac * 4));
-  RAKS_TRY(dev_alloc(c, c->icnt, (size_t)std::max(n_inst, 1) * 8));
-  RAKS_TRY(dev_alloc(c, c->items, (size_t)(max_level + 1) * c->lcap * sizeof(RecItem)));
-  RAKS_TRY(dev_alloc(c, c->lcnt, (size_t)(max_level + 1) * 4));
-  const size_t cg_ncap = (size_t)C * c->nc, cg_acap = (size_t)C * c->ac;
-  RAKS_TRY(dev_alloc(c, c->cg_nodes, (size_t)std::max(n_cg, 1) * cg_ncap * 4));
-  RAKS_TRY(dev_alloc(c, c->cg_arcs, (size_t)std::max(n_cg, 1) * cg_acap * 4));
-  RAKS_TRY(dev_alloc(c, c->cg_cnt, (size_t)std::max(n_cg, 1) * 8));
-  RAKS_TRY(dev_alloc(c, c->vc_tmp, (size_t)std::max(n_cg, 1) * cg_ncap * 4));
-  RAKS_TRY(dev_alloc(c, c->vc_nodes, (size_t)std::max(n_cg, 1) * cg_ncap * 4));
-  const size_t scap = std::max({cg_acap, cg_ncap + (size_t)M * c->nc, cg_acap + (size_t)M * c->ac});
-  const int nw = std::max(n_cg, n_res);
-  RAKS_TRY(dev_alloc(c, c->sort_a, (size_t)std::max(nw, 1) * scap * 4));
-  RAKS_TRY(dev_alloc(c, c->sort_b, (size_t)std::max(nw, 1) * scap * 4));
-  const size_t ncap = (size_t)n_res * ((size_t)C * c->nc + (size_t)M * c->nc);
-  const size_t acap = (size_t)n_res * ((size_t)C * c->ac + (size_t)M * c->ac);
-  RAKS_TRY(dev_alloc(c, c->hdr, (size_t)std::max(n_res, 1) * sizeof(ResultHdr)));
-  RAKS_TRY(dev_alloc(c, c->out_nodes, std::max<size_t>(ncap, 1) * 4));
-  RAKS_TRY(dev_alloc(c, c->out_arcs, std::max<size_t>(acap, 1) * 12));
+// ------------------------------------------------------------ recovery ---
+
+constexpr int kMaxAttempts = 24;
+
+uint32_t pow2_at_least(uint64_t x) {
+  uint32_t h = 64;
+  while (h < x && h < (1u << 31)) h <<= 1;
+  return h;
+}
+
+uint32_t dense_words(const Ctx* c) { return (uint32_t)(((uint64_t)c->n + 31) / 32); }
+
+// Initial capacities for a phase of n_res results with T instances each.
+void phase_reset(const Ctx* c, RecPhase& P, int n_res, int T) {
+  const int n_inst = n_res * T;
+  if (!P.grown && P.n_res == n_res && P.T == T && P.lcap) return;
+  P.n_inst = n_inst;
+  P.n_res = n_res;
+  P.T = T;
+  P.ncap.assign(n_inst, c->rec_nc0);
+  P.acap.assign(n_inst, c->rec_ac0);
+  P.dense.assign(n_inst, 0);
+  P.lcap = c->rec_lcap0;
+  P.grown = false;
+  P.dirty = true;
+}
+
+// Derives the device layout of a phase.  Phase 0 (CG recovery) also fixes
+// where each CG's lists live; phase 1 sizes its sort scratch and the output
+// from phase 0's largest CG lists.
+void phase_layout(const Ctx* c, RecPhase& P, const RecPhase* cg_phase) {
+  const uint32_t dw = dense_words(c);
+  P.caps.resize(P.n_inst);
+  uint64_t h = 0, nn = 0, aa = 0;
+  for (int i = 0; i < P.n_inst; ++i) {
+    InstCap& ic = P.caps[i];
+    ic.dense = P.dense[i];
+    ic.hcap = ic.dense ? 0u : pow2_at_least(2ull * P.ncap[i]);
+    ic.ncap = P.ncap[i];
+    ic.acap = P.acap[i];
+    ic.hoff = h;
+    ic.noff = nn;
+    ic.aoff = aa;
+    h += ((ic.dense ? (uint64_t)dw : (uint64_t)ic.hcap) + 63) & ~uint64_t(63);
+    nn += ic.ncap;
+    aa += ic.acap;
+  }
+  P.h_words = h;
+  P.n_total = nn;
+  P.a_total = aa;
+  P.cg_noff.assign(P.n_res + 1, 0);
+  P.cg_aoff.assign(P.n_res + 1, 0);
+  P.soff.assign(P.n_res + 1, 0);
+  P.cg_nmax = P.cg_amax = 0;
+  P.out_n = P.out_a = 0;
+  for (int r = 0; r < P.n_res; ++r) {
+    uint64_t sn = 0, sa = 0;
+    for (int j = 0; j < P.T; ++j) {
+      sn += P.ncap[r * P.T + j];
+      sa += P.acap[r * P.T + j];
+    }
+    uint64_t scratch = std::max(sn, sa);
+    if (cg_phase) {
+      // an RPG is its CG's lists plus its own instances
+      sn += cg_phase->cg_nmax;
+      sa += cg_phase->cg_amax;
+      scratch = std::max(sn, sa);
+      P.out_n += sn;
+      P.out_a += sa;
+    } else {
+      P.cg_nmax = std::max(P.cg_nmax, sn);
+      P.cg_amax = std::max(P.cg_amax, sa);
+    }
+    P.cg_noff[r + 1] = P.cg_noff[r] + sn;
+    P.cg_aoff[r + 1] = P.cg_aoff[r] + sa;
+    P.soff[r + 1] = P.soff[r] + scratch;
+  }
+}
+
+// Uploads a phase's layout (after a change) and sizes its counters.
+int phase_upload(Lane* L, RecPhase& P, int max_level) {
+  Ctx* c = L->ctx;
+  RAKS_TRY(dev_alloc(c, P.cnt, (size_t)std::max(P.n_inst, 1) * 8));
+  RAKS_TRY(dev_alloc(c, P.iflag, (size_t)std::max(P.n_inst, 1) * 4));
+  RAKS_TRY(dev_alloc(c, P.lcnt, (size_t)(max_level + 1) * 4));
+  if (!P.dirty) return RAKS_OK;
+  const size_t nr = (size_t)P.n_res + 1;
+  P.lay_cg_noff = ((size_t)P.n_inst * sizeof(InstCap) + 63) & ~size_t(63);
+  P.lay_cg_aoff = P.lay_cg_noff + nr * 8;
+  P.lay_soff = P.lay_cg_aoff + nr * 8;
+  const size_t bytes = P.lay_soff + nr * 8;
+  if (P.stage_bytes < bytes) {
+    if (P.stage) (void)hipHostFree(P.stage);
+    P.stage = nullptr;
+    P.stage_bytes = 0;
+    if (hipHostMalloc(&P.stage, bytes, hipHostMallocDefault) != hipSuccess)
+      return fail(RAKS_ENOMEM, "pinned staging allocation failed");
+    P.stage_bytes = bytes;
+  }
+  char* st = static_cast<char*>(P.stage);
+  if (P.n_inst) memcpy(st, P.caps.data(), (size_t)P.n_inst * sizeof(InstCap));
+  memcpy(st + P.lay_cg_noff, P.cg_noff.data(), nr * 8);
+  memcpy(st + P.lay_cg_aoff, P.cg_aoff.data(), nr * 8);
+  memcpy(st + P.lay_soff, P.soff.data(), nr * 8);
+  RAKS_TRY(dev_alloc(c, P.layout, bytes));
+  HIP_OK(hipMemcpyAsync(P.layout.p, st, bytes, hipMemcpyHostToDevice, L->stream));
+  P.dirty = false;
   return RAKS_OK;
 }
 
-RecoverView recover_view(raks_ctx* c, int marginal, DevBuf& H, int TP, int T, int n_inst,
-                         const int32_t* n_valid, int max_layer) {
+// Layouts and device storage for both phases (grown, never shrunk).  Called
+// only where no kernel of the lane is in flight, since a buffer may move.
+int ensure_recovery(Lane* L, const QueryPlan& p) {
+  Ctx* c = L->ctx;
+  RecPhase& P0 = L->ph[0];
+  RecPhase& P1 = L->ph[1];
+  if (P0.dirty) {
+    phase_layout(c, P0, nullptr);
+    P1.dirty = true;   // its scratch and output sizes follow the CG lists
+  }
+  if (P1.dirty) phase_layout(c, P1, &P0);
+  RAKS_TRY(phase_upload(L, P0, p.L));
+  RAKS_TRY(phase_upload(L, P1, p.L));
+  const uint64_t hw = std::max(P0.h_words, P1.h_words);
+  const uint64_t nt = std::max(P0.n_total, P1.n_total), at = std::max(P0.a_total, P1.a_total);
+  const uint64_t lc = std::max(P0.lcap, P1.lcap);
+  RAKS_TRY(dev_alloc(c, L->hpool, std::max<uint64_t>(hw, 1) * 4));
+  RAKS_TRY(dev_alloc(c, L->nl, std::max<uint64_t>(nt, 1) * 4));
+  RAKS_TRY(dev_alloc(c, L->al, std::max<uint64_t>(at, 1) * 4));
+  RAKS_TRY(dev_alloc(c, L->items, (size_t)(p.L + 1) * lc * sizeof(RecItem)));
+  const uint64_t cgn = P0.cg_noff[P0.n_res], cga = P0.cg_aoff[P0.n_res];
+  RAKS_TRY(dev_alloc(c, L->cg_nodes, std::max<uint64_t>(cgn, 1) * 4));
+  RAKS_TRY(dev_alloc(c, L->cg_arcs, std::max<uint64_t>(cga, 1) * 4));
+  RAKS_TRY(dev_alloc(c, L->cg_cnt, (size_t)std::max(P0.n_res, 1) * 8));
+  RAKS_TRY(dev_alloc(c, L->vc_tmp, std::max<uint64_t>(cgn, 1) * 4));
+  RAKS_TRY(dev_alloc(c, L->vc_nodes, std::max<uint64_t>(cgn, 1) * 4));
+  const uint64_t sc = std::max(P0.soff[P0.n_res], P1.soff[P1.n_res]);
+  RAKS_TRY(dev_alloc(c, L->sort_a, std::max<uint64_t>(sc, 1) * 4));
+  RAKS_TRY(dev_alloc(c, L->sort_b, std::max<uint64_t>(sc, 1) * 4));
+  RAKS_TRY(dev_alloc(c, L->hdr, (size_t)std::max(P1.n_res, 1) * sizeof(ResultHdr)));
+  RAKS_TRY(dev_alloc(c, L->out_nodes, std::max<uint64_t>(P1.out_n, 1) * 4));
+  RAKS_TRY(dev_alloc(c, L->out_arcs, std::max<uint64_t>(P1.out_a, 1) * 12));
+  return RAKS_OK;
+}
+
+// After an overflow of phase `ph`: every instance that ran out gets at least
+// twice its capacities and twice what it counted; one whose node table
+// filled up switches to a bitmap; the layer lists grow to twice the largest
+// request.
+int grow_phase(Lane* L, int ph, int max_level) {
+  Ctx* c = L->ctx;
+  RecPhase& P = L->ph[ph];
+  std::vector<uint32_t> cnt((size_t)P.n_inst * 2), fl(P.n_inst), lc(max_level + 1);
+  hipStream_t s = L->stream;
+  if (P.n_inst) {
+    HIP_OK(hipMemcpyAsync(cnt.data(), P.cnt.p, cnt.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(fl.data(), P.iflag.p, fl.size() * 4, hipMemcpyDeviceToHost, s));
+  }
+  HIP_OK(hipMemcpyAsync(lc.data(), P.lcnt.p, lc.size() * 4, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  const uint32_t dw = dense_words(c);
+  for (int i = 0; i < P.n_inst; ++i) {
+    const uint32_t cn = cnt[2 * i], ca = cnt[2 * i + 1];
+    if (cn <= P.ncap[i] && ca <= P.acap[i] && !fl[i]) continue;
+    const uint64_t nn = std::min<uint64_t>((uint64_t)c->n, 2ull * std::max(P.ncap[i], cn));
+    const uint64_t na = std::min<uint64_t>((uint64_t)std::max<uint32_t>(c->A, 1),
+                                           2ull * std::max(P.acap[i], ca));
+    P.ncap[i] = (uint32_t)nn;
+    P.acap[i] = (uint32_t)na;
+    if (fl[i] || pow2_at_least(2ull * nn) >= dw) P.dense[i] = 1;
+  }
+  uint32_t lmax = 0;
+  for (uint32_t x : lc) lmax = std::max(lmax, x);
+  if (lmax > P.lcap) P.lcap = (uint32_t)std::min<uint64_t>(2ull * lmax, 1u << 30);
+  P.grown = true;
+  P.dirty = true;
+  return RAKS_OK;
+}
+
+RecoverView recover_view(Lane* L, int ph, DevBuf& H, int TP, const int32_t* n_valid,
+                         int max_layer) {
+  RecPhase& Ph = L->ph[ph];
   RecoverView v = {};
-  v.items = P<RecItem>(c->items);
-  v.lcnt = P<uint32_t>(c->lcnt);
-  v.lcap = c->lcap;
-  v.max_layer = max_layer;
-  v.g = graph_view(c);
+  v.g = graph_view(L->ctx);
   v.H = P<uint8_t>(H);
   v.TP = TP;
-  v.T = T;
-  v.marginal = marginal;
-  v.n_inst = n_inst;
+  v.T = Ph.T;
+  v.marginal = ph;
+  v.n_inst = Ph.n_inst;
   v.n_valid = n_valid;
-  v.sel_node = P<int32_t>(c->sel_node);
-  v.ranked = P<int32_t>(c->ranked);
-  v.vc_off = P<uint32_t>(c->vc_off);
-  v.vc_nodes = P<int32_t>(c->vc_nodes);
-  v.dmin = P<uint8_t>(c->dmin);
-  v.ht = P<uint32_t>(c->ht);
-  v.nl = P<int32_t>(c->nl);
-  v.al = P<uint32_t>(c->al);
-  v.cnt = P<uint32_t>(c->icnt);
-  uint32_t hc = 1;
-  while (hc < 2 * c->nc) hc <<= 1;
-  v.hc = hc;
-  v.nc = c->nc;
-  v.ac = c->ac;
-  v.gst = P<Status>(c->status);
+  v.sel_node = P<int32_t>(L->sel_node);
+  v.ranked = P<int32_t>(L->ranked);
+  v.vc_off = P<uint32_t>(L->vc_off);
+  v.vc_nodes = P<int32_t>(L->vc_nodes);
+  v.dmin = P<uint8_t>(L->dmin);
+  v.caps = P<InstCap>(Ph.layout);
+  v.hpool = P<uint32_t>(L->hpool);
+  v.nl = P<int32_t>(L->nl);
+  v.al = P<uint32_t>(L->al);
+  v.cnt = P<uint32_t>(Ph.cnt);
+  v.iflag = P<uint32_t>(Ph.iflag);
+  v.dwords = dense_words(L->ctx);
+  v.items = P<RecItem>(L->items);
+  v.lcnt = P<uint32_t>(Ph.lcnt);
+  v.lcap = Ph.lcap;
+  v.max_layer = max_layer;
+  v.ovf_bit = ph == 0 ? 1 : 2;
+  v.gst = P<Status>(L->status);
   return v;
 }
 
-FinalizeView finalize_view(raks_ctx* c, int marginal, int T, int n_res, const int32_t* n_valid,
-                           int C, int TPc, int M) {
+FinalizeView finalize_view(Lane* L, int ph, const int32_t* n_valid, int C, int TPc) {
+  RecPhase& Ph = L->ph[ph];
+  RecPhase& P0 = L->ph[0];
+  char* lay = static_cast<char*>(Ph.layout.p);
+  char* lay0 = static_cast<char*>(P0.layout.p);
   FinalizeView v = {};
-  v.g = graph_view(c);
-  v.T = T;
-  v.marginal = marginal;
-  v.n_res = n_res;
+  v.g = graph_view(L->ctx);
+  v.T = Ph.T;
+  v.marginal = ph;
+  v.n_res = Ph.n_res;
   v.n_valid = n_valid;
-  v.sel_node = P<int32_t>(c->sel_node);
-  v.ranked = P<int32_t>(c->ranked);
-  v.nl = P<int32_t>(c->nl);
-  v.al = P<uint32_t>(c->al);
-  v.cnt = P<uint32_t>(c->icnt);
-  v.nc = c->nc;
-  v.ac = c->ac;
-  v.cg_nodes = P<uint32_t>(c->cg_nodes);
-  v.cg_arcs = P<uint32_t>(c->cg_arcs);
-  v.cg_cnt = P<uint32_t>(c->cg_cnt);
-  v.cg_ncap = (uint32_t)C * c->nc;
-  v.cg_acap = (uint32_t)C * c->ac;
-  v.Hc = P<uint8_t>(c->Hc);
+  v.sel_node = P<int32_t>(L->sel_node);
+  v.ranked = P<int32_t>(L->ranked);
+  v.caps = reinterpret_cast<const InstCap*>(lay);
+  v.nl = P<int32_t>(L->nl);
+  v.al = P<uint32_t>(L->al);
+  v.cnt = P<uint32_t>(Ph.cnt);
+  v.cg_nodes = P<uint32_t>(L->cg_nodes);
+  v.cg_arcs = P<uint32_t>(L->cg_arcs);
+  v.cg_cnt = P<uint32_t>(L->cg_cnt);
+  v.cg_noff = reinterpret_cast<const uint64_t*>(lay0 + P0.lay_cg_noff);
+  v.cg_aoff = reinterpret_cast<const uint64_t*>(lay0 + P0.lay_cg_aoff);
+  v.Hc = P<uint8_t>(L->Hc);
   v.TPc = TPc;
   v.Tc = C;
-  v.vc_cnt = P<uint32_t>(c->vc_cnt);
-  v.vc_tmp = P<int32_t>(c->vc_tmp);
-  v.sort_a = P<uint32_t>(c->sort_a);
-  v.sort_b = P<uint32_t>(c->sort_b);
-  v.scap = (uint32_t)std::max({(size_t)v.cg_acap, (size_t)v.cg_ncap + (size_t)M * c->nc,
-                               (size_t)v.cg_acap + (size_t)M * c->ac});
-  v.write_output = marginal;
-  v.hdr = P<ResultHdr>(c->hdr);
-  v.out_nodes = P<int32_t>(c->out_nodes);
-  v.out_arcs = P<int32_t>(c->out_arcs);
-  v.sel_sc = P<int32_t>(c->sel_sc);
-  v.sm = P<int32_t>(c->sm);
-  v.key = P<int64_t>(c->key);
-  v.gst = P<Status>(c->status);
+  v.vc_cnt = P<uint32_t>(L->vc_cnt);
+  v.vc_tmp = P<int32_t>(L->vc_tmp);
+  v.sort_a = P<uint32_t>(L->sort_a);
+  v.sort_b = P<uint32_t>(L->sort_b);
+  v.soff = reinterpret_cast<const uint64_t*>(lay + Ph.lay_soff);
+  v.write_output = ph;
+  v.hdr = P<ResultHdr>(L->hdr);
+  v.out_nodes = P<int32_t>(L->out_nodes);
+  v.out_arcs = P<int32_t>(L->out_arcs);
+  v.out_ncap = (uint32_t)std::min<size_t>(L->out_nodes.bytes / 4, UINT32_MAX);
+  v.out_acap = (uint32_t)std::min<size_t>(L->out_arcs.bytes / 12, UINT32_MAX);
+  v.sel_sc = P<int32_t>(L->sel_sc);
+  v.sm = P<int32_t>(L->sm);
+  v.key = P<int64_t>(L->key);
+  v.gst = P<Status>(L->status);
   return v;
 }
 
-// One attempt at a query with the current recovery capacities; *overflow is
-// set when a capacity ran out (the caller grows them and repeats).
-int query_attempt(raks_ctx* c, const QueryPlan& p, raks_results** out, bool* overflow) {
-  *overflow = false;
-  Status* st = P<Status>(c->status);
-  HIP_OK(hipEventRecord(c->q_start, c->stream));
-  k_query_reset<<<1, 1, 0, c->stream>>>(st);
+// ---------------------------------------------------------------- query ---
 
-  // ---- central run and top-w selection
-  RunView r1 = run_view(c, RUN_CENTRAL, p.C, c->Hc, p);
+// Clears the flags and output counters before a phase is repeated.
+__global__ void k_retry_reset(Status* st) {
+  st->overflow = 0;
+  st->out_nodes = 0;
+  st->out_arcs = 0;
+}
+
+struct QueryRun {
   RunStatus s1 = {}, s2 = {};
-  RAKS_TRY(run_levels(c, r1, p.TPc, p.central, p.C, &s1));
+  int top1 = 0, top2 = 0;
+};
+
+// Central run and top-w selection.
+int stage_central(Lane* L, const QueryPlan& p, QueryRun& q) {
+  hipStream_t s = L->stream;
+  Status* st = P<Status>(L->status);
+  HIP_OK(hipEventRecord(L->q_start, s));
+  k_query_reset<<<1, 1, 0, s>>>(st);
+  RunView r1 = run_view(L, RUN_CENTRAL, p.C, L->Hc, p);
+  RAKS_TRY(run_levels(L, r1, p.TPc, p.central, p.C, &q.s1));
+  q.top1 = std::max(0, q.s1.levels - 1);   // central levels are at most this
   SelectView sv;
-  sv.cand = P<uint64_t>(c->cand);
+  sv.cand = P<uint64_t>(L->cand);
   sv.st = r1.st;
   sv.gst = st;
   sv.w = p.w;
-  sv.sel_node = P<int32_t>(c->sel_node);
-  sv.sel_sc = P<int32_t>(c->sel_sc);
-  sv.sel_sumh = P<int32_t>(c->sel_sumh);
-  {
-    Timed t(c, 2);
-    launch_select(sv, c->stream);
-  }
+  sv.sel_node = P<int32_t>(L->sel_node);
+  sv.sel_sc = P<int32_t>(L->sel_sc);
+  sv.sel_sumh = P<int32_t>(L->sel_sumh);
+  Timed t(L, 2);
+  launch_select(sv, s);
+  return RAKS_OK;
+}
 
-  // ---- recovery of the selected CGs (instances beyond nsel exit at once)
-  const int top1 = std::max(0, s1.levels - 1);   // central levels are at most this
-  RAKS_TRY(ensure_recovery(c, std::max(p.w * p.C, p.k * p.M), p.w, p.C, p.M, p.k, p.L));
+// CG recovery (instances beyond nsel exit at once), CG lists and V_C.
+int stage_cg_recovery(Lane* L, const QueryPlan& p, const QueryRun& q) {
+  hipStream_t s = L->stream;
+  Status* st = P<Status>(L->status);
   {
-    Timed t(c, 3);
-    launch_recover(recover_view(c, 0, c->Hc, p.TPc, p.C, p.w * p.C, &st->nsel, top1), c->stream);
-    launch_finalize(finalize_view(c, 0, p.C, p.w, &st->nsel, p.C, p.TPc, p.M), c->stream);
-    if (p.M > 0)
-      launch_pack_vc(P<uint32_t>(c->vc_cnt), P<int32_t>(c->vc_tmp), (uint32_t)p.C * c->nc,
-                     &st->nsel, P<uint32_t>(c->vc_off), P<int32_t>(c->vc_nodes), c->stream);
+    Timed t(L, 3);
+    launch_recover(recover_view(L, 0, L->Hc, p.TPc, &st->nsel, q.top1), s);
+    launch_finalize(finalize_view(L, 0, &st->nsel, p.C, p.TPc), s);
+    if (p.M > 0) {
+      const char* lay0 = static_cast<const char*>(L->ph[0].layout.p);
+      launch_pack_vc(P<uint32_t>(L->vc_cnt), P<int32_t>(L->vc_tmp),
+                     reinterpret_cast<const uint64_t*>(lay0 + L->ph[0].lay_cg_noff), &st->nsel,
+                     P<uint32_t>(L->vc_off), P<int32_t>(L->vc_nodes), s);
+    }
   }
   HIP_OK(hipGetLastError());
+  return RAKS_OK;
+}
 
-  // ---- marginal run (ends before level 0 when no CG was selected)
-  int top2 = 0;
+// Marginal run (ends before level 0 when no CG was selected) and ranking.
+int stage_marginal(Lane* L, const QueryPlan& p, QueryRun& q) {
+  hipStream_t s = L->stream;
+  Status* st = P<Status>(L->status);
+  q.top2 = 0;
   if (p.M > 0) {
-    RunView r2 = run_view(c, RUN_MARGINAL, p.M, c->Hm, p);
-    RAKS_TRY(run_levels(c, r2, p.TPm, p.marginal, p.M, &s2));
-    top2 = std::max(0, s2.levels - 1);
+    RunView r2 = run_view(L, RUN_MARGINAL, p.M, L->Hm, p);
+    RAKS_TRY(run_levels(L, r2, p.TPm, p.marginal, p.M, &q.s2));
+    q.top2 = std::max(0, q.s2.levels - 1);
   }
-
-  // ---- ranking, marginal recovery, output
   RankView rv;
   rv.gst = st;
   rv.nsel = &st->nsel;
@@ -606,61 +808,70 @@ int query_attempt(raks_ctx* c, const QueryPlan& p, raks_results** out, bool* ove
   rv.k = p.k;
   rv.gamma_num = p.gn;
   rv.gamma_den = p.gd;
-  rv.sel_sc = P<int32_t>(c->sel_sc);
-  rv.has_rpg = P<int32_t>(c->has_rpg);
-  rv.sm = P<int32_t>(c->sm);
-  rv.key = P<int64_t>(c->key);
-  rv.ranked = P<int32_t>(c->ranked);
+  rv.sel_sc = P<int32_t>(L->sel_sc);
+  rv.has_rpg = P<int32_t>(L->has_rpg);
+  rv.sm = P<int32_t>(L->sm);
+  rv.key = P<int64_t>(L->key);
+  rv.ranked = P<int32_t>(L->ranked);
+  Timed t(L, 2);
+  launch_rank(rv, s);
+  return RAKS_OK;
+}
+
+// RPG recovery and the output.
+int stage_output(Lane* L, const QueryPlan& p, const QueryRun& q) {
+  hipStream_t s = L->stream;
+  Status* st = P<Status>(L->status);
   {
-    Timed t(c, 2);
-    launch_rank(rv, c->stream);
-  }
-  {
-    Timed t(c, 3);
-    if (p.M > 0)
-      launch_recover(recover_view(c, 1, c->Hm, p.TPm, p.M, p.k * p.M, &st->nres, top2), c->stream);
-    FinalizeView fv = finalize_view(c, 1, p.M, p.k, &st->nres, p.C, p.TPc, p.M);
-    fv.out_ncap = (uint32_t)std::min<size_t>(c->out_nodes.bytes / 4, UINT32_MAX);
-    fv.out_acap = (uint32_t)std::min<size_t>(c->out_arcs.bytes / 12, UINT32_MAX);
-    launch_finalize(fv, c->stream);
+    Timed t(L, 3);
+    if (p.M > 0) launch_recover(recover_view(L, 1, L->Hm, p.TPm, &st->nres, q.top2), s);
+    launch_finalize(finalize_view(L, 1, &st->nres, p.C, p.TPc), s);
   }
   HIP_OK(hipGetLastError());
-  HIP_OK(hipEventRecord(c->q_end, c->stream));
+  HIP_OK(hipEventRecord(L->q_end, s));
+  return RAKS_OK;
+}
 
-  // ---- results to the host: status, headers and a first slice of the
-  // output in one round trip
-  HIP_OK(hipMemcpyAsync(c->h_status, st, sizeof(Status), hipMemcpyDeviceToHost, c->stream));
-  HIP_OK(hipMemcpyAsync(c->h_hdr, c->hdr.p, sizeof(ResultHdr) * p.k, hipMemcpyDeviceToHost, c->stream));
-  const size_t spec_n = std::min(c->out_nodes.bytes / 4, (size_t)kSpecNodes);
-  const size_t spec_a = std::min(c->out_arcs.bytes / 12, (size_t)kSpecArcs);
-  HIP_OK(hipMemcpyAsync(c->h_nodes, c->out_nodes.p, 4 * spec_n, hipMemcpyDeviceToHost, c->stream));
-  HIP_OK(hipMemcpyAsync(c->h_arcs, c->out_arcs.p, 12 * spec_a, hipMemcpyDeviceToHost, c->stream));
-  HIP_OK(hipStreamSynchronize(c->stream));
-  const Status hs = *c->h_status;
+// Status, headers and a first slice of the output in one round trip; the
+// rest of the output only when it is larger.  *ovf receives the overflow
+// bits (1 CG recovery, 2 RPG recovery, 4 output arena); results are built
+// only when it is 0.
+int collect(Lane* L, const QueryPlan& p, raks_results** out, int* ovf) {
+  Ctx* c = L->ctx;
+  hipStream_t s = L->stream;
+  Status* st = P<Status>(L->status);
+  HIP_OK(hipMemcpyAsync(L->h_status, st, sizeof(Status), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(L->h_hdr, L->hdr.p, sizeof(ResultHdr) * p.k, hipMemcpyDeviceToHost, s));
+  const size_t spec_n = std::min(L->out_nodes.bytes / 4, (size_t)kSpecNodes);
+  const size_t spec_a = std::min(L->out_arcs.bytes / 12, (size_t)kSpecArcs);
+  HIP_OK(hipMemcpyAsync(L->h_nodes, L->out_nodes.p, 4 * spec_n, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(L->h_arcs, L->out_arcs.p, 12 * spec_a, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  const Status hs = *L->h_status;
+  *ovf = hs.overflow;
   if (hs.overflow) {
-    *overflow = true;
-    if (c->timing) harvest_timing(c);
+    if (c->timing.load()) harvest_timing(L);
     return RAKS_OK;
   }
   const int nres = hs.nres, nsel = hs.nsel;
   const uint32_t tn = hs.out_nodes, ta = hs.out_arcs;
   std::vector<int32_t> big_nodes, big_arcs;
-  const int32_t* nodes = c->h_nodes;
-  const int32_t* arcs = c->h_arcs;
+  const int32_t* nodes = L->h_nodes;
+  const int32_t* arcs = L->h_arcs;
   if (tn > spec_n) {
     big_nodes.resize(tn);
-    HIP_OK(hipMemcpyAsync(big_nodes.data(), c->out_nodes.p, 4 * (size_t)tn, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipMemcpyAsync(big_nodes.data(), L->out_nodes.p, 4 * (size_t)tn, hipMemcpyDeviceToHost, s));
     nodes = big_nodes.data();
   }
   if (ta > spec_a) {
     big_arcs.resize((size_t)ta * 3);
-    HIP_OK(hipMemcpyAsync(big_arcs.data(), c->out_arcs.p, 12 * (size_t)ta, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipMemcpyAsync(big_arcs.data(), L->out_arcs.p, 12 * (size_t)ta, hipMemcpyDeviceToHost, s));
     arcs = big_arcs.data();
   }
-  if (tn > spec_n || ta > spec_a) HIP_OK(hipStreamSynchronize(c->stream));
+  if (tn > spec_n || ta > spec_a) HIP_OK(hipStreamSynchronize(s));
   float ms = 0;
-  (void)hipEventElapsedTime(&ms, c->q_start, c->q_end);
-  if (c->timing) harvest_timing(c);
+  (void)hipEventElapsedTime(&ms, L->q_start, L->q_end);
+  if (c->timing.load()) harvest_timing(L);
 
   raks_results* res = (raks_results*)calloc(1, sizeof(raks_results));
   if (!res) return fail(RAKS_ENOMEM, "host allocation failed");
@@ -668,7 +879,7 @@ int query_attempt(raks_ctx* c, const QueryPlan& p, raks_results** out, bool* ove
   res->r = (raks_result*)calloc(std::max(nres, 1), sizeof(raks_result));
   for (int t = 0; t < nres; ++t) {
     raks_result& o = res->r[t];
-    const ResultHdr& h = c->h_hdr[t];
+    const ResultHdr& h = L->h_hdr[t];
     o.central_node = h.central;
     o.score_c = h.score_c;
     o.score_m = h.score_m;
@@ -682,9 +893,8 @@ int query_attempt(raks_ctx* c, const QueryPlan& p, raks_results** out, bool* ove
     memcpy(ar, arcs + 3 * (size_t)h.arc_off, sizeof(raks_arc) * h.n_arcs);
     o.arcs = ar;
   }
-  const RunStatus* rs2[2] = {&hs.run[0], &hs.run[1]};
   for (int k = 0; k < 2; ++k) {
-    const RunStatus& rs = *rs2[k];
+    const RunStatus& rs = hs.run[k];
     const bool ran = (k == 0) || (p.M > 0 && nsel > 0);
     res->stats.levels[k] = ran ? rs.levels : 0;
     res->stats.end_reason[k] = ran ? rs.end_reason : END_NONE;
@@ -704,25 +914,132 @@ int query_attempt(raks_ctx* c, const QueryPlan& p, raks_results** out, bool* ove
   return RAKS_OK;
 }
 
-int query_one(raks_ctx* c, const raks_query_desc* q, raks_results** out) {
-  if (!c) return fail(RAKS_EINVAL, "ctx is NULL");
+// A whole query on one lane.  The common case is one pass with one host wait
+// at the end.  When a recovery capacity ran out, only that phase is repeated
+// (the CG phase together with everything after it, since V_C feeds the
+// marginal run), with the overflowing instances grown.
+int query_on_lane(Lane* L, const raks_query_desc* q, raks_results** out) {
+  Ctx* c = L->ctx;
   if (!out) return fail(RAKS_EINVAL, "out is NULL");
   *out = nullptr;
   if (!c->loaded) return fail(RAKS_ESTATE, "no graph loaded");
+  const double t0 = now_ms();
   QueryPlan p;
   RAKS_TRY(validate_query(c, q, p));
-  RAKS_TRY(ensure_node_buffers(c));
-  RAKS_TRY(dev_alloc(c, c->Hc, (size_t)c->n_pad * p.TPc));
-  if (p.M > 0) RAKS_TRY(dev_alloc(c, c->Hm, (size_t)c->n_pad * p.TPm));
-  for (int attempt = 0;; ++attempt) {
-    bool overflow = false;
-    RAKS_TRY(query_attempt(c, p, out, &overflow));
-    if (!overflow) return RAKS_OK;
-    if (attempt >= 6) return fail(RAKS_ENOMEM, "recovered subgraphs exceed the recovery capacity");
-    c->nc *= 4;
-    c->ac *= 4;
-    c->lcap *= 4;
+  RAKS_TRY(ensure_node_buffers(L));
+  RAKS_TRY(dev_alloc(c, L->Hc, (size_t)L->n_pad * p.TPc));
+  if (p.M > 0) RAKS_TRY(dev_alloc(c, L->Hm, (size_t)L->n_pad * p.TPm));
+  phase_reset(c, L->ph[0], p.w, p.C);
+  phase_reset(c, L->ph[1], p.k, p.M);
+  QueryRun qr;
+  RAKS_TRY(ensure_recovery(L, p));   // before any kernel of this query is queued
+  RAKS_TRY(stage_central(L, p, qr));
+  RAKS_TRY(stage_cg_recovery(L, p, qr));
+  RAKS_TRY(stage_marginal(L, p, qr));
+  RAKS_TRY(stage_output(L, p, qr));
+  int ovf = 0;
+  RAKS_TRY(collect(L, p, out, &ovf));
+  for (int attempt = 1; ovf; ++attempt) {
+    if (attempt >= kMaxAttempts)
+      return fail(RAKS_ENOMEM, "recovered subgraphs exceed the recovery capacity");
+    // collect() waited for the stream, so buffers may move now
+    if (ovf & 1) RAKS_TRY(grow_phase(L, 0, p.L));
+    else if (ovf & 2) RAKS_TRY(grow_phase(L, 1, p.L));
+    else return fail(RAKS_EDEVICE, "output arena smaller than the recovered lists (internal error)");
+    RAKS_TRY(ensure_recovery(L, p));
+    k_retry_reset<<<1, 1, 0, L->stream>>>(P<Status>(L->status));
+    if (ovf & 1) {
+      RAKS_TRY(stage_cg_recovery(L, p, qr));
+      RAKS_TRY(stage_marginal(L, p, qr));
+    }
+    RAKS_TRY(stage_output(L, p, qr));
+    RAKS_TRY(collect(L, p, out, &ovf));
   }
+  (*out)->stats.host_ms = now_ms() - t0;
+  return RAKS_OK;
+}
+
+// ------------------------------------------------------------ serving ---
+//
+// One worker thread per lane takes the oldest waiting query as soon as its
+// lane is free, so queries that arrive while others run start on the device
+// beside them.  Admission is by lanes; the queue may be bounded.
+
+void serve_worker(Ctx* c, Lane* L) {
+  (void)hipSetDevice(c->device);
+  ServeState& S = c->serve;
+  for (;;) {
+    Job* job = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(S.mu);
+      S.cv_work.wait(lk, [&] { return S.stop || !S.queue.empty(); });
+      if (S.queue.empty()) return;   // stop requested and nothing left
+      job = S.queue.front();
+      S.queue.pop_front();
+      ++S.in_flight;
+    }
+    job->t_start = now_ms();
+    g_err.clear();
+    job->rc = query_on_lane(L, &job->desc, &job->res);
+    if (job->rc) job->err = g_err;
+    job->t_done = now_ms();
+    if (job->res) {
+      job->res->stats.queue_ms = job->t_start - job->t_submit;
+      job->res->stats.host_ms = job->t_done - job->t_submit;
+    }
+    {
+      std::lock_guard<std::mutex> lk(S.mu);
+      job->done = true;
+      --S.in_flight;
+    }
+    S.cv_done.notify_all();
+  }
+}
+
+// Device bytes one lane holds on this graph (node-sized buffers for up to 16
+// keywords per run plus a recovery allowance).
+size_t lane_bytes_estimate(const Ctx* c) {
+  const size_t np = (size_t)c->n + kScanNodes;
+  return np * (16 + 16 + 1 + 16 + 8) + ((size_t)64 << 20);
+}
+
+// Drains the queue: queries already submitted still run; their results are
+// freed with the jobs nobody collected.
+void stop_serving(Ctx* c) {
+  ServeState& S = c->serve;
+  if (!S.running) return;
+  {
+    std::lock_guard<std::mutex> lk(S.mu);
+    S.stop = true;
+  }
+  S.cv_work.notify_all();
+  for (auto& t : S.workers) t.join();
+  S.workers.clear();
+  for (auto& kv : S.jobs) {
+    raks_results_free(kv.second->res);
+    delete kv.second;
+  }
+  S.jobs.clear();
+  S.queue.clear();
+  S.running = false;
+  S.stop = false;
+}
+
+int take_job(Ctx* c, uint64_t ticket, raks_results** out, bool wait) {
+  ServeState& S = c->serve;
+  std::unique_lock<std::mutex> lk(S.mu);
+  auto it = S.jobs.find(ticket);
+  if (it == S.jobs.end()) return fail(RAKS_EINVAL, "unknown ticket");
+  Job* job = it->second;
+  if (wait) S.cv_done.wait(lk, [&] { return job->done; });
+  if (!job->done) return fail(RAKS_EAGAIN, "query still running");
+  S.jobs.erase(it);
+  lk.unlock();
+  const int rc = job->rc;
+  if (rc == RAKS_OK) *out = job->res;
+  else fail(rc, job->err);
+  delete job;
+  return rc;
 }
 
 }  // namespace
@@ -733,7 +1050,7 @@ extern "C" {
 
 const char* raks_last_error(void) { return g_err.c_str(); }
 
-const char* raks_version(void) { return "raks-gfx950 0.1"; }
+const char* raks_version(void) { return "raks-gfx950 0.2"; }
 
 int raks_create(raks_ctx** out, const raks_ctx_opts* opts) {
   if (!out) return fail(RAKS_EINVAL, "out is NULL");
@@ -744,6 +1061,7 @@ int raks_create(raks_ctx** out, const raks_ctx_opts* opts) {
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
     return fail(RAKS_EDEVICE, "no HIP device");
   if (o.device < 0 || o.device >= ndev) return fail(RAKS_EINVAL, "device ordinal out of range");
+  if (o.lanes < 0 || o.lanes > kMaxLanes) return fail(RAKS_EINVAL, "lanes must be in 0..32");
   hipDeviceProp_t prop;
   HIP_OK(hipGetDeviceProperties(&prop, o.device));
   if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
@@ -756,27 +1074,16 @@ int raks_create(raks_ctx** out, const raks_ctx_opts* opts) {
   c->free_fn = o.free;
   c->alloc_user = o.alloc_user;
   c->budget = o.mem_budget;
-  if (o.stream) {
-    c->stream = (hipStream_t)o.stream;
-  } else {
-    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
-      delete c;
-      return fail(RAKS_EDEVICE, "hipStreamCreate failed");
-    }
-    c->own_stream = true;
-  }
-  if (hipHostMalloc((void**)&c->h_status, sizeof(Status), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_run, 2 * sizeof(RunStatus), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_hdr, kMaxW * sizeof(ResultHdr), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_nodes, kSpecNodes * 4, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_arcs, kSpecArcs * 12, hipHostMallocDefault) != hipSuccess ||
-      hipEventCreate(&c->lvl_ev[0]) != hipSuccess || hipEventCreate(&c->lvl_ev[1]) != hipSuccess ||
-      hipEventCreate(&c->q_start) != hipSuccess || hipEventCreate(&c->q_end) != hipSuccess) {
+  c->user_stream = (hipStream_t)o.stream;
+  if (o.rec_nodes) c->rec_nc0 = o.rec_nodes;
+  if (o.rec_arcs) c->rec_ac0 = o.rec_arcs;
+  if (o.rec_chunks) c->rec_lcap0 = o.rec_chunks;
+  const int rc = ensure_lanes(c, std::max(1, (int)o.lanes));
+  if (rc) {
+    const std::string msg = g_err;
     raks_destroy(c);
-    return fail(RAKS_EDEVICE, "host status / event allocation failed");
+    return fail(rc, msg);
   }
-  int rc = dev_alloc(c, c->status, sizeof(Status));
-  if (rc) { raks_destroy(c); return rc; }
   *out = c;
   return RAKS_OK;
 }
@@ -784,33 +1091,19 @@ int raks_create(raks_ctx** out, const raks_ctx_opts* opts) {
 int raks_destroy(raks_ctx* c) {
   if (!c) return RAKS_OK;
   (void)hipSetDevice(c->device);
-  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  stop_serving(c);
+  for (auto& L : c->lanes) lane_destroy(c, L.get());
+  c->lanes.clear();
   DevBuf* bufs[] = {&c->row_ptr, &c->col, &c->label, &c->act, &c->act_node, &c->nw, &c->kw_nodes,
-                    &c->col_s, &c->act_s, &c->eid_s, &c->row_amax, &c->bnd,
-                    &c->arc_src, &c->Hc, &c->Hm, &c->F, &c->tot, &c->off, &c->q_lo, &c->q_off, &c->q_rs,
-                    &c->q_mask, &c->cand, &c->sel_node, &c->sel_sc, &c->sel_sumh, &c->has_rpg,
-                    &c->sm, &c->key, &c->dmin, &c->ranked, &c->vc_cnt, &c->vc_tmp, &c->vc_off,
-                    &c->vc_nodes, &c->ht, &c->nl, &c->al, &c->icnt, &c->cg_nodes, &c->cg_arcs,
-                    &c->cg_cnt, &c->sort_a, &c->sort_b, &c->items, &c->lcnt, &c->hdr, &c->out_nodes, &c->out_arcs,
-                    &c->status};
+                    &c->col_s, &c->act_s, &c->eid_s, &c->row_amax, &c->bnd, &c->arc_src};
   for (DevBuf* b : bufs) dev_free(c, *b);
-  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-  if (c->q_start) (void)hipEventDestroy(c->q_start);
-  if (c->q_end) (void)hipEventDestroy(c->q_end);
-  if (c->h_status) (void)hipHostFree(c->h_status);
-  if (c->h_run) (void)hipHostFree(c->h_run);
-  if (c->h_hdr) (void)hipHostFree(c->h_hdr);
-  if (c->h_nodes) (void)hipHostFree(c->h_nodes);
-  if (c->h_arcs) (void)hipHostFree(c->h_arcs);
-  for (hipEvent_t e : c->lvl_ev)
-    if (e) (void)hipEventDestroy(e);
-  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return RAKS_OK;
 }
 
 int raks_load_graph(raks_ctx* c, const raks_graph_desc* g) {
   if (!c || !g) return fail(RAKS_EINVAL, "NULL argument");
+  if (c->serve.running) return fail(RAKS_ESTATE, "serving is running");
   HIP_OK(hipSetDevice(c->device));
   const int64_t n = g->n_nodes, A = g->n_arcs;
   if (n < 1 || n >= INT32_MAX) return fail(RAKS_EINVAL, "n_nodes out of range");
@@ -840,6 +1133,8 @@ int raks_load_graph(raks_ctx* c, const raks_graph_desc* g) {
     }
   }
   if (nkw >= (int64_t)UINT32_MAX) return fail(RAKS_EINVAL, "keyword index too large");
+  Lane* L = c->lanes[0].get();
+  hipStream_t s = L->stream;
   c->loaded = false;
   c->n = (int32_t)n;
   c->A = (uint32_t)A;
@@ -854,21 +1149,21 @@ int raks_load_graph(raks_ctx* c, const raks_graph_desc* g) {
   RAKS_TRY(dev_alloc(c, c->label, std::max<int64_t>(A, 1) * 2));
   RAKS_TRY(dev_alloc(c, c->act, std::max<int64_t>(A, 1)));
   RAKS_TRY(dev_alloc(c, c->kw_nodes, std::max<int64_t>(nkw, 1) * 4));
-  HIP_OK(hipMemcpyAsync(c->row_ptr.p, rp32.data(), (n + 1) * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_OK(hipMemcpyAsync(c->row_ptr.p, rp32.data(), (n + 1) * 4, hipMemcpyHostToDevice, s));
   if (A > 0) {
-    HIP_OK(hipMemcpyAsync(c->col.p, g->col, A * 4, hipMemcpyHostToDevice, c->stream));
-    HIP_OK(hipMemcpyAsync(c->label.p, g->label, A * 2, hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(c->col.p, g->col, A * 4, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(c->label.p, g->label, A * 2, hipMemcpyHostToDevice, s));
   }
-  if (nkw > 0) HIP_OK(hipMemcpyAsync(c->kw_nodes.p, g->kw_nodes, nkw * 4, hipMemcpyHostToDevice, c->stream));
+  if (nkw > 0) HIP_OK(hipMemcpyAsync(c->kw_nodes.p, g->kw_nodes, nkw * 4, hipMemcpyHostToDevice, s));
   if (g->act_mode == RAKS_ACT_NODE) {
     RAKS_TRY(dev_alloc(c, c->nw, n));
     RAKS_TRY(dev_alloc(c, c->act_node, n));
-    HIP_OK(hipMemcpyAsync(c->nw.p, g->node_weight, n, hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(c->nw.p, g->node_weight, n, hipMemcpyHostToDevice, s));
   }
   c->kw_ptr.assign(g->kw_ptr, g->kw_ptr + (g->n_keywords > 0 ? g->n_keywords + 1 : 0));
   if (c->kw_ptr.empty()) c->kw_ptr.push_back(0);
-  HIP_OK(hipStreamSynchronize(c->stream));
-  RAKS_TRY(compute_activation(c));
+  HIP_OK(hipStreamSynchronize(s));
+  RAKS_TRY(compute_activation(c, L));
   c->loaded = true;
   return RAKS_OK;
 }
@@ -876,10 +1171,11 @@ int raks_load_graph(raks_ctx* c, const raks_graph_desc* g) {
 int raks_set_alpha(raks_ctx* c, double alpha) {
   if (!c) return fail(RAKS_EINVAL, "ctx is NULL");
   if (!c->loaded) return fail(RAKS_ESTATE, "no graph loaded");
+  if (c->serve.running) return fail(RAKS_ESTATE, "serving is running");
   if (!(alpha > 0.0 && alpha < 1.0)) return fail(RAKS_EINVAL, "alpha must be in (0,1)");
   HIP_OK(hipSetDevice(c->device));
   c->alpha = alpha;
-  return compute_activation(c);
+  return compute_activation(c, c->lanes[0].get());
 }
 
 int raks_get_activations(raks_ctx* c, uint8_t* out, int64_t n) {
@@ -887,27 +1183,61 @@ int raks_get_activations(raks_ctx* c, uint8_t* out, int64_t n) {
   if (!c->loaded) return fail(RAKS_ESTATE, "no graph loaded");
   if (n != (int64_t)c->A) return fail(RAKS_EINVAL, "n must equal n_arcs");
   HIP_OK(hipSetDevice(c->device));
-  if (n > 0) HIP_OK(hipMemcpyAsync(out, c->act.p, n, hipMemcpyDeviceToHost, c->stream));
-  HIP_OK(hipStreamSynchronize(c->stream));
+  hipStream_t s = c->lanes[0]->stream;
+  if (n > 0) HIP_OK(hipMemcpyAsync(out, c->act.p, n, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
   return RAKS_OK;
 }
 
 int raks_query(raks_ctx* c, const raks_query_desc* q, raks_results** out) {
   if (!c) return fail(RAKS_EINVAL, "ctx is NULL");
+  if (c->serve.running) return fail(RAKS_ESTATE, "serving is running: use raks_submit");
   HIP_OK(hipSetDevice(c->device));
-  return query_one(c, q, out);
+  return query_on_lane(c->lanes[0].get(), q, out);
 }
 
 int raks_query_batch(raks_ctx* c, const raks_query_desc* qs, int32_t n, raks_results** outs) {
   if (!c || (n > 0 && (!qs || !outs))) return fail(RAKS_EINVAL, "NULL argument");
   if (n < 0) return fail(RAKS_EINVAL, "n < 0");
+  if (c->serve.running) return fail(RAKS_ESTATE, "serving is running: use raks_submit");
   HIP_OK(hipSetDevice(c->device));
   for (int32_t i = 0; i < n; ++i) outs[i] = nullptr;
-  for (int32_t i = 0; i < n; ++i) {
-    int rc = query_one(c, &qs[i], &outs[i]);
-    if (rc != RAKS_OK) {
-      for (int32_t j = 0; j <= i; ++j) { raks_results_free(outs[j]); outs[j] = nullptr; }
-      return rc;
+  const int lanes = std::min<int>((int)c->lanes.size(), std::max(n, 1));
+  std::atomic<int32_t> next{0};
+  std::vector<int> rcs(lanes, RAKS_OK);
+  std::vector<std::string> errs(lanes);
+  // Each lane takes the next query index until none is left; a failure stops
+  // the others from taking more.
+  auto work = [&](int li) {
+    (void)hipSetDevice(c->device);
+    Lane* L = c->lanes[li].get();
+    for (;;) {
+      const int32_t i = next.fetch_add(1);
+      if (i >= n) return;
+      const int rc = query_on_lane(L, &qs[i], &outs[i]);
+      if (rc) {
+        rcs[li] = rc;
+        errs[li] = g_err;
+        next.store(n);
+        return;
+      }
+    }
+  };
+  if (lanes <= 1) {
+    work(0);
+  } else {
+    std::vector<std::thread> ts;
+    for (int li = 1; li < lanes; ++li) ts.emplace_back(work, li);
+    work(0);
+    for (auto& t : ts) t.join();
+  }
+  for (int li = 0; li < lanes; ++li) {
+    if (rcs[li] != RAKS_OK) {
+      for (int32_t j = 0; j < n; ++j) {
+        raks_results_free(outs[j]);
+        outs[j] = nullptr;
+      }
+      return fail(rcs[li], errs[li]);
     }
   }
   return RAKS_OK;
@@ -923,17 +1253,93 @@ void raks_results_free(raks_results* r) {
   free(r);
 }
 
-int raks_set_timing(raks_ctx* c, int32_t enable) {
+int raks_serve_start(raks_ctx* c, const raks_serve_opts* o) {
   if (!c) return fail(RAKS_EINVAL, "ctx is NULL");
-  c->timing = enable != 0;
-  if (c->timing)
+  if (!c->loaded) return fail(RAKS_ESTATE, "no graph loaded");
+  if (c->serve.running) return fail(RAKS_ESTATE, "serving is already running");
+  int lanes = o ? o->lanes : 0;
+  const int32_t cap = o ? o->queue_cap : 0;
+  if (lanes < 0 || lanes > kMaxLanes || cap < 0) return fail(RAKS_EINVAL, "bad serving options");
+  HIP_OK(hipSetDevice(c->device));
+  if (lanes == 0) {
+    // as many lanes as half of the free device memory holds, 1..8
+    size_t free_b = 0, total_b = 0;
+    HIP_OK(hipMemGetInfo(&free_b, &total_b));
+    lanes = (int)std::max<size_t>(1, std::min<size_t>(8, free_b / 2 / lane_bytes_estimate(c)));
+  }
+  RAKS_TRY(ensure_lanes(c, lanes));
+  ServeState& S = c->serve;
+  S.queue_cap = cap;
+  S.stop = false;
+  S.running = true;
+  for (int li = 0; li < lanes; ++li)
+    S.workers.emplace_back(serve_worker, static_cast<Ctx*>(c), c->lanes[li].get());
+  return RAKS_OK;
+}
+
+int raks_submit(raks_ctx* c, const raks_query_desc* q, uint64_t* ticket) {
+  if (!c || !q || !ticket) return fail(RAKS_EINVAL, "NULL argument");
+  ServeState& S = c->serve;
+  if (!S.running) return fail(RAKS_ESTATE, "serving is not running");
+  if (q->n_central < 0 || q->n_central > kMaxKw || q->n_marginal < 0 || q->n_marginal > kMaxKw ||
+      (q->n_central > 0 && !q->central) || (q->n_marginal > 0 && !q->marginal))
+    return fail(RAKS_EINVAL, "bad keyword arrays");
+  Job* job = new Job();
+  job->central.assign(q->central, q->central + q->n_central);
+  if (q->n_marginal > 0) job->marginal.assign(q->marginal, q->marginal + q->n_marginal);
+  job->desc = *q;
+  job->desc.central = job->central.data();
+  job->desc.marginal = job->marginal.empty() ? nullptr : job->marginal.data();
+  job->t_submit = now_ms();
+  {
+    std::lock_guard<std::mutex> lk(S.mu);
+    if (S.queue_cap > 0 && (int32_t)S.queue.size() >= S.queue_cap) {
+      delete job;
+      return fail(RAKS_EAGAIN, "serving queue is full");
+    }
+    job->ticket = S.next_ticket++;
+    S.jobs[job->ticket] = job;
+    S.queue.push_back(job);
+  }
+  S.cv_work.notify_one();
+  *ticket = job->ticket;
+  return RAKS_OK;
+}
+
+int raks_poll(raks_ctx* c, uint64_t ticket, raks_results** out) {
+  if (!c || !out) return fail(RAKS_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (!c->serve.running) return fail(RAKS_ESTATE, "serving is not running");
+  return take_job(c, ticket, out, false);
+}
+
+int raks_wait(raks_ctx* c, uint64_t ticket, raks_results** out) {
+  if (!c || !out) return fail(RAKS_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (!c->serve.running) return fail(RAKS_ESTATE, "serving is not running");
+  return take_job(c, ticket, out, true);
+}
+
+int raks_serve_stop(raks_ctx* c) {
+  if (!c) return fail(RAKS_EINVAL, "ctx is NULL");
+  stop_serving(c);
+  return RAKS_OK;
+}
+
+int raks_set_timing(raks_ctx* c, int32_t mask) {
+  if (!c) return fail(RAKS_EINVAL, "ctx is NULL");
+  if (mask < 0 || mask >= (1 << kTimers)) return fail(RAKS_EINVAL, "timer mask out of range");
+  std::lock_guard<std::mutex> lk(c->timing_mu);
+  if (mask)
     for (auto& a : c->acc) a = raks_kernel_timing{};
+  c->timing.store((uint32_t)mask);
   return RAKS_OK;
 }
 
 int raks_get_timing(raks_ctx* c, int32_t kernel, raks_kernel_timing* out) {
   if (!c || !out) return fail(RAKS_EINVAL, "NULL argument");
   if (kernel < 0 || kernel >= kTimers) return fail(RAKS_EINVAL, "kernel id out of range");
+  std::lock_guard<std::mutex> lk(c->timing_mu);
   *out = c->acc[kernel];
   return RAKS_OK;
 }

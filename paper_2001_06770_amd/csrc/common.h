@@ -41,7 +41,7 @@ struct Status {
   RunStatus run[2];
   int32_t nsel;          // selected CGs (<= w)
   int32_t nres;          // ranked results (<= k)
-  int32_t overflow;      // a recovery instance ran out of scratch capacity
+  int32_t overflow;      // capacity ran out: 1 CG recovery, 2 RPG recovery, 4 output arena
   int32_t err;           // graph contract violation bits (load)
   uint64_t cmin, cmax;   // label-count extremes (load)
   uint32_t out_nodes, out_arcs;  // output arena use

@@ -33,6 +33,14 @@ template <> struct RowVec<4> { using T = uint32_t; };
 template <> struct RowVec<8> { using T = uint2; };
 template <> struct RowVec<16> { using T = uint4; };
 
+// Per-node mask of the keywords whose hitting level is finite.
+template <int TP> struct RMask { using T = uint8_t; };
+template <> struct RMask<16> { using T = uint16_t; };
+template <int TP> using RMaskT = typename RMask<TP>::T;
+// Four consecutive masks as one vector.
+template <int TP> struct RMask4 { using T = uint32_t; };
+template <> struct RMask4<16> { using T = uint2; };
+
 template <int TP>
 __device__ inline void load_row(const uint8_t* H, int64_t v, uint8_t (&b)[TP]) {
   using V = typename RowVec<TP>::T;
@@ -53,8 +61,8 @@ __global__ void k_run_reset(RunStatus* st, int32_t empty, const int32_t* nsel) {
 }
 
 template <int TP>
-__global__ __launch_bounds__(kBlock) void k_init_rows(uint8_t* H, uint8_t* F, int32_t n,
-                                                      int32_t n_pad, int32_t T) {
+__global__ __launch_bounds__(kBlock) void k_init_rows(uint8_t* H, uint8_t* F, RMaskT<TP>* R,
+                                                      int32_t n, int32_t n_pad, int32_t T) {
   uint8_t b[TP];
 #pragma unroll
   for (int i = 0; i < TP; ++i) b[i] = i < T ? kInf : 0;
@@ -63,6 +71,7 @@ __global__ __launch_bounds__(kBlock) void k_init_rows(uint8_t* H, uint8_t* F, in
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n_pad; v += stride) {
     reinterpret_cast<typename RowVec<TP>::T*>(H)[v] = pat;
+    R[v] = 0;
     if (v < n_pad / 16) reinterpret_cast<uint4*>(F)[v] = make_uint4(0, 0, 0, 0);
   }
 }
@@ -97,6 +106,7 @@ struct NodeInfo {
   uint32_t rs, lo, hi, start;   // row start; arcs of level < l end at lo, <= l end at hi
   uint32_t work;                // hi - start if the node expands
   uint32_t hw;                  // entries written at the previous level
+  uint32_t reached;             // keywords with a finite hitting level
   bool active, cand, retain;
   uint64_t key;
 };
@@ -107,12 +117,13 @@ __device__ inline NodeInfo inspect_node(const RunView& r, const DevGraphView& g,
   uint8_t b[TP];
   load_row<TP>(r.H, v, b);
   bool complete = true;
-  uint32_t mn = 0, mo = 0, mx = 0, sum = 0;
+  uint32_t mn = 0, mo = 0, mx = 0, sum = 0, rm = 0;
 #pragma unroll
   for (int i = 0; i < TP; ++i) {
     const uint32_t h = b[i];
     const bool inf = h == kInf;
     complete &= !inf;
+    rm |= (inf ? 0u : 1u) << i;
     if (h == (uint32_t)level) mn |= 1u << i;
     if (h < (uint32_t)level) mo |= 1u << i;
     mx = (!inf && h > mx) ? h : mx;
@@ -121,6 +132,7 @@ __device__ inline NodeInfo inspect_node(const RunView& r, const DevGraphView& g,
   NodeInfo o;
   o.mask_new = mn & r.tmask;
   o.mask_old = mo & r.tmask;
+  o.reached = rm & r.tmask;
   o.hw = level >= 1 ? __popc(o.mask_new) : 0;
   const bool blocked = r.block_rule && complete;
   o.rs = g.row_ptr[v];
@@ -263,10 +275,15 @@ __device__ int rpg_identify(const RunView& r, RunStatus* st, int level) {
   return s_stop;
 }
 
+// The final status of the level also goes to `mirror` (pinned host memory),
+// so the host learns it without a copy.
 template <int TP>
-__global__ __launch_bounds__(kCtl) void k_front_control(RunView r, int level) {
+__global__ __launch_bounds__(kCtl) void k_front_control(RunView r, int level, RunStatus* mirror) {
   RunStatus* st = r.st;
-  if (level > st->end_level) return;
+  if (level > st->end_level) {
+    if (threadIdx.x == 0) *mirror = *st;
+    return;
+  }
   __shared__ int32_t s_end;
   const int nb = r.nblocks;
   const int per = (nb + kCtl - 1) / kCtl;
@@ -328,6 +345,7 @@ __global__ __launch_bounds__(kCtl) void k_front_control(RunView r, int level) {
       st->e_alg += tdk;
       st->gate_pass += tgt;
     }
+    *mirror = *st;
   }
 }
 
@@ -357,6 +375,20 @@ __global__ __launch_bounds__(kBlock) void k_front_write(RunView r, DevGraphView 
   const uint32_t xc = block_exclusive_scan<uint32_t, kBlock>(nc, s32, &t);
   const uint32_t xw = block_exclusive_scan<uint32_t, kBlock>(wk, s32, &t);
   if (!fw) return;
+  // Every node whose H row changed in the previous expansion is flagged, so
+  // refreshing the masks of the flagged nodes keeps R equal to H's finite set.
+  {
+    using V4 = typename RMask4<TP>::T;
+    V4* rp = reinterpret_cast<V4*>(reinterpret_cast<RMaskT<TP>*>(r.R) + base);
+    V4 cur = *rp;
+    RMaskT<TP> m4[4];
+    __builtin_memcpy(m4, &cur, sizeof(V4));
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if ((fw >> (8 * k)) & 0xFF) m4[k] = (RMaskT<TP>)o[k].reached;
+    __builtin_memcpy(&cur, m4, sizeof(V4));
+    *rp = cur;
+  }
   const ScanOff bo = r.off[blockIdx.x];
   uint32_t qpos = bo.q + xq, wpos = bo.work + xw;
   uint32_t cpos = (st->ncand_total - st->ncand_level) + bo.cand + xc;
@@ -441,12 +473,8 @@ __global__ __launch_bounds__(kBlock) void k_expand(RunView r, DevGraphView g, in
       const uint32_t mk = s_mask[j];
       const uint32_t want = (e < s_lo[j]) ? (mk & 0xFFFFu) : ((mk & 0xFFFFu) | (mk >> 16));
       const int32_t nb = g.col_s[e];
-      uint8_t b[TP];
-      load_row<TP>(r.H, nb, b);
-      uint32_t mm = 0;
-#pragma unroll
-      for (int t = 0; t < TP; ++t) mm |= (b[t] == kInf ? 1u : 0u) << t;
-      mm &= want;
+      // keywords that have not reached nb (as of the start of this level)
+      const uint32_t mm = ~(uint32_t)reinterpret_cast<const RMaskT<TP>*>(r.R)[nb] & want;
       if (mm) {
 #pragma unroll
         for (int t = 0; t < TP; ++t)
@@ -576,7 +604,8 @@ void launch_run_init(const RunView& r, int TP, int32_t n, const int32_t* kw_node
   for (int i = 0; i < seeds.T; ++i) empty |= seeds.count[i] == 0;
   k_run_reset<<<1, 1, 0, s>>>(r.st, empty, r.kind == RUN_MARGINAL ? r.nsel : nullptr);
   const unsigned g = (unsigned)std::min<int64_t>(8192, (r.n_pad + kBlock - 1) / kBlock);
-  RAKS_TP_DISPATCH(TP, k_init_rows<kTP><<<g, kBlock, 0, s>>>(r.H, r.F, n, r.n_pad, r.T));
+  RAKS_TP_DISPATCH(TP, k_init_rows<kTP><<<g, kBlock, 0, s>>>(
+                           r.H, r.F, reinterpret_cast<RMaskT<kTP>*>(r.R), n, r.n_pad, r.T));
   const uint32_t total = seeds.prefix[seeds.T];
   if (total > 0) {
     const unsigned gs = (unsigned)std::min<uint32_t>(4096, (total + kBlock - 1) / kBlock);
@@ -589,8 +618,9 @@ void launch_front_count(const RunView& r, int TP, const DevGraphView& g, int lev
   RAKS_TP_DISPATCH(TP, k_front_count<kTP><<<r.nblocks, kBlock, 0, s>>>(r, g, level));
 }
 
-void launch_front_control(const RunView& r, int TP, int level, hipStream_t s) {
-  RAKS_TP_DISPATCH(TP, k_front_control<kTP><<<1, kCtl, 0, s>>>(r, level));
+void launch_front_control(const RunView& r, int TP, int level, RunStatus* mirror,
+                          hipStream_t s) {
+  RAKS_TP_DISPATCH(TP, k_front_control<kTP><<<1, kCtl, 0, s>>>(r, level, mirror));
 }
 
 void launch_front_write(const RunView& r, int TP, const DevGraphView& g, int level, hipStream_t s) {

@@ -46,6 +46,8 @@ struct RunView {
   int32_t block_rule;    // 1: a node reached by every keyword stops expanding (CF)
   uint8_t* H;            // node-keyword matrix [n_pad][TP]; INF = 0xFF, padding bytes 0
   uint8_t* F;            // frontier flags [n_pad]
+  void* R;               // reached-keyword mask per node [n_pad] (u8; u16 when TP == 16):
+                         // bit i set iff h_vi is finite at the start of the level
   int32_t n_pad;         // n rounded up to kScanNodes
   RunStatus* st;
   ScanTot* tot;          // [nblocks]
@@ -108,6 +110,17 @@ struct RecItem {
 
 constexpr uint32_t kRecChunk = 256;
 
+// Storage of one recovery instance.  Its node set is an open-addressing table
+// of hcap slots, or (dense) a bitmap of n bits; its node and arc lists hold
+// ncap / acap entries.  Counts continue past the capacities, so after an
+// overflow the host knows (or bounds from below) what the instance needs.
+struct InstCap {
+  uint64_t hoff;   // node set at hpool + hoff
+  uint64_t noff;   // node list at nl + noff
+  uint64_t aoff;   // arc list at al + aoff
+  uint32_t hcap, ncap, acap, dense;
+};
+
 struct RecoverView {
   DevGraphView g;
   const uint8_t* H;
@@ -121,15 +134,18 @@ struct RecoverView {
   const uint32_t* vc_off;
   const int32_t* vc_nodes;
   const uint8_t* dmin;       // [nsel][kMaxKw]
-  uint32_t* ht;              // [n_inst][hc] node hash set per instance
-  int32_t* nl;               // [n_inst][nc] recovered nodes
-  uint32_t* al;              // [n_inst][ac] recovered arcs (CSR position of n -> q)
-  uint32_t* cnt;             // [n_inst][2] node / arc counters (may exceed capacity: overflow)
-  uint32_t hc, nc, ac;
+  const InstCap* caps;       // [n_inst]
+  uint32_t* hpool;           // node sets
+  int32_t* nl;               // node lists
+  uint32_t* al;              // arc lists (CSR position of n -> q)
+  uint32_t* cnt;             // [n_inst][2] nodes / arcs found
+  uint32_t* iflag;           // [n_inst] 1: the node table filled up (nodes were lost)
+  uint32_t dwords;           // words of a dense node set
   RecItem* items;            // [max_layer + 1][lcap] work chunks per layer
-  uint32_t* lcnt;            // [max_layer + 1]
+  uint32_t* lcnt;            // [max_layer + 1] chunks requested per layer
   uint32_t lcap;
   int32_t max_layer;
+  int32_t ovf_bit;           // bit set in gst->overflow when a capacity runs out
   Status* gst;
 };
 
@@ -142,24 +158,26 @@ struct FinalizeView {
   const int32_t* n_valid;    // device: results that exist
   const int32_t* sel_node;
   const int32_t* ranked;
+  const InstCap* caps;       // [n_res * T]
   const int32_t* nl;
   const uint32_t* al;
   const uint32_t* cnt;
-  uint32_t nc, ac;
-  // CG lists (written when marginal == 0, read when marginal == 1)
-  uint32_t* cg_nodes;        // [nsel][cg_ncap]
-  uint32_t* cg_arcs;         // [nsel][cg_acap]
+  // CG lists (written when marginal == 0, read when marginal == 1); CG r owns
+  // cg_nodes / vc_tmp from cg_noff[r] and cg_arcs from cg_aoff[r]
+  uint32_t* cg_nodes;
+  uint32_t* cg_arcs;
   uint32_t* cg_cnt;          // [nsel][2]
-  uint32_t cg_ncap, cg_acap;
+  const uint64_t* cg_noff;
+  const uint64_t* cg_aoff;
   // V_C (marginal == 0): nodes with some central hitting level 0
   const uint8_t* Hc;
   int32_t TPc, Tc;
   uint32_t* vc_cnt;          // [nsel]
-  int32_t* vc_tmp;           // [nsel][cg_ncap]
-  // sort scratch, per workgroup
-  uint32_t* sort_a;          // [n_res][scap]
+  int32_t* vc_tmp;
+  // sort scratch of result t: sort_a / sort_b from soff[t] to soff[t + 1]
+  uint32_t* sort_a;
   uint32_t* sort_b;
-  uint32_t scap;
+  const uint64_t* soff;
   // final output (marginal == 1 or no marginal keywords)
   int32_t write_output;
   ResultHdr* hdr;
@@ -190,8 +208,8 @@ __device__ inline uint32_t row_of(const uint32_t* row_ptr, int32_t n, uint32_t e
   return (uint32_t)upper_index<uint32_t>(row_ptr, 0, n + 1, e);
 }
 
-void launch_pack_vc(const uint32_t* vc_cnt, const int32_t* vc_tmp, uint32_t cg_ncap, const int32_t* nsel,
-                    uint32_t* vc_off, int32_t* vc_nodes, hipStream_t s);
+void launch_pack_vc(const uint32_t* vc_cnt, const int32_t* vc_tmp, const uint64_t* cg_noff,
+                    const int32_t* nsel, uint32_t* vc_off, int32_t* vc_nodes, hipStream_t s);
 void launch_check_and_count(const DevGraphView& g, uint32_t* c_tmp, int32_t* arc_src, Status* st,
                             hipStream_t s);
 void launch_act_edge(const DevGraphView& g, const uint32_t* c_tmp, const Status* st, double abar,
@@ -204,7 +222,9 @@ void launch_act_node(const DevGraphView& g, const uint8_t* nw, Status* st, doubl
 void launch_run_init(const RunView& r, int TP, int32_t n, const int32_t* kw_nodes,
                      const SeedList& seeds, hipStream_t s);
 void launch_front_count(const RunView& r, int TP, const DevGraphView& g, int level, hipStream_t s);
-void launch_front_control(const RunView& r, int TP, int level, hipStream_t s);
+// mirror: device-visible pinned host memory that receives the level's status
+void launch_front_control(const RunView& r, int TP, int level, RunStatus* mirror,
+                          hipStream_t s);
 void launch_front_write(const RunView& r, int TP, const DevGraphView& g, int level, hipStream_t s);
 void launch_expand(const RunView& r, int TP, const DevGraphView& g, int level, int grid,
                    hipStream_t s);

@@ -11,10 +11,12 @@
 // at most 256 that go to the work list of its layer; one wavefront takes a
 // chunk, so a hub's arcs spread over the whole GPU.  Only arcs of level below
 // the layer can qualify; they are a prefix of the node's level-sorted row, so
-// a hub whose arcs all have high levels costs nothing.  Each
-// instance has a hash set of nodes in global memory (open addressing), a node
-// list and an arc list; capacities are fixed per launch and running out sets
-// a flag on which the host repeats the phase with larger buffers.
+// a hub whose arcs all have high levels costs nothing.  Each instance has its
+// own node set (open addressing, or a bitmap of n bits once a table was too
+// small), node list and arc list, with capacities of its own.  Nodes and arcs
+// are counted even when a list is full, and the search goes on, so an
+// overflow tells the host how much the instance needs; the host then repeats
+// only the phase that overflowed, with only the overflowing instances grown.
 #include "common.h"
 #include "kernels.h"
 
@@ -36,48 +38,70 @@ __device__ inline bool ht_insert(uint32_t* ht, uint32_t hc, uint32_t key, int* f
 
 // Node n (hitting level hn in this instance's column) is recovered: record
 // it once per instance and queue its arcs on layer hn.
-__device__ inline void rec_discover(const RecoverView& v, uint32_t inst, int32_t n, uint32_t hn) {
-  int full = 0;
-  if (ht_insert(v.ht + (size_t)inst * v.hc, v.hc, (uint32_t)n, &full)) {
-    const uint32_t slot = atomicAdd(&v.cnt[inst * 2], 1u);
-    if (slot < v.nc) v.nl[(size_t)inst * v.nc + slot] = n;
-    else atomicOr(&v.gst->overflow, 1);
-    if (hn >= 1 && (int)hn <= v.max_layer) {
-      // in-arcs m -> n that can meet h_n = 1 + max(a, h_m) have a <= h_n - 1:
-      // a prefix of n's level-sorted row (EDGE), or all arcs when the node's
-      // own level is below h_n (NODE: every in-arc of n has the level of n)
-      const uint32_t rs = v.g.row_ptr[n];
-      const uint32_t deg = v.g.mode ? ((uint32_t)v.g.act_node[n] < hn ? v.g.row_ptr[n + 1] - rs : 0u)
-                                    : count_le(v.g, n, (int)hn - 1);
-      const uint32_t k = (deg + kRecChunk - 1) / kRecChunk;
-      if (k > 0) {
-        const uint32_t base = atomicAdd(&v.lcnt[hn], k);
-        if (base + k > v.lcap) {
-          atomicOr(&v.gst->overflow, 1);
-        } else {
-          RecItem* dst = v.items + (size_t)hn * v.lcap + base;
-          for (uint32_t c = 0; c < k; ++c) {
-            RecItem it;
-            it.inst = inst;
-            it.q = n;
-            it.start = rs + c * kRecChunk;
-            it.len = min(kRecChunk, deg - c * kRecChunk);
-            dst[c] = it;
-          }
+__device__ inline void rec_discover(const RecoverView& v, uint32_t inst, const InstCap& ic,
+                                    int32_t n, uint32_t hn) {
+  bool fresh;
+  if (ic.dense) {
+    uint32_t* w = v.hpool + ic.hoff + ((uint32_t)n >> 5);
+    const uint32_t bit = 1u << ((uint32_t)n & 31u);
+    fresh = (atomicOr(w, bit) & bit) == 0;
+  } else {
+    int full = 0;
+    fresh = ht_insert(v.hpool + ic.hoff, ic.hcap, (uint32_t)n, &full);
+    if (full) {
+      v.iflag[inst] = 1;
+      atomicOr(&v.gst->overflow, v.ovf_bit);
+    }
+  }
+  if (!fresh) return;
+  const uint32_t slot = atomicAdd(&v.cnt[inst * 2], 1u);
+  if (slot < ic.ncap) v.nl[ic.noff + slot] = n;
+  else atomicOr(&v.gst->overflow, v.ovf_bit);
+  if (hn >= 1 && (int)hn <= v.max_layer) {
+    // in-arcs m -> n that can meet h_n = 1 + max(a, h_m) have a <= h_n - 1:
+    // a prefix of n's level-sorted row (EDGE), or all arcs when the node's
+    // own level is below h_n (NODE: every in-arc of n has the level of n)
+    const uint32_t rs = v.g.row_ptr[n];
+    const uint32_t deg = v.g.mode ? ((uint32_t)v.g.act_node[n] < hn ? v.g.row_ptr[n + 1] - rs : 0u)
+                                  : count_le(v.g, n, (int)hn - 1);
+    const uint32_t k = (deg + kRecChunk - 1) / kRecChunk;
+    if (k > 0) {
+      const uint32_t base = atomicAdd(&v.lcnt[hn], k);
+      if (base + k > v.lcap) {
+        atomicOr(&v.gst->overflow, v.ovf_bit);
+      } else {
+        RecItem* dst = v.items + (size_t)hn * v.lcap + base;
+        for (uint32_t c = 0; c < k; ++c) {
+          RecItem it;
+          it.inst = inst;
+          it.q = n;
+          it.start = rs + c * kRecChunk;
+          it.len = min(kRecChunk, deg - c * kRecChunk);
+          dst[c] = it;
         }
       }
     }
   }
-  if (full) atomicOr(&v.gst->overflow, 1);
 }
 
+// Clears the node sets and counters of the live instances: row y of the grid
+// takes instance y.
 __global__ __launch_bounds__(kBlock) void k_rec_clear(RecoverView v) {
-  const size_t live = (size_t)min(v.n_inst, *v.n_valid * v.T);
-  const size_t total = live * v.hc;
-  const size_t stride = (size_t)gridDim.x * kBlock;
-  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += stride) v.ht[i] = kEmpty;
-  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < 2 * (size_t)v.n_inst; i += stride) v.cnt[i] = 0;
-  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i <= (size_t)v.max_layer; i += stride) v.lcnt[i] = 0;
+  const uint32_t inst = blockIdx.y;
+  if (inst == 0 && blockIdx.x == 0)
+    for (int i = threadIdx.x; i <= v.max_layer; i += kBlock) v.lcnt[i] = 0;
+  if ((int)(inst / v.T) >= *v.n_valid) return;
+  const InstCap ic = v.caps[inst];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    v.cnt[inst * 2] = 0;
+    v.cnt[inst * 2 + 1] = 0;
+    v.iflag[inst] = 0;
+  }
+  const size_t words = ic.dense ? (size_t)v.dwords : (size_t)ic.hcap;
+  const uint32_t fill = ic.dense ? 0u : kEmpty;
+  uint32_t* p = v.hpool + ic.hoff;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < words; i += (size_t)gridDim.x * kBlock)
+    p[i] = fill;
 }
 
 // Start nodes: the central node (central graphs), or the V_C nodes whose
@@ -87,17 +111,18 @@ __global__ __launch_bounds__(kBlock) void k_rec_seed(RecoverView v) {
   const uint32_t inst = blockIdx.x;
   const int res = inst / v.T, col = inst % v.T;
   if (res >= *v.n_valid) return;
+  const InstCap ic = v.caps[inst];
   if (!v.marginal) {
     if (threadIdx.x == 0) {
       const int32_t c = v.sel_node[res];
-      rec_discover(v, inst, c, v.H[(int64_t)c * TP + col]);
+      rec_discover(v, inst, ic, c, v.H[(int64_t)c * TP + col]);
     }
   } else {
     const int r = v.ranked[res];
     const uint8_t d = v.dmin[r * kMaxKw + col];
     for (uint32_t p = v.vc_off[r] + threadIdx.x; p < v.vc_off[r + 1]; p += kBlock) {
       const int32_t x = v.vc_nodes[p];
-      if (v.H[(int64_t)x * TP + col] == d) rec_discover(v, inst, x, d);
+      if (v.H[(int64_t)x * TP + col] == d) rec_discover(v, inst, ic, x, d);
     }
   }
 }
@@ -111,6 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_rec_layer(RecoverView v, int h) {
   const DevGraphView& g = v.g;
   for (uint32_t it = blockIdx.x * (kBlock / kWave) + wave_id(); it < n_items; it += waves) {
     const RecItem item = list[it];
+    const InstCap ic = v.caps[item.inst];
     const int col = item.inst % v.T;
     const int32_t q = item.q;
     const uint32_t aq = g.mode ? g.act_node[q] : 0u;   // NODE mode: level of the in-arc's target q
@@ -124,9 +150,9 @@ __global__ __launch_bounds__(kBlock) void k_rec_layer(RecoverView v, int h) {
       if (a + 1 != (uint32_t)h && hn + 1 != (uint32_t)h) continue;   // h = 1 + max(a, h_n)
       const uint32_t fwd = find_arc_dev(g.row_ptr, g.col, g.label, n, g.label[g.eid_s[e]], q);
       const uint32_t sa = atomicAdd(&v.cnt[item.inst * 2 + 1], 1u);
-      if (sa < v.ac) v.al[(size_t)item.inst * v.ac + sa] = fwd;
-      else atomicOr(&v.gst->overflow, 1);
-      rec_discover(v, item.inst, n, hn);
+      if (sa < ic.acap) v.al[ic.aoff + sa] = fwd;
+      else atomicOr(&v.gst->overflow, v.ovf_bit);
+      rec_discover(v, item.inst, ic, n, hn);
     }
   }
 }
@@ -141,8 +167,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeView v) {
   __shared__ RadixLds lds;
   __shared__ uint32_t s_off;
   __shared__ uint32_t s_sa[kLdsSort], s_sb[kLdsSort];
-  uint32_t* A_g = v.sort_a + (size_t)t * v.scap;
-  uint32_t* B_g = v.sort_b + (size_t)t * v.scap;
+  uint32_t* A_g = v.sort_a + v.soff[t];
+  uint32_t* B_g = v.sort_b + v.soff[t];
   const int r = v.marginal ? v.ranked[t] : t;
   const DevGraphView& g = v.g;
 
@@ -150,7 +176,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeView v) {
     // total input size first: small lists are sorted in LDS
     uint32_t n = v.marginal ? v.cg_cnt[r * 2 + pass] : 0u;
     for (int j = 0; j < v.T; ++j)
-      n += min(v.cnt[(t * v.T + j) * 2 + pass], pass == 0 ? v.nc : v.ac);
+      n += min(v.cnt[(t * v.T + j) * 2 + pass],
+               pass == 0 ? v.caps[t * v.T + j].ncap : v.caps[t * v.T + j].acap);
     const bool small = n <= kLdsSort;
     uint32_t* A = small ? s_sa : A_g;
     uint32_t* B = small ? s_sb : B_g;
@@ -158,19 +185,19 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeView v) {
     n = 0;
     if (v.marginal) {
       const uint32_t cnt = v.cg_cnt[r * 2 + pass];
-      const uint32_t* src = pass == 0 ? v.cg_nodes + (size_t)r * v.cg_ncap
-                                      : v.cg_arcs + (size_t)r * v.cg_acap;
+      const uint32_t* src = pass == 0 ? v.cg_nodes + v.cg_noff[r] : v.cg_arcs + v.cg_aoff[r];
       for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) A[i] = src[i];
       n = cnt;
     }
     for (int j = 0; j < v.T; ++j) {
       const int inst = t * v.T + j;
-      const uint32_t cnt = min(v.cnt[inst * 2 + pass], pass == 0 ? v.nc : v.ac);
+      const InstCap ic = v.caps[inst];
+      const uint32_t cnt = min(v.cnt[inst * 2 + pass], pass == 0 ? ic.ncap : ic.acap);
       if (pass == 0) {
-        const int32_t* src = v.nl + (size_t)inst * v.nc;
+        const int32_t* src = v.nl + ic.noff;
         for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) A[n + i] = (uint32_t)src[i];
       } else {
-        const uint32_t* src = v.al + (size_t)inst * v.ac;
+        const uint32_t* src = v.al + ic.aoff;
         for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) A[n + i] = src[i];
       }
       n += cnt;
@@ -181,12 +208,12 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeView v) {
     const uint32_t m = wg_unique_u32(sorted, n, uniq, lds.scan);
     __syncthreads();
     if (!v.marginal) {
-      uint32_t* dst = pass == 0 ? v.cg_nodes + (size_t)r * v.cg_ncap : v.cg_arcs + (size_t)r * v.cg_acap;
+      uint32_t* dst = pass == 0 ? v.cg_nodes + v.cg_noff[r] : v.cg_arcs + v.cg_aoff[r];
       for (uint32_t i = threadIdx.x; i < m; i += kBlock) dst[i] = uniq[i];
       if (threadIdx.x == 0) v.cg_cnt[r * 2 + pass] = m;
       if (pass == 0) {
         // V_C in node order
-        int32_t* vc = v.vc_tmp + (size_t)r * v.cg_ncap;
+        int32_t* vc = v.vc_tmp + v.cg_noff[r];
         uint32_t written = 0;
         for (uint32_t t0 = 0; t0 < m; t0 += kBlock) {
           const uint32_t i = t0 + threadIdx.x;
@@ -207,7 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeView v) {
       if (threadIdx.x == 0) {
         const uint32_t off = atomicAdd(pass == 0 ? &v.gst->out_nodes : &v.gst->out_arcs, m);
         const uint32_t cap = pass == 0 ? v.out_ncap : v.out_acap;
-        if (off + m > cap) atomicOr(&v.gst->overflow, 2);
+        if (off + m > cap) atomicOr(&v.gst->overflow, 4);
         s_off = off;
         ResultHdr& hd = v.hdr[t];
         if (pass == 0) {
@@ -245,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeView v) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_pack_vc(const uint32_t* vc_cnt, const int32_t* vc_tmp,
-                                                    uint32_t cg_ncap, const int32_t* nsel_p,
+                                                    const uint64_t* cg_noff, const int32_t* nsel_p,
                                                     uint32_t* vc_off, int32_t* vc_nodes) {
   __shared__ uint32_t s_off[kMaxW + 1];
   const int nsel = *nsel_p;
@@ -257,16 +284,17 @@ __global__ __launch_bounds__(kBlock) void k_pack_vc(const uint32_t* vc_cnt, cons
   __syncthreads();
   for (int r = threadIdx.x; r <= nsel; r += kBlock) vc_off[r] = s_off[r];
   for (int r = 0; r < nsel; ++r) {
-    const int32_t* src = vc_tmp + (size_t)r * cg_ncap;
+    const int32_t* src = vc_tmp + cg_noff[r];
     for (uint32_t i = threadIdx.x; i < vc_cnt[r]; i += kBlock) vc_nodes[s_off[r] + i] = src[i];
   }
 }
 
 void launch_recover(const RecoverView& v, hipStream_t s) {
   if (v.n_inst <= 0) return;
-  const size_t clear_items = (size_t)v.n_inst * v.hc;
-  const unsigned gc = (unsigned)std::min<size_t>(2048, (clear_items + kBlock - 1) / kBlock + 1);
-  k_rec_clear<<<gc, kBlock, 0, s>>>(v);
+  // enough blocks per instance for a dense node set; tables of sparse ones
+  // are small
+  const unsigned gx = (unsigned)std::min<size_t>(64, ((size_t)v.dwords + kBlock - 1) / kBlock + 1);
+  k_rec_clear<<<dim3(gx, (unsigned)v.n_inst), kBlock, 0, s>>>(v);
   const unsigned grid = 1024;
   switch (v.TP) {
     case 4:
@@ -288,9 +316,9 @@ void launch_finalize(const FinalizeView& v, hipStream_t s) {
   if (v.n_res > 0) k_finalize<<<v.n_res, kBlock, 0, s>>>(v);
 }
 
-void launch_pack_vc(const uint32_t* vc_cnt, const int32_t* vc_tmp, uint32_t cg_ncap, const int32_t* nsel,
-                    uint32_t* vc_off, int32_t* vc_nodes, hipStream_t s) {
-  k_pack_vc<<<1, kBlock, 0, s>>>(vc_cnt, vc_tmp, cg_ncap, nsel, vc_off, vc_nodes);
+void launch_pack_vc(const uint32_t* vc_cnt, const int32_t* vc_tmp, const uint64_t* cg_noff,
+                    const int32_t* nsel, uint32_t* vc_off, int32_t* vc_nodes, hipStream_t s) {
+  k_pack_vc<<<1, kBlock, 0, s>>>(vc_cnt, vc_tmp, cg_noff, nsel, vc_off, vc_nodes);
 }
 
 }  // namespace raks

@@ -1,0 +1,154 @@
+// runtime.h -- host-side state of the RAKS library: the context (graph,
+// allocator) and its lanes (per-query workspaces, each with its own HIP
+// stream), plus the serving queue.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/raks.h"
+#include "common.h"
+#include "kernels.h"
+
+namespace raks {
+
+constexpr int kTimers = 5;
+constexpr size_t kSpecNodes = 1 << 16;   // output read back with the headers
+constexpr size_t kSpecArcs = 1 << 16;
+constexpr int kMaxLanes = 32;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+template <typename T>
+T* P(DevBuf& b) { return reinterpret_cast<T*>(b.p); }
+
+struct Ctx;
+
+// Recovery capacities of one phase (Algorithm 2 over CGs, or over RPGs plus
+// the output): per instance node / arc list capacities and the kind of node
+// set, the per-layer work-list capacity, and the derived layout uploaded to
+// the device (InstCap table, CG list offsets, sort scratch offsets).
+struct RecPhase {
+  int32_t n_inst = 0, n_res = 0, T = 0;
+  bool grown = false;                 // capacities differ from the defaults
+  std::vector<uint32_t> ncap, acap;
+  std::vector<uint8_t> dense;
+  uint32_t lcap = 0;
+  // derived
+  std::vector<InstCap> caps;
+  std::vector<uint64_t> cg_noff, cg_aoff, soff;   // [n_res + 1]
+  uint64_t h_words = 0, n_total = 0, a_total = 0;
+  uint64_t cg_nmax = 0, cg_amax = 0;              // largest CG lists (phase 0)
+  uint64_t out_n = 0, out_a = 0;                  // output bound (phase 1)
+  bool dirty = true;                              // layout not uploaded yet
+  DevBuf layout;                                  // caps | cg_noff | cg_aoff | soff
+  size_t lay_cg_noff = 0, lay_cg_aoff = 0, lay_soff = 0;
+  void* stage = nullptr;                          // pinned staging of the layout
+  size_t stage_bytes = 0;
+  DevBuf cnt, iflag, lcnt;                        // device counters of the phase
+};
+
+// Everything one query needs besides the graph.  A lane runs one query at a
+// time on its own stream.
+struct Lane {
+  Ctx* ctx = nullptr;
+  int id = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+
+  int32_t n_pad = 0, nblocks = 0;
+  DevBuf Hc, Hm, F, R, tot, off, q_off, q_rs, q_lo, q_mask, cand;
+  DevBuf sel_node, sel_sc, sel_sumh, has_rpg, sm, key, dmin, ranked;
+  DevBuf vc_cnt, vc_tmp, vc_off, vc_nodes;
+  // recovery storage, shared by both phases (sized for the larger one)
+  DevBuf hpool, nl, al, items, sort_a, sort_b;
+  DevBuf cg_nodes, cg_arcs, cg_cnt;   // CG lists, kept for the marginal phase
+  DevBuf hdr, out_nodes, out_arcs, status;
+  RecPhase ph[2];                     // [0] CG recovery, [1] RPG recovery + output
+  Status* h_status = nullptr;   // pinned
+  RunStatus* h_run = nullptr;   // pinned [2]: per-level status, double-buffered
+  RunStatus* d_run = nullptr;   // the same memory as the device addresses it
+  ResultHdr* h_hdr = nullptr;   // pinned [kMaxW]
+  int32_t* h_nodes = nullptr;   // pinned [kSpecNodes]
+  int32_t* h_arcs = nullptr;    // pinned [3 * kSpecArcs]
+  hipEvent_t lvl_ev[2] = {nullptr, nullptr};
+  hipEvent_t q_start = nullptr, q_end = nullptr;
+
+  // event timing (enabled by the context)
+  struct Pending { hipEvent_t a, b; int kind; double bytes; int level, run; };
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<Pending> pending;
+};
+
+struct Job {
+  uint64_t ticket = 0;
+  std::vector<int32_t> central, marginal;
+  raks_query_desc desc = {};
+  raks_results* res = nullptr;
+  int rc = 0;
+  std::string err;
+  bool done = false;
+  double t_submit = 0, t_start = 0, t_done = 0;
+};
+
+struct ServeState {
+  bool running = false;
+  bool stop = false;
+  int32_t queue_cap = 0;
+  std::vector<std::thread> workers;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Job*> queue;
+  std::unordered_map<uint64_t, Job*> jobs;
+  uint64_t next_ticket = 1;
+  int in_flight = 0;
+};
+
+struct Ctx {
+  int device = 0;
+  int num_cu = 256;
+  raks_alloc_fn alloc = nullptr;
+  raks_free_fn free_fn = nullptr;
+  void* alloc_user = nullptr;
+  uint64_t budget = 0;
+  uint64_t in_use = 0;
+  std::mutex mem_mu;
+  hipStream_t user_stream = nullptr;
+  uint32_t rec_nc0 = 4096, rec_ac0 = 16384, rec_lcap0 = 1u << 16;   // initial recovery capacities
+
+  // graph
+  bool loaded = false;
+  int32_t n = 0;
+  uint32_t A = 0;
+  int32_t vocab = 0;
+  int32_t mode = 0;
+  double abar = 0, alpha = 0;
+  DevBuf row_ptr, col, label, act, act_node, nw, kw_nodes, col_s, act_s, eid_s, row_amax, bnd,
+      arc_src;
+  int32_t nbnd = 1;
+  std::vector<int64_t> kw_ptr;
+
+  std::vector<std::unique_ptr<Lane>> lanes;
+
+  // timing
+  std::atomic<uint32_t> timing{0};   // bit k: timer k is recorded
+  std::mutex timing_mu;
+  raks_kernel_timing acc[kTimers] = {};
+
+  ServeState serve;
+};
+
+}  // namespace raks

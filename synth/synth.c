@@ -31,6 +31,7 @@
  *      rounded to two decimals and returned as an integer x100.
  */
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
@@ -262,7 +263,17 @@ static int64_t estimate_abar_x100(const synth_graph* g, const synth_params* p) {
     return (int64_t)floor(mean * 100.0 + 0.5);
 }
 
+/* Phase lines on stderr when SYNTH_PROGRESS is set (long generations). */
+static void progress(const char* what, double t0) {
+    const char* e = getenv("SYNTH_PROGRESS");
+    if (e && *e && *e != '0') {
+        fprintf(stderr, "[synth] %s (%.1f s)\n", what, omp_get_wtime() - t0);
+        fflush(stderr);
+    }
+}
+
 synth_graph* synth_generate(const synth_params* p) {
+    const double t_start = omp_get_wtime();
     const int64_t n = p->n_nodes, E = p->n_edges;
     if (n < 2 || E < 1 || p->n_labels < 1 || p->n_labels > 65536 || p->vocab < 1 ||
         p->kw_min < 0 || p->kw_max < p->kw_min || p->kw_max > p->vocab || p->n_hubs < 0 ||
@@ -311,6 +322,7 @@ synth_graph* synth_generate(const synth_params* p) {
     free(w); w = NULL;
     free(perm); perm = NULL;
 
+    progress("degree weights", t_start);
     /* 2.-3. directed edges, deduplicated to exactly E */
     uint64_t* keys = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(2 * E));
     if (!keys) goto fail;
@@ -357,6 +369,7 @@ synth_graph* synth_generate(const synth_params* p) {
         if (m != E) goto fail;
         alias_free(&src_al); alias_free(&dst_al);
 
+        progress("directed edges", t_start);
         /* 4. node weights from directed in-degree */
         int64_t* indeg = (int64_t*)calloc((size_t)n, sizeof(int64_t));
         g->node_weight = (uint8_t*)malloc((size_t)n);
@@ -392,6 +405,7 @@ synth_graph* synth_generate(const synth_params* p) {
         for (int64_t v = 0; v < n; ++v) g->row_ptr[v + 1] += g->row_ptr[v];
     }
     free(keys); keys = NULL;
+    progress("bi-directed CSR", t_start);
 
     /* 6. keywords per node, Zipf popularity */
     {
@@ -437,8 +451,10 @@ synth_graph* synth_generate(const synth_params* p) {
         free(fill); free(tags); free(ntag);
     }
 
+    progress("keywords", t_start);
     /* 7. A-bar from sampled pairs */
     g->abar_x100 = estimate_abar_x100(g, p);
+    progress("average hop count", t_start);
     if (g->abar_x100 <= 0) goto fail;
     return g;
 

@@ -72,8 +72,9 @@ def main():
               f"{res['stats'][0]['e_arc'] + res['stats'][1]['e_arc']} ({time.time() - t1:.1f} s)",
               flush=True)
     path = os.path.join(HERE, f"{name}_queries.json")
-    with open(path, "w") as f:
+    with open(path + ".tmp", "w") as f:
         json.dump(out, f, indent=1)
+    os.replace(path + ".tmp", path)
     print(f"wrote {path} ({time.time() - t0:.0f} s total)")
 
 

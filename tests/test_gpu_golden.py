@@ -1,0 +1,77 @@
+"""Full-size parity: the large (20M nodes, 200M edges, hubs above 1M degree),
+batch (20M nodes, 200M edges) and serving (50M nodes, 500M edges) workloads
+against expected values the reference implementation wrote
+(tests/golden/make_golden.py; the reference takes minutes per graph on one
+core, too long to run beside the GPU).  Checked bit-exactly: the SHA-256 of
+all activation levels, and per sampled query the status, the counters of both
+runs and every result (central node, scores, key, sizes, SHA-256 of the node
+and arc lists).  The batch workload's sample runs as one batch over 4 lanes."""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def golden(name):
+    path = os.path.join(HERE, "golden", f"{name}_queries.json")
+    if not os.path.exists(path):
+        pytest.skip(f"no expected values for {name}")
+    with open(path) as f:
+        return json.load(f)
+
+
+def digest(res):
+    out = {"status": res["status"], "n_cg": res["n_cg"],
+           "stats": [{k: v for k, v in s.items()} for s in res["stats"]], "results": []}
+    for r in res["results"]:
+        nodes = np.asarray(r["nodes"], np.int32)
+        arcs = np.asarray(r["arcs"], np.int32).reshape(-1, 3)
+        out["results"].append({
+            "central": r["central"], "score_c": r["score_c"], "score_m": r["score_m"],
+            "key": r["key"], "n_nodes": int(nodes.shape[0]), "n_arcs": int(arcs.shape[0]),
+            "nodes_sha256": hashlib.sha256(nodes.tobytes()).hexdigest(),
+            "arcs_sha256": hashlib.sha256(arcs.tobytes()).hexdigest()})
+    return out
+
+
+def expected(entry):
+    return {k: entry[k] for k in ("status", "n_cg", "stats", "results")}
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", ["large", "batch", "serve"])
+def test_full_size_golden(name):
+    import paper_2001_06770_amd as raks
+    gold = golden(name)
+    print(f"[golden] generating {name}", flush=True)
+    g = synth.make_graph(name)
+    assert g.n_arcs == gold["n_arcs"] and g.abar_x100 == gold["abar_x100"]
+    c = raks.Context(0, lanes=4)
+    try:
+        c.load_graph(g, alpha=gold["alpha"])
+        if "act_sha256" in gold:
+            act = c.activations()
+            assert hashlib.sha256(act.tobytes()).hexdigest() == gold["act_sha256"]
+            del act
+        qs = [synth.Query(tuple(e["central"]), tuple(e["marginal"]), e["k"], e["w"],
+                          e["max_level"]) for e in gold["queries"]]
+        print(f"[golden] {name}: {len(qs)} queries", flush=True)
+        if name == "batch":
+            got = c.query_batch(qs, lean=True)
+        else:
+            got = [c.query(q, lean=True) for q in qs]
+        for e, q, r in zip(gold["queries"], qs, got):
+            assert digest(r) == expected(e), (name, e["index"], q)
+    finally:
+        c.close()
+        synth.make_graph.cache_clear()

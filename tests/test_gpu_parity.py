@@ -29,8 +29,10 @@ def ctx(raks):
 
 
 def strip(r):
+    """Drops the timing fields, which differ between runs."""
     r = dict(r)
-    r.pop("device_ms", None)
+    for k in ("device_ms", "host_ms", "queue_ms"):
+        r.pop(k, None)
     return r
 
 
@@ -205,3 +207,23 @@ def test_medium_parity(ctx, medium, qi):
         ctx.load_graph(g, alpha=0.5)
     q = synth.make_queries(g, "medium")[qi]
     assert_same(ctx.query(q), o.query(act, q), q)
+
+
+def test_timing_mask(ctx, raks):
+    g = synth.make_graph("small")
+    ctx.load_graph(g, alpha=0.5)
+    q = synth.make_queries(g, "small")[0]
+    ctx.set_timing(1 << raks.TIMER_EXPAND)
+    ctx.query(q)
+    t = [ctx.timing(i) for i in range(5)]
+    ctx.set_timing(False)
+    assert t[raks.TIMER_EXPAND]["launches"] > 0 and t[raks.TIMER_EXPAND]["bytes"] > 0
+    assert all(t[i]["launches"] == 0 for i in range(5) if i != raks.TIMER_EXPAND)
+    ctx.set_timing(True)
+    ctx.query(q)
+    assert all(ctx.timing(i)["launches"] > 0 for i in (raks.TIMER_EXPAND, raks.TIMER_SCAN,
+                                                       raks.TIMER_CONTROL, raks.TIMER_RECOVER))
+    ctx.set_timing(False)
+    with pytest.raises(raks.RaksError) as e:
+        ctx.set_timing(64)
+    assert e.value.code == -1

@@ -55,3 +55,35 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(raks, "_lib_handle", None)
     with pytest.raises(RuntimeError):
         raks.lib()
+
+
+LAYOUT_STRUCTS = {
+    "raks_ctx_opts": "CtxOpts", "raks_serve_opts": "ServeOpts", "raks_graph_desc": "GraphDesc",
+    "raks_query_desc": "QueryDesc", "raks_arc": "Arc", "raks_result": "Result",
+    "raks_query_stats": "QueryStats", "raks_results": "Results",
+    "raks_kernel_timing": "KernelTiming",
+}
+
+
+def test_binding_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the ABI structs have the C compiler's sizes and
+    field offsets (a mismatch would corrupt every call silently)."""
+    import paper_2001_06770_amd as raks
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "raks.h"', "int main(void) {"]
+    for cname, pyname in LAYOUT_STRUCTS.items():
+        st = getattr(raks, pyname)
+        lines.append(f'printf("{pyname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in st._fields_:
+            lines.append(f'printf("{pyname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    for line in filter(None, out):
+        pyname, field, value = line.split()
+        st = getattr(raks, pyname)
+        got = ctypes.sizeof(st) if field == "size" else getattr(st, field).offset
+        assert got == int(value), (pyname, field, got, value)
