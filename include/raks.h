@@ -127,6 +127,10 @@ int raks_get_activations(raks_ctx* ctx, uint8_t* out, int64_t n);
  *   central.  k >= 1 results, beam width w >= k (0 = k) and w <= 256
  *   (Section 3.4); gamma = gamma_num/gamma_den in [0,1] (Eq. 6; 0/0 = 1/2);
  *   max_level in 1..250 (0 = 20, the paper's level bound).
+ *   alpha: the granularity of Eqs. 1-2 for this query alone, without
+ *   reloading (users tune alpha per search, Section 3.1); the levels for an
+ *   alpha are built on first use (one pass over the arcs) and the last few
+ *   are cached.
  * Violations give RAKS_EINVAL.  A keyword with no node gives no results. */
 typedef struct {
     const int32_t* central;
@@ -138,6 +142,7 @@ typedef struct {
     int32_t gamma_num;
     int32_t gamma_den;
     int32_t max_level;
+    double alpha;       /* 0: the context's alpha; else in (0,1) for this query only */
 } raks_query_desc;
 
 typedef struct {

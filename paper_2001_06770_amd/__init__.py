@@ -47,7 +47,8 @@ class QueryDesc(ctypes.Structure):
     _fields_ = [("central", ctypes.c_void_p), ("n_central", ctypes.c_int32),
                 ("marginal", ctypes.c_void_p), ("n_marginal", ctypes.c_int32),
                 ("k", ctypes.c_int32), ("w", ctypes.c_int32), ("gamma_num", ctypes.c_int32),
-                ("gamma_den", ctypes.c_int32), ("max_level", ctypes.c_int32)]
+                ("gamma_den", ctypes.c_int32), ("max_level", ctypes.c_int32),
+                ("alpha", ctypes.c_double)]
 
 
 class Arc(ctypes.Structure):
@@ -245,7 +246,7 @@ class Context:
         keep += [c, m]
         return QueryDesc(c.ctypes.data, len(q.central), m.ctypes.data, len(q.marginal), q.k, q.w,
                          getattr(q, "gamma_num", 1), getattr(q, "gamma_den", 2),
-                         getattr(q, "max_level", 20))
+                         getattr(q, "max_level", 20), float(getattr(q, "alpha", 0.0)))
 
     def query(self, q, lean: bool = False) -> dict:
         keep = []

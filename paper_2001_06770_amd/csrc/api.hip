@@ -101,25 +101,27 @@ void dev_free(Ctx* c, DevBuf& b) {
 
 int tp_for(int T) { return T <= 4 ? 4 : (T <= 8 ? 8 : 16); }
 
-DevGraphView graph_view(Ctx* c) {
+DevGraphView graph_view(const Ctx* c, const AlphaView& v) {
   DevGraphView g;
   g.n = c->n;
   g.A = c->A;
-  g.row_ptr = P<uint32_t>(c->row_ptr);
-  g.col = P<int32_t>(c->col);
-  g.label = P<uint16_t>(c->label);
-  g.act = P<uint8_t>(c->act);
-  g.act_node = c->mode ? P<uint8_t>(c->act_node) : nullptr;
+  g.row_ptr = reinterpret_cast<const uint32_t*>(c->row_ptr.p);
+  g.col = reinterpret_cast<const int32_t*>(c->col.p);
+  g.label = reinterpret_cast<const uint16_t*>(c->label.p);
+  g.act = reinterpret_cast<const uint8_t*>(v.act.p);
+  g.act_node = c->mode ? reinterpret_cast<const uint8_t*>(v.act_node.p) : nullptr;
   g.mode = c->mode;
-  g.col_s = P<int32_t>(c->col_s);
-  g.act_s = P<uint8_t>(c->act_s);
-  g.row_amax = P<uint8_t>(c->row_amax);
-  g.eid_s = P<uint32_t>(c->eid_s);
-  g.arc_src = P<int32_t>(c->arc_src);
-  g.bnd = P<uint32_t>(c->bnd);
+  g.col_s = reinterpret_cast<const int32_t*>(v.col_s.p);
+  g.act_s = reinterpret_cast<const uint8_t*>(v.act_s.p);
+  g.row_amax = reinterpret_cast<const uint8_t*>(v.row_amax.p);
+  g.eid_s = reinterpret_cast<const uint32_t*>(v.eid_s.p);
+  g.arc_src = reinterpret_cast<const int32_t*>(c->arc_src.p);
+  g.bnd = reinterpret_cast<const uint32_t*>(v.bnd.p);
   g.nbnd = c->nbnd;
   return g;
 }
+
+DevGraphView graph_view(const Lane* L) { return graph_view(L->ctx, *L->view); }
 
 // -------------------------------------------------------------- lanes ---
 
@@ -199,10 +201,12 @@ int ensure_lanes(Ctx* c, int n) {
 
 // ------------------------------------------------------------- timing ---
 
+// Timing events skip the system-scope fence: they are read only after the
+// query's final stream synchronisation.
 hipEvent_t next_event(Lane* L) {
   if (L->ev_used == L->ev_pool.size()) {
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     L->ev_pool.push_back(e);
   }
   return L->ev_pool[L->ev_used++];
@@ -251,52 +255,128 @@ void harvest_timing(Lane* L) {
 
 // -------------------------------------------------------------- graph ---
 
-int compute_activation(Ctx* c, Lane* L) {
+// Checks the input contract and computes what every alpha's levels derive
+// from: the label count c of every arc (EDGE) and the range of c or of the
+// node weights (in ctx->wstat).
+int check_graph(Ctx* c, Lane* L) {
   hipStream_t s = L->stream;
-  Status* st = P<Status>(L->status);
+  RAKS_TRY(dev_alloc(c, c->wstat, sizeof(Status)));
+  Status* st = P<Status>(c->wstat);
   RAKS_TRY(dev_alloc(c, c->arc_src, (size_t)std::max<uint32_t>(c->A, 1) * 4));
-  DevGraphView g = graph_view(c);
-  DevBuf ctmp;
-  RAKS_TRY(dev_alloc(c, ctmp, (size_t)std::max<uint32_t>(c->A, 1) * 4));
-  launch_check_and_count(g, P<uint32_t>(ctmp), P<int32_t>(c->arc_src), st, s);
+  RAKS_TRY(dev_alloc(c, c->cweight, (size_t)std::max<uint32_t>(c->A, 1) * 4));
+  const DevGraphView g = graph_view(c, c->base);
+  launch_check_and_count(g, P<uint32_t>(c->cweight), P<int32_t>(c->arc_src), st, s);
   HIP_OK(hipMemcpyAsync(L->h_status, st, sizeof(Status), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   if (L->h_status->err) {
-    dev_free(c, ctmp);
     char msg[160];
     snprintf(msg, sizeof msg,
              "graph violates the input contract (bits 0x%x: 1 col range, 2 self-loop, "
              "4 row order, 8 missing reverse arc)", L->h_status->err);
     return fail(RAKS_EINVAL, msg);
   }
-  if (c->mode == RAKS_ACT_EDGE)
-    launch_act_edge(g, P<uint32_t>(ctmp), st, c->abar, c->alpha, P<uint8_t>(c->act), s);
-  else
-    launch_act_node(g, P<uint8_t>(c->nw), st, c->abar, c->alpha, P<uint8_t>(c->act_node),
-                    P<uint8_t>(c->act), s);
+  if (c->mode == RAKS_ACT_NODE) launch_node_weight_range(g, P<uint8_t>(c->nw), st, s);
   HIP_OK(hipGetLastError());
   HIP_OK(hipStreamSynchronize(s));
-  dev_free(c, ctmp);
-  // traversal copy sorted by activation level within each row
-  RAKS_TRY(dev_alloc(c, c->col_s, (size_t)std::max<uint32_t>(c->A, 1) * 4));
-  RAKS_TRY(dev_alloc(c, c->act_s, (size_t)std::max<uint32_t>(c->A, 1)));
-  RAKS_TRY(dev_alloc(c, c->eid_s, (size_t)std::max<uint32_t>(c->A, 1) * 4));
-  RAKS_TRY(dev_alloc(c, c->row_amax, (size_t)c->n));
   // levels never exceed Round(2 * a_bar) (x <= 1 in Eqs. 1-3)
   c->nbnd = (int32_t)std::min(16.0, std::floor(2.0 * c->abar + 0.5) + 1.0);
-  RAKS_TRY(dev_alloc(c, c->bnd, (size_t)c->n * c->nbnd * 4));
-  g = graph_view(c);
-  launch_sort_rows(g, P<int32_t>(c->col_s), P<uint8_t>(c->act_s), P<uint32_t>(c->eid_s),
-                   P<uint8_t>(c->row_amax), P<uint32_t>(c->bnd), c->nbnd, s);
+  return RAKS_OK;
+}
+
+// Activation levels for `alpha` (Eqs. 1-3) and the traversal copy with every
+// row sorted by level, on lane L's stream.
+int build_view(Ctx* c, Lane* L, AlphaView& v, double alpha) {
+  hipStream_t s = L->stream;
+  const size_t A1 = std::max<uint32_t>(c->A, 1);
+  RAKS_TRY(dev_alloc(c, v.act, A1));
+  if (c->mode == RAKS_ACT_NODE) RAKS_TRY(dev_alloc(c, v.act_node, (size_t)c->n));
+  RAKS_TRY(dev_alloc(c, v.col_s, A1 * 4));
+  RAKS_TRY(dev_alloc(c, v.act_s, A1));
+  RAKS_TRY(dev_alloc(c, v.eid_s, A1 * 4));
+  RAKS_TRY(dev_alloc(c, v.row_amax, (size_t)c->n));
+  RAKS_TRY(dev_alloc(c, v.bnd, (size_t)c->n * c->nbnd * 4));
+  const Status* st = P<Status>(c->wstat);
+  DevGraphView g = graph_view(c, v);
+  if (c->mode == RAKS_ACT_EDGE)
+    launch_act_edge(g, P<uint32_t>(c->cweight), st, c->abar, alpha, P<uint8_t>(v.act), s);
+  else
+    launch_act_node(g, P<uint8_t>(c->nw), st, c->abar, alpha, P<uint8_t>(v.act_node),
+                    P<uint8_t>(v.act), s);
+  launch_sort_rows(g, P<int32_t>(v.col_s), P<uint8_t>(v.act_s), P<uint32_t>(v.eid_s),
+                   P<uint8_t>(v.row_amax), P<uint32_t>(v.bnd), c->nbnd, s);
   HIP_OK(hipGetLastError());
   HIP_OK(hipStreamSynchronize(s));
+  v.alpha = alpha;
   return RAKS_OK;
+}
+
+void free_view(Ctx* c, AlphaView& v) {
+  DevBuf* bufs[] = {&v.act, &v.act_node, &v.col_s, &v.act_s, &v.eid_s, &v.row_amax, &v.bnd};
+  for (DevBuf* b : bufs) dev_free(c, *b);
+}
+
+void drop_views(Ctx* c) {
+  std::lock_guard<std::mutex> lk(c->view_mu);
+  for (auto& v : c->views) free_view(c, *v);
+  c->views.clear();
+}
+
+// The levels a query runs on: the context's own, or a cached view for the
+// query's alpha (built on the lane's stream the first time; the least
+// recently used unused view is dropped beyond kMaxViews).
+int acquire_view(Lane* L, double alpha) {
+  Ctx* c = L->ctx;
+  if (alpha == 0.0 || alpha == c->alpha) {
+    L->view = &c->base;
+    return RAKS_OK;
+  }
+  std::lock_guard<std::mutex> lk(c->view_mu);
+  for (auto& v : c->views) {
+    if (v->alpha == alpha) {
+      ++v->refs;
+      v->last_use = ++c->view_clock;
+      L->view = v.get();
+      return RAKS_OK;
+    }
+  }
+  if ((int)c->views.size() >= kMaxViews) {
+    int victim = -1;
+    for (int i = 0; i < (int)c->views.size(); ++i)
+      if (c->views[i]->refs == 0 &&
+          (victim < 0 || c->views[i]->last_use < c->views[victim]->last_use))
+        victim = i;
+    if (victim >= 0) {
+      free_view(c, *c->views[victim]);
+      c->views.erase(c->views.begin() + victim);
+    }
+  }
+  std::unique_ptr<AlphaView> v(new AlphaView());
+  const int rc = build_view(c, L, *v, alpha);
+  if (rc) {
+    free_view(c, *v);
+    return rc;
+  }
+  v->refs = 1;
+  v->last_use = ++c->view_clock;
+  L->view = v.get();
+  c->views.push_back(std::move(v));
+  return RAKS_OK;
+}
+
+void release_view(Lane* L) {
+  Ctx* c = L->ctx;
+  if (L->view && L->view != &c->base) {
+    std::lock_guard<std::mutex> lk(c->view_mu);
+    --const_cast<AlphaView*>(L->view)->refs;
+  }
+  L->view = nullptr;
 }
 
 // ------------------------------------------------------------- query ---
 
 struct QueryPlan {
   int C, M, TPc, TPm, k, w, L, gn, gd;
+  double alpha;   // 0: the context's
   std::vector<int32_t> central, marginal;
 };
 
@@ -326,6 +406,9 @@ int validate_query(Ctx* c, const raks_query_desc* q, QueryPlan& p) {
   if (p.gn == 0 && p.gd == 0) { p.gn = 1; p.gd = 2; }
   if (p.gd < 1 || p.gd > 1000000 || p.gn < 0 || p.gn > p.gd)
     return fail(RAKS_EINVAL, "gamma must be gamma_num/gamma_den in [0,1]");
+  p.alpha = q->alpha;
+  if (!(p.alpha == 0.0 || (p.alpha > 0.0 && p.alpha < 1.0)))
+    return fail(RAKS_EINVAL, "alpha must be 0 (the context's) or in (0,1)");
   p.L = q->max_level ? q->max_level : 20;
   if (p.L < 1 || p.L > 250) return fail(RAKS_EINVAL, "max_level must be in 1..250");
   p.TPc = tp_for(p.C);
@@ -425,7 +508,7 @@ int run_levels(Lane* L, RunView& r, int TP, const std::vector<int32_t>& kws, int
                RunStatus* last) {
   Ctx* c = L->ctx;
   hipStream_t s = L->stream;
-  DevGraphView g = graph_view(c);
+  const DevGraphView g = graph_view(L);
   const SeedList seeds = seeds_for(c, kws);
   {
     Timed t(L, 4);
@@ -434,7 +517,7 @@ int run_levels(Lane* L, RunView& r, int TP, const std::vector<int32_t>& kws, int
   const int grid = c->num_cu * 8;
   // The control kernel writes the level's status into the pinned slot; the
   // slot's event follows it, so the host learns the decision while the
-  // level's expansion still runs.
+  // level's enqueue and expansion still run.
   auto enqueue = [&](int level, int slot) -> int {
     {
       Timed t(L, 1, level, r.kind);
@@ -630,20 +713,23 @@ int ensure_recovery(Lane* L, const QueryPlan& p) {
 // After an overflow of phase `ph`: every instance that ran out gets at least
 // twice its capacities and twice what it counted; one whose node table
 // filled up switches to a bitmap; the layer lists grow to twice the largest
-// request.
-int grow_phase(Lane* L, int ph, int max_level) {
+// request.  Only what the phase's kernels cleared is read: the instances of
+// the n_valid existing results and the layers 1..max_layer.
+int grow_phase(Lane* L, int ph, int n_valid, int max_layer) {
   Ctx* c = L->ctx;
   RecPhase& P = L->ph[ph];
-  std::vector<uint32_t> cnt((size_t)P.n_inst * 2), fl(P.n_inst), lc(max_level + 1);
+  const int live = std::min(P.n_inst, n_valid * P.T);
+  const int layers = std::max(max_layer, 0) + 1;
+  std::vector<uint32_t> cnt((size_t)std::max(live, 1) * 2), fl(std::max(live, 1)), lc(layers);
   hipStream_t s = L->stream;
-  if (P.n_inst) {
-    HIP_OK(hipMemcpyAsync(cnt.data(), P.cnt.p, cnt.size() * 4, hipMemcpyDeviceToHost, s));
-    HIP_OK(hipMemcpyAsync(fl.data(), P.iflag.p, fl.size() * 4, hipMemcpyDeviceToHost, s));
+  if (live > 0) {
+    HIP_OK(hipMemcpyAsync(cnt.data(), P.cnt.p, (size_t)live * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(fl.data(), P.iflag.p, (size_t)live * 4, hipMemcpyDeviceToHost, s));
   }
-  HIP_OK(hipMemcpyAsync(lc.data(), P.lcnt.p, lc.size() * 4, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(lc.data(), P.lcnt.p, (size_t)layers * 4, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   const uint32_t dw = dense_words(c);
-  for (int i = 0; i < P.n_inst; ++i) {
+  for (int i = 0; i < live; ++i) {
     const uint32_t cn = cnt[2 * i], ca = cnt[2 * i + 1];
     if (cn <= P.ncap[i] && ca <= P.acap[i] && !fl[i]) continue;
     const uint64_t nn = std::min<uint64_t>((uint64_t)c->n, 2ull * std::max(P.ncap[i], cn));
@@ -653,9 +739,13 @@ int grow_phase(Lane* L, int ph, int max_level) {
     P.acap[i] = (uint32_t)na;
     if (fl[i] || pow2_at_least(2ull * nn) >= dw) P.dense[i] = 1;
   }
+  // a layer holds at most every node's chunks once per instance
+  const uint64_t bound = (uint64_t)std::max(live, 1) *
+                         ((uint64_t)c->n + (uint64_t)c->A / kRecChunk + 1);
   uint32_t lmax = 0;
-  for (uint32_t x : lc) lmax = std::max(lmax, x);
-  if (lmax > P.lcap) P.lcap = (uint32_t)std::min<uint64_t>(2ull * lmax, 1u << 30);
+  for (int h = 1; h < layers; ++h) lmax = std::max(lmax, lc[h]);
+  if (lmax > P.lcap)
+    P.lcap = (uint32_t)std::min<uint64_t>({2ull * lmax, bound, 1ull << 30});
   P.grown = true;
   P.dirty = true;
   return RAKS_OK;
@@ -665,7 +755,7 @@ RecoverView recover_view(Lane* L, int ph, DevBuf& H, int TP, const int32_t* n_va
                          int max_layer) {
   RecPhase& Ph = L->ph[ph];
   RecoverView v = {};
-  v.g = graph_view(L->ctx);
+  v.g = graph_view(L);
   v.H = P<uint8_t>(H);
   v.TP = TP;
   v.T = Ph.T;
@@ -699,7 +789,7 @@ FinalizeView finalize_view(Lane* L, int ph, const int32_t* n_valid, int C, int T
   char* lay = static_cast<char*>(Ph.layout.p);
   char* lay0 = static_cast<char*>(P0.layout.p);
   FinalizeView v = {};
-  v.g = graph_view(L->ctx);
+  v.g = graph_view(L);
   v.T = Ph.T;
   v.marginal = ph;
   v.n_res = Ph.n_res;
@@ -918,14 +1008,8 @@ int collect(Lane* L, const QueryPlan& p, raks_results** out, int* ovf) {
 // at the end.  When a recovery capacity ran out, only that phase is repeated
 // (the CG phase together with everything after it, since V_C feeds the
 // marginal run), with the overflowing instances grown.
-int query_on_lane(Lane* L, const raks_query_desc* q, raks_results** out) {
+int query_plan_on_lane(Lane* L, const QueryPlan& p, raks_results** out, double t0) {
   Ctx* c = L->ctx;
-  if (!out) return fail(RAKS_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (!c->loaded) return fail(RAKS_ESTATE, "no graph loaded");
-  const double t0 = now_ms();
-  QueryPlan p;
-  RAKS_TRY(validate_query(c, q, p));
   RAKS_TRY(ensure_node_buffers(L));
   RAKS_TRY(dev_alloc(c, L->Hc, (size_t)L->n_pad * p.TPc));
   if (p.M > 0) RAKS_TRY(dev_alloc(c, L->Hm, (size_t)L->n_pad * p.TPm));
@@ -943,8 +1027,8 @@ int query_on_lane(Lane* L, const raks_query_desc* q, raks_results** out) {
     if (attempt >= kMaxAttempts)
       return fail(RAKS_ENOMEM, "recovered subgraphs exceed the recovery capacity");
     // collect() waited for the stream, so buffers may move now
-    if (ovf & 1) RAKS_TRY(grow_phase(L, 0, p.L));
-    else if (ovf & 2) RAKS_TRY(grow_phase(L, 1, p.L));
+    if (ovf & 1) RAKS_TRY(grow_phase(L, 0, L->h_status->nsel, qr.top1));
+    else if (ovf & 2) RAKS_TRY(grow_phase(L, 1, L->h_status->nres, qr.top2));
     else return fail(RAKS_EDEVICE, "output arena smaller than the recovered lists (internal error)");
     RAKS_TRY(ensure_recovery(L, p));
     k_retry_reset<<<1, 1, 0, L->stream>>>(P<Status>(L->status));
@@ -957,6 +1041,20 @@ int query_on_lane(Lane* L, const raks_query_desc* q, raks_results** out) {
   }
   (*out)->stats.host_ms = now_ms() - t0;
   return RAKS_OK;
+}
+
+int query_on_lane(Lane* L, const raks_query_desc* q, raks_results** out) {
+  Ctx* c = L->ctx;
+  if (!out) return fail(RAKS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!c->loaded) return fail(RAKS_ESTATE, "no graph loaded");
+  const double t0 = now_ms();
+  QueryPlan p;
+  RAKS_TRY(validate_query(c, q, p));
+  RAKS_TRY(acquire_view(L, p.alpha));
+  const int rc = query_plan_on_lane(L, p, out, t0);
+  release_view(L);
+  return rc;
 }
 
 // ------------------------------------------------------------ serving ---
@@ -1094,8 +1192,10 @@ int raks_destroy(raks_ctx* c) {
   stop_serving(c);
   for (auto& L : c->lanes) lane_destroy(c, L.get());
   c->lanes.clear();
-  DevBuf* bufs[] = {&c->row_ptr, &c->col, &c->label, &c->act, &c->act_node, &c->nw, &c->kw_nodes,
-                    &c->col_s, &c->act_s, &c->eid_s, &c->row_amax, &c->bnd, &c->arc_src};
+  drop_views(c);
+  free_view(c, c->base);
+  DevBuf* bufs[] = {&c->row_ptr, &c->col, &c->label, &c->nw, &c->kw_nodes, &c->arc_src,
+                    &c->cweight, &c->wstat};
   for (DevBuf* b : bufs) dev_free(c, *b);
   delete c;
   return RAKS_OK;
@@ -1147,7 +1247,7 @@ int raks_load_graph(raks_ctx* c, const raks_graph_desc* g) {
   RAKS_TRY(dev_alloc(c, c->row_ptr, (n + 1) * 4));
   RAKS_TRY(dev_alloc(c, c->col, std::max<int64_t>(A, 1) * 4));
   RAKS_TRY(dev_alloc(c, c->label, std::max<int64_t>(A, 1) * 2));
-  RAKS_TRY(dev_alloc(c, c->act, std::max<int64_t>(A, 1)));
+  drop_views(c);
   RAKS_TRY(dev_alloc(c, c->kw_nodes, std::max<int64_t>(nkw, 1) * 4));
   HIP_OK(hipMemcpyAsync(c->row_ptr.p, rp32.data(), (n + 1) * 4, hipMemcpyHostToDevice, s));
   if (A > 0) {
@@ -1157,13 +1257,13 @@ int raks_load_graph(raks_ctx* c, const raks_graph_desc* g) {
   if (nkw > 0) HIP_OK(hipMemcpyAsync(c->kw_nodes.p, g->kw_nodes, nkw * 4, hipMemcpyHostToDevice, s));
   if (g->act_mode == RAKS_ACT_NODE) {
     RAKS_TRY(dev_alloc(c, c->nw, n));
-    RAKS_TRY(dev_alloc(c, c->act_node, n));
     HIP_OK(hipMemcpyAsync(c->nw.p, g->node_weight, n, hipMemcpyHostToDevice, s));
   }
   c->kw_ptr.assign(g->kw_ptr, g->kw_ptr + (g->n_keywords > 0 ? g->n_keywords + 1 : 0));
   if (c->kw_ptr.empty()) c->kw_ptr.push_back(0);
   HIP_OK(hipStreamSynchronize(s));
-  RAKS_TRY(compute_activation(c, L));
+  RAKS_TRY(check_graph(c, L));
+  RAKS_TRY(build_view(c, L, c->base, c->alpha));
   c->loaded = true;
   return RAKS_OK;
 }
@@ -1174,8 +1274,9 @@ int raks_set_alpha(raks_ctx* c, double alpha) {
   if (c->serve.running) return fail(RAKS_ESTATE, "serving is running");
   if (!(alpha > 0.0 && alpha < 1.0)) return fail(RAKS_EINVAL, "alpha must be in (0,1)");
   HIP_OK(hipSetDevice(c->device));
+  RAKS_TRY(build_view(c, c->lanes[0].get(), c->base, alpha));
   c->alpha = alpha;
-  return compute_activation(c, c->lanes[0].get());
+  return RAKS_OK;
 }
 
 int raks_get_activations(raks_ctx* c, uint8_t* out, int64_t n) {
@@ -1184,7 +1285,7 @@ int raks_get_activations(raks_ctx* c, uint8_t* out, int64_t n) {
   if (n != (int64_t)c->A) return fail(RAKS_EINVAL, "n must equal n_arcs");
   HIP_OK(hipSetDevice(c->device));
   hipStream_t s = c->lanes[0]->stream;
-  if (n > 0) HIP_OK(hipMemcpyAsync(out, c->act.p, n, hipMemcpyDeviceToHost, s));
+  if (n > 0) HIP_OK(hipMemcpyAsync(out, c->base.act.p, n, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   return RAKS_OK;
 }

@@ -216,10 +216,14 @@ void launch_act_edge(const DevGraphView& g, const uint32_t* c_tmp, const Status*
   if (g.A > 0) k_act_edge<<<grid_for(g.A), kBlock, 0, s>>>(c_tmp, g.A, st, abar, alpha, act);
 }
 
-void launch_act_node(const DevGraphView& g, const uint8_t* nw, Status* st, double abar,
-                     double alpha, uint8_t* act_node, uint8_t* act, hipStream_t s) {
+void launch_node_weight_range(const DevGraphView& g, const uint8_t* nw, Status* st,
+                              hipStream_t s) {
   k_status_reset_minmax<<<1, 1, 0, s>>>(st);
   k_node_weight_range<<<grid_for(g.n), kBlock, 0, s>>>(nw, g.n, st);
+}
+
+void launch_act_node(const DevGraphView& g, const uint8_t* nw, const Status* st, double abar,
+                     double alpha, uint8_t* act_node, uint8_t* act, hipStream_t s) {
   k_act_node<<<grid_for(g.n), kBlock, 0, s>>>(nw, g.n, st, abar, alpha, act_node);
   if (g.A > 0) k_act_gather<<<grid_for(g.A), kBlock, 0, s>>>(act_node, g.col, g.A, act);
 }

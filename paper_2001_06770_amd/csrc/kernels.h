@@ -216,7 +216,10 @@ void launch_act_edge(const DevGraphView& g, const uint32_t* c_tmp, const Status*
                      double alpha, uint8_t* act, hipStream_t s);
 void launch_sort_rows(const DevGraphView& g, int32_t* col_s, uint8_t* act_s, uint32_t* eid_s,
                       uint8_t* row_amax, uint32_t* bnd, int32_t nbnd, hipStream_t s);
-void launch_act_node(const DevGraphView& g, const uint8_t* nw, Status* st, double abar,
+// node weight range into st->cmin / st->cmax (NODE mode, once per graph)
+void launch_node_weight_range(const DevGraphView& g, const uint8_t* nw, Status* st,
+                              hipStream_t s);
+void launch_act_node(const DevGraphView& g, const uint8_t* nw, const Status* st, double abar,
                      double alpha, uint8_t* act_node, uint8_t* act, hipStream_t s);
 
 void launch_run_init(const RunView& r, int TP, int32_t n, const int32_t* kw_nodes,

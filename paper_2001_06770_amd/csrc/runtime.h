@@ -25,6 +25,7 @@ constexpr int kTimers = 5;
 constexpr size_t kSpecNodes = 1 << 16;   // output read back with the headers
 constexpr size_t kSpecArcs = 1 << 16;
 constexpr int kMaxLanes = 32;
+constexpr int kMaxViews = 4;       // cached activation views for per-query alphas
 
 struct DevBuf {
   void* p = nullptr;
@@ -35,6 +36,18 @@ template <typename T>
 T* P(DevBuf& b) { return reinterpret_cast<T*>(b.p); }
 
 struct Ctx;
+
+// Activation levels for one alpha (Section 3.1, Eqs. 1-3): per-arc levels in
+// CSR order, per-node levels (NODE mode), and the traversal copy of the graph
+// with every row sorted by level (col_s, act_s, eid_s, row_amax, level
+// table).  The context's own alpha has one; queries with another alpha use
+// cached ones.
+struct AlphaView {
+  double alpha = 0;
+  DevBuf act, act_node, col_s, act_s, eid_s, row_amax, bnd;
+  int refs = 0;           // queries using it
+  uint64_t last_use = 0;
+};
 
 // Recovery capacities of one phase (Algorithm 2 over CGs, or over RPGs plus
 // the output): per instance node / arc list capacities and the kind of node
@@ -66,6 +79,7 @@ struct Lane {
   Ctx* ctx = nullptr;
   int id = 0;
   hipStream_t stream = nullptr;
+  const AlphaView* view = nullptr;   // activation levels of the current query
   bool own_stream = false;
 
   int32_t n_pad = 0, nblocks = 0;
@@ -136,9 +150,14 @@ struct Ctx {
   int32_t vocab = 0;
   int32_t mode = 0;
   double abar = 0, alpha = 0;
-  DevBuf row_ptr, col, label, act, act_node, nw, kw_nodes, col_s, act_s, eid_s, row_amax, bnd,
-      arc_src;
+  DevBuf row_ptr, col, label, nw, kw_nodes, arc_src;
+  DevBuf cweight;        // EDGE: label count c of every arc, kept for other alphas
+  DevBuf wstat;          // Status holding the c (or node weight) range of the graph
   int32_t nbnd = 1;
+  AlphaView base;        // levels for the context's alpha
+  std::vector<std::unique_ptr<AlphaView>> views;   // other alphas, least recently used evicted
+  std::mutex view_mu;
+  uint64_t view_clock = 0;
   std::vector<int64_t> kw_ptr;
 
   std::vector<std::unique_ptr<Lane>> lanes;

@@ -136,6 +136,7 @@ class Query:
     max_level: int = 20
     gamma_num: int = 1
     gamma_den: int = 2
+    alpha: float = 0.0     # 0: the alpha the graph was loaded with
 
 
 GRAPHS = {
