@@ -67,6 +67,10 @@ typedef struct {
      * (0 = 4096, 16384, 65536).  An instance that needs more is grown and its
      * phase repeated, so these only trade memory against repeats. */
     uint32_t rec_nodes, rec_arcs, rec_chunks;
+    /* Results whose recovered lists hold more entries than this (0 = 2^20)
+     * are merged through bitmaps over all nodes and arcs instead of a
+     * one-workgroup sort; the output is the same. */
+    uint64_t big_list;
 } raks_ctx_opts;
 
 /* Creates a context on opts->device (opts may be NULL: device 0, own stream,

@@ -27,7 +27,8 @@ class CtxOpts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("alloc", _ALLOC),
                 ("free", _FREE), ("alloc_user", ctypes.c_void_p), ("mem_budget", ctypes.c_uint64),
                 ("lanes", ctypes.c_int32), ("rec_nodes", ctypes.c_uint32),
-                ("rec_arcs", ctypes.c_uint32), ("rec_chunks", ctypes.c_uint32)]
+                ("rec_arcs", ctypes.c_uint32), ("rec_chunks", ctypes.c_uint32),
+                ("big_list", ctypes.c_uint64)]
 
 
 class ServeOpts(ctypes.Structure):
@@ -171,13 +172,14 @@ class Context:
     """One GPU context holding one graph (``raks_ctx``)."""
 
     def __init__(self, device: int = 0, use_torch: bool = True, mem_budget: int = 0,
-                 lanes: int = 1, rec_caps=(0, 0, 0)):
+                 lanes: int = 1, rec_caps=(0, 0, 0), big_list: int = 0):
         self._keep = []
         opts = CtxOpts()
         opts.device = device
         opts.mem_budget = mem_budget
         opts.lanes = lanes
         opts.rec_nodes, opts.rec_arcs, opts.rec_chunks = (int(x) for x in rec_caps)
+        opts.big_list = int(big_list)
         if use_torch:
             import torch
             if not torch.cuda.is_available():

@@ -116,6 +116,7 @@ DevGraphView graph_view(const Ctx* c, const AlphaView& v) {
   g.row_amax = reinterpret_cast<const uint8_t*>(v.row_amax.p);
   g.eid_s = reinterpret_cast<const uint32_t*>(v.eid_s.p);
   g.arc_src = reinterpret_cast<const int32_t*>(c->arc_src.p);
+  g.rev = reinterpret_cast<const uint32_t*>(c->rev.p);
   g.bnd = reinterpret_cast<const uint32_t*>(v.bnd.p);
   g.nbnd = c->nbnd;
   return g;
@@ -133,7 +134,7 @@ void lane_destroy(Ctx* c, Lane* L) {
                     &L->has_rpg, &L->sm, &L->key, &L->dmin, &L->ranked, &L->vc_cnt, &L->vc_tmp,
                     &L->vc_off, &L->vc_nodes, &L->hpool, &L->nl, &L->al, &L->items, &L->sort_a,
                     &L->sort_b, &L->cg_nodes, &L->cg_arcs, &L->cg_cnt, &L->hdr, &L->out_nodes,
-                    &L->out_arcs, &L->status};
+                    &L->out_arcs, &L->status, &L->bigf, &L->big_bm, &L->big_chunk, &L->big_slot};
   for (RecPhase& P : L->ph) {
     DevBuf* pb[] = {&P.layout, &P.cnt, &P.iflag, &P.lcnt};
     for (DevBuf* b : pb) dev_free(c, *b);
@@ -264,8 +265,10 @@ int check_graph(Ctx* c, Lane* L) {
   Status* st = P<Status>(c->wstat);
   RAKS_TRY(dev_alloc(c, c->arc_src, (size_t)std::max<uint32_t>(c->A, 1) * 4));
   RAKS_TRY(dev_alloc(c, c->cweight, (size_t)std::max<uint32_t>(c->A, 1) * 4));
+  RAKS_TRY(dev_alloc(c, c->rev, (size_t)std::max<uint32_t>(c->A, 1) * 4));
   const DevGraphView g = graph_view(c, c->base);
-  launch_check_and_count(g, P<uint32_t>(c->cweight), P<int32_t>(c->arc_src), st, s);
+  launch_check_and_count(g, P<uint32_t>(c->cweight), P<int32_t>(c->arc_src), P<uint32_t>(c->rev),
+                         st, s);
   HIP_OK(hipMemcpyAsync(L->h_status, st, sizeof(Status), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   if (L->h_status->err) {
@@ -532,8 +535,12 @@ int run_levels(Lane* L, RunView& r, int TP, const std::vector<int32_t>& kws, int
       Timed t(L, 1, level, r.kind);
       launch_front_write(r, TP, g, level, s);
     }
-    {
-      Timed t(L, 0, level, r.kind);
+    if (c->timing.load() & 1u) {
+      // expansion timing: the launch itself stamps the two events
+      hipEvent_t a = next_event(L), b = next_event(L);
+      launch_expand(r, TP, g, level, grid, s, a, b);
+      if (a && b) L->pending.push_back({a, b, 0, 0.0, level, r.kind});
+    } else {
       launch_expand(r, TP, g, level, grid, s);
     }
     HIP_OK(hipGetLastError());
@@ -705,6 +712,7 @@ int ensure_recovery(Lane* L, const QueryPlan& p) {
   RAKS_TRY(dev_alloc(c, L->sort_a, std::max<uint64_t>(sc, 1) * 4));
   RAKS_TRY(dev_alloc(c, L->sort_b, std::max<uint64_t>(sc, 1) * 4));
   RAKS_TRY(dev_alloc(c, L->hdr, (size_t)std::max(P1.n_res, 1) * sizeof(ResultHdr)));
+  RAKS_TRY(dev_alloc(c, L->bigf, (size_t)std::max({P0.n_res, P1.n_res, 1}) * 4));
   RAKS_TRY(dev_alloc(c, L->out_nodes, std::max<uint64_t>(P1.out_n, 1) * 4));
   RAKS_TRY(dev_alloc(c, L->out_arcs, std::max<uint64_t>(P1.out_a, 1) * 12));
   return RAKS_OK;
@@ -728,13 +736,20 @@ int grow_phase(Lane* L, int ph, int n_valid, int max_layer) {
   }
   HIP_OK(hipMemcpyAsync(lc.data(), P.lcnt.p, (size_t)layers * 4, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
+  uint32_t lmax = 0;
+  for (int h = 1; h < layers; ++h) lmax = std::max(lmax, lc[h]);
+  const bool chunks_fit = lmax <= P.lcap;
   const uint32_t dw = dense_words(c);
   for (int i = 0; i < live; ++i) {
     const uint32_t cn = cnt[2 * i], ca = cnt[2 * i + 1];
     if (cn <= P.ncap[i] && ca <= P.acap[i] && !fl[i]) continue;
-    const uint64_t nn = std::min<uint64_t>((uint64_t)c->n, 2ull * std::max(P.ncap[i], cn));
+    // a bitmap instance that lost no work chunk counted exactly
+    const bool exact = P.dense[i] && !fl[i] && chunks_fit;
+    const uint64_t wn = exact ? cn + cn / 8 + 64 : 2ull * std::max(P.ncap[i], cn);
+    const uint64_t wa = exact ? ca + ca / 8 + 64 : 2ull * std::max(P.acap[i], ca);
+    const uint64_t nn = std::min<uint64_t>((uint64_t)c->n, std::max<uint64_t>(wn, P.ncap[i]));
     const uint64_t na = std::min<uint64_t>((uint64_t)std::max<uint32_t>(c->A, 1),
-                                           2ull * std::max(P.acap[i], ca));
+                                           std::max<uint64_t>(wa, P.acap[i]));
     P.ncap[i] = (uint32_t)nn;
     P.acap[i] = (uint32_t)na;
     if (fl[i] || pow2_at_least(2ull * nn) >= dw) P.dense[i] = 1;
@@ -742,9 +757,7 @@ int grow_phase(Lane* L, int ph, int n_valid, int max_layer) {
   // a layer holds at most every node's chunks once per instance
   const uint64_t bound = (uint64_t)std::max(live, 1) *
                          ((uint64_t)c->n + (uint64_t)c->A / kRecChunk + 1);
-  uint32_t lmax = 0;
-  for (int h = 1; h < layers; ++h) lmax = std::max(lmax, lc[h]);
-  if (lmax > P.lcap)
+  if (!chunks_fit)
     P.lcap = (uint32_t)std::min<uint64_t>({2ull * lmax, bound, 1ull << 30});
   P.grown = true;
   P.dirty = true;
@@ -814,6 +827,9 @@ FinalizeView finalize_view(Lane* L, int ph, const int32_t* n_valid, int C, int T
   v.sort_b = P<uint32_t>(L->sort_b);
   v.soff = reinterpret_cast<const uint64_t*>(lay + Ph.lay_soff);
   v.write_output = ph;
+  v.skip_bits = ph == 0 ? 1 : 3;
+  v.big = P<uint32_t>(L->bigf);
+  v.big_list = L->ctx->big_list;
   v.hdr = P<ResultHdr>(L->hdr);
   v.out_nodes = P<int32_t>(L->out_nodes);
   v.out_arcs = P<int32_t>(L->out_arcs);
@@ -838,7 +854,41 @@ __global__ void k_retry_reset(Status* st) {
 struct QueryRun {
   RunStatus s1 = {}, s2 = {};
   int top1 = 0, top2 = 0;
+  bool big0 = false;   // some CG needs the bitmap path: finish CGs before the marginal run
 };
+
+__global__ void k_clear_flag(Status* st, int32_t bits) { st->overflow &= ~bits; }
+
+// Runs the bitmap path for every result of phase `ph` that its finalize
+// flagged.  Waits for the stream first (the flags are read on the host).
+int big_finalize(Lane* L, int ph, const QueryPlan& p, int n_res) {
+  Ctx* c = L->ctx;
+  hipStream_t s = L->stream;
+  std::vector<uint32_t> flags((size_t)std::max(n_res, 1), 0u);
+  if (n_res > 0)
+    HIP_OK(hipMemcpyAsync(flags.data(), L->bigf.p, (size_t)n_res * 4, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(L->h_status, L->status.p, sizeof(Status), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  // only results that exist: the flags of the others are not written
+  n_res = std::min(n_res, ph == 0 ? L->h_status->nsel : L->h_status->nres);
+  const uint64_t bits = std::max<uint64_t>((uint64_t)c->n, (uint64_t)c->A) + 32;
+  const uint64_t words = (bits + 31) / 32;
+  RAKS_TRY(dev_alloc(c, L->big_bm, words * 4));
+  RAKS_TRY(dev_alloc(c, L->big_chunk, (words / 1024 + 2) * 4));
+  RAKS_TRY(dev_alloc(c, L->big_slot, 8));
+  const FinalizeView fv = finalize_view(L, ph, ph == 0 ? &P<Status>(L->status)->nsel
+                                                       : &P<Status>(L->status)->nres, p.C, p.TPc);
+  {
+    Timed t(L, 3);
+    for (int r = 0; r < n_res; ++r)
+      if (flags[r])
+        launch_big_finalize(fv, r, P<uint32_t>(L->big_bm), P<uint32_t>(L->big_chunk),
+                            P<uint64_t>(L->big_slot), s);
+    k_clear_flag<<<1, 1, 0, s>>>(P<Status>(L->status), ph == 0 ? kOvfBig0 : kOvfBig1);
+  }
+  HIP_OK(hipGetLastError());
+  return RAKS_OK;
+}
 
 // Central run and top-w selection.
 int stage_central(Lane* L, const QueryPlan& p, QueryRun& q) {
@@ -870,6 +920,10 @@ int stage_cg_recovery(Lane* L, const QueryPlan& p, const QueryRun& q) {
     Timed t(L, 3);
     launch_recover(recover_view(L, 0, L->Hc, p.TPc, &st->nsel, q.top1), s);
     launch_finalize(finalize_view(L, 0, &st->nsel, p.C, p.TPc), s);
+  }
+  if (q.big0) RAKS_TRY(big_finalize(L, 0, p, p.w));
+  {
+    Timed t(L, 3);
     if (p.M > 0) {
       const char* lay0 = static_cast<const char*>(L->ph[0].layout.p);
       launch_pack_vc(P<uint32_t>(L->vc_cnt), P<int32_t>(L->vc_tmp),
@@ -1027,12 +1081,21 @@ int query_plan_on_lane(Lane* L, const QueryPlan& p, raks_results** out, double t
     if (attempt >= kMaxAttempts)
       return fail(RAKS_ENOMEM, "recovered subgraphs exceed the recovery capacity");
     // collect() waited for the stream, so buffers may move now
+    if (ovf & 4) return fail(RAKS_EDEVICE, "output arena smaller than the recovered lists (internal error)");
+    const bool redo_cg = (ovf & (1 | kOvfBig0)) != 0;
+    if (!redo_cg && !(ovf & 2)) {
+      // only RPGs too large for the sort path: their lists are all there
+      RAKS_TRY(big_finalize(L, 1, p, p.k));
+      HIP_OK(hipEventRecord(L->q_end, L->stream));
+      RAKS_TRY(collect(L, p, out, &ovf));
+      continue;
+    }
     if (ovf & 1) RAKS_TRY(grow_phase(L, 0, L->h_status->nsel, qr.top1));
-    else if (ovf & 2) RAKS_TRY(grow_phase(L, 1, L->h_status->nres, qr.top2));
-    else return fail(RAKS_EDEVICE, "output arena smaller than the recovered lists (internal error)");
+    if (ovf & kOvfBig0) qr.big0 = true;   // finish the CG lists before the marginal run
+    if (!redo_cg) RAKS_TRY(grow_phase(L, 1, L->h_status->nres, qr.top2));
     RAKS_TRY(ensure_recovery(L, p));
     k_retry_reset<<<1, 1, 0, L->stream>>>(P<Status>(L->status));
-    if (ovf & 1) {
+    if (redo_cg) {
       RAKS_TRY(stage_cg_recovery(L, p, qr));
       RAKS_TRY(stage_marginal(L, p, qr));
     }
@@ -1176,6 +1239,7 @@ int raks_create(raks_ctx** out, const raks_ctx_opts* opts) {
   if (o.rec_nodes) c->rec_nc0 = o.rec_nodes;
   if (o.rec_arcs) c->rec_ac0 = o.rec_arcs;
   if (o.rec_chunks) c->rec_lcap0 = o.rec_chunks;
+  if (o.big_list) c->big_list = o.big_list;
   const int rc = ensure_lanes(c, std::max(1, (int)o.lanes));
   if (rc) {
     const std::string msg = g_err;
@@ -1195,7 +1259,7 @@ int raks_destroy(raks_ctx* c) {
   drop_views(c);
   free_view(c, c->base);
   DevBuf* bufs[] = {&c->row_ptr, &c->col, &c->label, &c->nw, &c->kw_nodes, &c->arc_src,
-                    &c->cweight, &c->wstat};
+                    &c->rev, &c->cweight, &c->wstat};
   for (DevBuf* b : bufs) dev_free(c, *b);
   delete c;
   return RAKS_OK;

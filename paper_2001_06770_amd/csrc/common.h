@@ -16,6 +16,8 @@ constexpr int kMaxKw = 16;         // keywords per run
 constexpr int kMaxW = 256;         // beam width limit
 constexpr uint8_t kInf = 0xFF;     // "not reached" in the node-keyword matrix
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr int32_t kOvfBig0 = 8;    // a CG's lists exceed the sort path (Status::overflow)
+constexpr int32_t kOvfBig1 = 16;   // an RPG's lists exceed the sort path
 
 enum RunKind : int { RUN_CENTRAL = 0, RUN_MARGINAL = 1 };
 enum EndReason : int { END_NONE = 0, END_EXHAUSTED = 1, END_STOP = 2, END_LEVEL_BOUND = 3,
@@ -41,7 +43,7 @@ struct Status {
   RunStatus run[2];
   int32_t nsel;          // selected CGs (<= w)
   int32_t nres;          // ranked results (<= k)
-  int32_t overflow;      // capacity ran out: 1 CG recovery, 2 RPG recovery, 4 output arena
+  int32_t overflow;      // 1/2: CG/RPG recovery capacity ran out, 4: output arena; 8/16: CG/RPG lists for the bitmap path
   int32_t err;           // graph contract violation bits (load)
   uint64_t cmin, cmax;   // label-count extremes (load)
   uint32_t out_nodes, out_arcs;  // output arena use

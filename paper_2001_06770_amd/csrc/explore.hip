@@ -21,6 +21,8 @@
 // stores level+1 into a byte that was INF, every F write stores 1.  The
 // joining flag array is implied by H: a node is blocked exactly when its row
 // is complete, and it is identified at the level equal to its row maximum.
+#include <hip/hip_ext.h>
+
 #include <climits>
 
 #include "common.h"
@@ -628,8 +630,14 @@ void launch_front_write(const RunView& r, int TP, const DevGraphView& g, int lev
 }
 
 void launch_expand(const RunView& r, int TP, const DevGraphView& g, int level, int grid,
-                   hipStream_t s) {
-  RAKS_TP_DISPATCH(TP, k_expand<kTP><<<grid, kBlock, 0, s>>>(r, g, level));
+                   hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  if (ev0 && ev1) {
+    // the events take the kernel's own start and end times
+    RAKS_TP_DISPATCH(TP, hipExtLaunchKernelGGL(k_expand<kTP>, dim3(grid), dim3(kBlock), 0, s,
+                                               ev0, ev1, 0, r, g, level));
+  } else {
+    RAKS_TP_DISPATCH(TP, k_expand<kTP><<<grid, kBlock, 0, s>>>(r, g, level));
+  }
 }
 
 void launch_select(const SelectView& v, hipStream_t s) { k_select<<<1, kCtl, 0, s>>>(v); }

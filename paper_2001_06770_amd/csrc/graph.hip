@@ -32,7 +32,8 @@ __global__ __launch_bounds__(kBlock) void k_check_and_count(const uint32_t* row_
                                                             const int32_t* col,
                                                             const uint16_t* label, int32_t n,
                                                             uint32_t A, uint32_t* c_out,
-                                                            int32_t* arc_src, Status* st) {
+                                                            int32_t* arc_src, uint32_t* rev,
+                                                            Status* st) {
   uint32_t err = 0;
   uint64_t cmin = ~0ull, cmax = 0;
   for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < A; e += gridDim.x * kBlock) {
@@ -40,14 +41,16 @@ __global__ __launch_bounds__(kBlock) void k_check_and_count(const uint32_t* row_
     arc_src[e] = (int32_t)i;
     const int32_t j = col[e];
     const uint16_t lab = label[e];
-    if (j < 0 || j >= n) { err |= 1; c_out[e] = 0; continue; }
+    if (j < 0 || j >= n) { err |= 1; c_out[e] = 0; rev[e] = kEmpty; continue; }
     if ((uint32_t)j == i) err |= 2;
     if (e > row_ptr[i]) {
       const uint16_t pl = label[e - 1];
       const int32_t pc = col[e - 1];
       if (pl > lab || (pl == lab && pc >= j)) err |= 4;
     }
-    if (find_arc_dev(row_ptr, col, label, j, lab, (int32_t)i) == kEmpty) err |= 8;
+    const uint32_t r = find_arc_dev(row_ptr, col, label, j, lab, (int32_t)i);
+    rev[e] = r;
+    if (r == kEmpty) err |= 8;
     const uint64_t c = (uint64_t)label_run(row_ptr, label, i, lab) + label_run(row_ptr, label, j, lab);
     c_out[e] = (uint32_t)c;
     cmin = c < cmin ? c : cmin;
@@ -203,12 +206,12 @@ static unsigned grid_for(uint64_t items, unsigned cap = 8192) {
   return (unsigned)(g > cap ? cap : g);
 }
 
-void launch_check_and_count(const DevGraphView& g, uint32_t* c_tmp, int32_t* arc_src, Status* st,
-                            hipStream_t s) {
+void launch_check_and_count(const DevGraphView& g, uint32_t* c_tmp, int32_t* arc_src, uint32_t* rev,
+                            Status* st, hipStream_t s) {
   k_status_reset_minmax<<<1, 1, 0, s>>>(st);
   if (g.A > 0)
     k_check_and_count<<<grid_for(g.A), kBlock, 0, s>>>(g.row_ptr, g.col, g.label, g.n, g.A, c_tmp,
-                                                        arc_src, st);
+                                                        arc_src, rev, st);
 }
 
 void launch_act_edge(const DevGraphView& g, const uint32_t* c_tmp, const Status* st, double abar,

@@ -19,6 +19,7 @@ struct DevGraphView {
   const uint8_t* act_s;     // [A]
   const uint32_t* eid_s;    // [A] CSR position of the arc
   const int32_t* arc_src;   // [A] source node of each arc (CSR order)
+  const uint32_t* rev;      // [A] CSR position of each arc's reverse arc
   const uint8_t* row_amax;  // [n] largest activation level of the row (0 if empty)
   const uint32_t* bnd;      // [n][nbnd] arcs of the row with level <= l, l < nbnd
   int32_t nbnd;             // levels covered by bnd (1..16)
@@ -180,6 +181,9 @@ struct FinalizeView {
   const uint64_t* soff;
   // final output (marginal == 1 or no marginal keywords)
   int32_t write_output;
+  int32_t skip_bits;         // overflow bits that make this finalize pointless (phase repeats)
+  uint32_t* big;             // [n_res] 1: the result's lists go to the bitmap path
+  uint64_t big_list;         // lists longer than this take the bitmap path
   ResultHdr* hdr;
   int32_t* out_nodes;
   int32_t* out_arcs;         // (src, dst, label) triples
@@ -210,7 +214,8 @@ __device__ inline uint32_t row_of(const uint32_t* row_ptr, int32_t n, uint32_t e
 
 void launch_pack_vc(const uint32_t* vc_cnt, const int32_t* vc_tmp, const uint64_t* cg_noff,
                     const int32_t* nsel, uint32_t* vc_off, int32_t* vc_nodes, hipStream_t s);
-void launch_check_and_count(const DevGraphView& g, uint32_t* c_tmp, int32_t* arc_src, Status* st,
+void launch_check_and_count(const DevGraphView& g, uint32_t* c_tmp, int32_t* arc_src, uint32_t* rev,
+                            Status* st,
                             hipStream_t s);
 void launch_act_edge(const DevGraphView& g, const uint32_t* c_tmp, const Status* st, double abar,
                      double alpha, uint8_t* act, hipStream_t s);
@@ -229,11 +234,16 @@ void launch_front_count(const RunView& r, int TP, const DevGraphView& g, int lev
 void launch_front_control(const RunView& r, int TP, int level, RunStatus* mirror,
                           hipStream_t s);
 void launch_front_write(const RunView& r, int TP, const DevGraphView& g, int level, hipStream_t s);
+// ev0 / ev1 (optional): events that receive the kernel's start and end times
 void launch_expand(const RunView& r, int TP, const DevGraphView& g, int level, int grid,
-                   hipStream_t s);
+                   hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_select(const SelectView& v, hipStream_t s);
 void launch_rank(const RankView& v, hipStream_t s);
 void launch_recover(const RecoverView& v, hipStream_t s);   // all layers of one phase
 void launch_finalize(const FinalizeView& v, hipStream_t s);
+// Bitmap path for result t (flagged in v.big): bm holds max(n, A) bits, chunk
+// one count per kBigChunk words, slot one 64-bit list start.
+void launch_big_finalize(const FinalizeView& v, int t, uint32_t* bm, uint32_t* chunk, uint64_t* slot,
+                         hipStream_t s);
 
 }  // namespace raks

@@ -36,41 +36,70 @@ __device__ inline bool ht_insert(uint32_t* ht, uint32_t hc, uint32_t key, int* f
   return false;
 }
 
-// Node n (hitting level hn in this instance's column) is recovered: record
-// it once per instance and queue its arcs on layer hn.
-__device__ inline void rec_discover(const RecoverView& v, uint32_t inst, const InstCap& ic,
-                                    int32_t n, uint32_t hn) {
-  bool fresh;
-  if (ic.dense) {
-    uint32_t* w = v.hpool + ic.hoff + ((uint32_t)n >> 5);
-    const uint32_t bit = 1u << ((uint32_t)n & 31u);
-    fresh = (atomicOr(w, bit) & bit) == 0;
-  } else {
-    int full = 0;
-    fresh = ht_insert(v.hpool + ic.hoff, ic.hcap, (uint32_t)n, &full);
-    if (full) {
-      v.iflag[inst] = 1;
-      atomicOr(&v.gst->overflow, v.ovf_bit);
+// Lanes with `act` set have recovered node n (hitting level hn in instance
+// inst's column): record each node once per instance and queue its arcs on
+// layer hn.  Called by all lanes of a wavefront together (the counters are
+// bumped once per wavefront, not once per lane: every wave of a large
+// instance would otherwise queue on the same two addresses).
+__device__ inline void rec_discover(const RecoverView& v, bool act, uint32_t inst,
+                                    const InstCap& ic, int32_t n, uint32_t hn) {
+  const int lane = lane_id();
+  const uint64_t below = (1ull << lane) - 1;
+  bool fresh = false;
+  if (act) {
+    if (ic.dense) {
+      uint32_t* w = v.hpool + ic.hoff + ((uint32_t)n >> 5);
+      const uint32_t bit = 1u << ((uint32_t)n & 31u);
+      fresh = (atomicOr(w, bit) & bit) == 0;
+    } else {
+      int full = 0;
+      fresh = ht_insert(v.hpool + ic.hoff, ic.hcap, (uint32_t)n, &full);
+      if (full) {
+        v.iflag[inst] = 1;
+        atomicOr(&v.gst->overflow, v.ovf_bit);
+      }
     }
   }
-  if (!fresh) return;
-  const uint32_t slot = atomicAdd(&v.cnt[inst * 2], 1u);
-  if (slot < ic.ncap) v.nl[ic.noff + slot] = n;
-  else atomicOr(&v.gst->overflow, v.ovf_bit);
-  if (hn >= 1 && (int)hn <= v.max_layer) {
+  // node list slots
+  const uint64_t fb = __ballot(fresh);
+  if (fb == 0) return;
+  const int lead = __ffsll((unsigned long long)fb) - 1;
+  uint32_t base = 0;
+  if (lane == lead) base = atomicAdd(&v.cnt[inst * 2], (uint32_t)__popcll(fb));
+  base = __shfl(base, lead, kWave);
+  if (fresh) {
+    const uint32_t slot = base + (uint32_t)__popcll(fb & below);
+    if (slot < ic.ncap) v.nl[ic.noff + slot] = n;
+    else atomicOr(&v.gst->overflow, v.ovf_bit);
+  }
+  // work chunks, grouped by layer
+  uint32_t k = 0, rs = 0, deg = 0;
+  if (fresh && hn >= 1 && (int)hn <= v.max_layer) {
     // in-arcs m -> n that can meet h_n = 1 + max(a, h_m) have a <= h_n - 1:
     // a prefix of n's level-sorted row (EDGE), or all arcs when the node's
     // own level is below h_n (NODE: every in-arc of n has the level of n)
-    const uint32_t rs = v.g.row_ptr[n];
-    const uint32_t deg = v.g.mode ? ((uint32_t)v.g.act_node[n] < hn ? v.g.row_ptr[n + 1] - rs : 0u)
-                                  : count_le(v.g, n, (int)hn - 1);
-    const uint32_t k = (deg + kRecChunk - 1) / kRecChunk;
-    if (k > 0) {
-      const uint32_t base = atomicAdd(&v.lcnt[hn], k);
-      if (base + k > v.lcap) {
+    rs = v.g.row_ptr[n];
+    deg = v.g.mode ? ((uint32_t)v.g.act_node[n] < hn ? v.g.row_ptr[n + 1] - rs : 0u)
+                   : count_le(v.g, n, (int)hn - 1);
+    k = (deg + kRecChunk - 1) / kRecChunk;
+  }
+  uint64_t pend = __ballot(k > 0);
+  while (pend) {
+    const int l0 = __ffsll((unsigned long long)pend) - 1;
+    const uint32_t hv = __shfl(hn, l0, kWave);
+    const bool mine = k > 0 && hn == hv && ((pend >> lane) & 1ull);
+    const uint64_t grp = __ballot(mine);
+    const uint32_t inc = wave_inclusive_scan<uint32_t>(mine ? k : 0u);
+    const uint32_t tot = __shfl(inc, kWave - 1, kWave);
+    uint32_t b0 = 0;
+    if (lane == l0) b0 = atomicAdd(&v.lcnt[hv], tot);
+    b0 = __shfl(b0, l0, kWave);
+    if (mine) {
+      const uint32_t first = b0 + inc - k;
+      if (first + k > v.lcap) {
         atomicOr(&v.gst->overflow, v.ovf_bit);
       } else {
-        RecItem* dst = v.items + (size_t)hn * v.lcap + base;
+        RecItem* dst = v.items + (size_t)hv * v.lcap + first;
         for (uint32_t c = 0; c < k; ++c) {
           RecItem it;
           it.inst = inst;
@@ -81,6 +110,7 @@ __device__ inline void rec_discover(const RecoverView& v, uint32_t inst, const I
         }
       }
     }
+    pend &= ~grp;
   }
 }
 
@@ -113,16 +143,18 @@ __global__ __launch_bounds__(kBlock) void k_rec_seed(RecoverView v) {
   if (res >= *v.n_valid) return;
   const InstCap ic = v.caps[inst];
   if (!v.marginal) {
-    if (threadIdx.x == 0) {
+    if (wave_id() == 0) {
       const int32_t c = v.sel_node[res];
-      rec_discover(v, inst, ic, c, v.H[(int64_t)c * TP + col]);
+      rec_discover(v, lane_id() == 0, inst, ic, c, v.H[(int64_t)c * TP + col]);
     }
   } else {
     const int r = v.ranked[res];
     const uint8_t d = v.dmin[r * kMaxKw + col];
-    for (uint32_t p = v.vc_off[r] + threadIdx.x; p < v.vc_off[r + 1]; p += kBlock) {
-      const int32_t x = v.vc_nodes[p];
-      if (v.H[(int64_t)x * TP + col] == d) rec_discover(v, inst, ic, x, d);
+    const uint32_t p0 = v.vc_off[r], p1 = v.vc_off[r + 1];
+    for (uint32_t p = p0 + (threadIdx.x & ~(uint32_t)(kWave - 1)); p < p1; p += kBlock) {
+      const uint32_t q = p + lane_id();
+      const int32_t x = q < p1 ? v.vc_nodes[q] : 0;
+      rec_discover(v, q < p1 && v.H[(int64_t)x * TP + col] == d, inst, ic, x, d);
     }
   }
 }
@@ -132,27 +164,46 @@ __global__ __launch_bounds__(kBlock) void k_rec_layer(RecoverView v, int h) {
   const uint32_t n_items = min(v.lcnt[h], v.lcap);
   const uint32_t waves = gridDim.x * (kBlock / kWave);
   const int lane = lane_id();
+  const uint64_t below = (1ull << lane) - 1;
   const RecItem* list = v.items + (size_t)h * v.lcap;
   const DevGraphView& g = v.g;
   for (uint32_t it = blockIdx.x * (kBlock / kWave) + wave_id(); it < n_items; it += waves) {
     const RecItem item = list[it];
+    // an instance whose node table filled up has lost nodes: this pass only
+    // tells the host to give it a bitmap, so its remaining work is skipped
+    if (v.iflag[item.inst]) continue;
     const InstCap ic = v.caps[item.inst];
     const int col = item.inst % v.T;
     const int32_t q = item.q;
     const uint32_t aq = g.mode ? g.act_node[q] : 0u;   // NODE mode: level of the in-arc's target q
-    for (uint32_t k = lane; k < item.len; k += kWave) {
-      const uint32_t e = item.start + k;                   // position in q's level-sorted row
-      const uint32_t a = g.mode ? aq : g.act_s[e];         // EDGE: level of q -> n = level of n -> q
-      if (a >= (uint32_t)h) continue;
-      const int32_t n = g.col_s[e];
-      const uint32_t hn = v.H[(int64_t)n * TP + col];
-      if (hn >= (uint32_t)h) continue;
-      if (a + 1 != (uint32_t)h && hn + 1 != (uint32_t)h) continue;   // h = 1 + max(a, h_n)
-      const uint32_t fwd = find_arc_dev(g.row_ptr, g.col, g.label, n, g.label[g.eid_s[e]], q);
-      const uint32_t sa = atomicAdd(&v.cnt[item.inst * 2 + 1], 1u);
-      if (sa < ic.acap) v.al[ic.aoff + sa] = fwd;
-      else atomicOr(&v.gst->overflow, v.ovf_bit);
-      rec_discover(v, item.inst, ic, n, hn);
+    for (uint32_t k0 = 0; k0 < item.len; k0 += kWave) {
+      const uint32_t k = k0 + lane;
+      bool take = false;
+      int32_t n = 0;
+      uint32_t hn = 0, fwd = 0;
+      if (k < item.len) {
+        const uint32_t e = item.start + k;                 // position in q's level-sorted row
+        const uint32_t a = g.mode ? aq : g.act_s[e];       // EDGE: level of q -> n = level of n -> q
+        if (a < (uint32_t)h) {
+          n = g.col_s[e];
+          hn = v.H[(int64_t)n * TP + col];
+          // h = 1 + max(a, h_n)
+          take = hn < (uint32_t)h && (a + 1 == (uint32_t)h || hn + 1 == (uint32_t)h);
+          if (take) fwd = g.rev[g.eid_s[e]];               // the arc n -> q, CSR position
+        }
+      }
+      const uint64_t tb = __ballot(take);
+      if (tb == 0) continue;
+      const int lead = __ffsll((unsigned long long)tb) - 1;
+      uint32_t base = 0;
+      if (lane == lead) base = atomicAdd(&v.cnt[item.inst * 2 + 1], (uint32_t)__popcll(tb));
+      base = __shfl(base, lead, kWave);
+      if (take) {
+        const uint32_t sa = base + (uint32_t)__popcll(tb & below);
+        if (sa < ic.acap) v.al[ic.aoff + sa] = fwd;
+        else atomicOr(&v.gst->overflow, v.ovf_bit);
+      }
+      rec_discover(v, take, item.inst, ic, n, hn);
     }
   }
 }
@@ -163,7 +214,43 @@ __global__ __launch_bounds__(kBlock) void k_rec_layer(RecoverView v, int h) {
 // output arena with their header; arcs are written as (src, dst, label).
 __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeView v) {
   const int t = blockIdx.x;
-  if (t >= *v.n_valid) return;
+  if (t >= *v.n_valid) {
+    if (threadIdx.x == 0) v.big[t] = 0;
+    return;
+  }
+  bool skip = (v.gst->overflow & v.skip_bits) != 0;
+  if (!skip) {
+    // inputs beyond big_list go to the bitmap path (k_big_*), run by the host
+    // once this launch has finished
+    const int r0 = v.marginal ? v.ranked[t] : t;
+    uint64_t nn = v.marginal ? v.cg_cnt[r0 * 2] : 0u, na = v.marginal ? v.cg_cnt[r0 * 2 + 1] : 0u;
+    for (int j = 0; j < v.T; ++j) {
+      const InstCap ic = v.caps[t * v.T + j];
+      nn += min(v.cnt[(t * v.T + j) * 2], ic.ncap);
+      na += min(v.cnt[(t * v.T + j) * 2 + 1], ic.acap);
+    }
+    if (nn > v.big_list || na > v.big_list) {
+      if (threadIdx.x == 0) {
+        v.big[t] = 1;
+        atomicOr(&v.gst->overflow, v.marginal ? kOvfBig1 : kOvfBig0);
+      }
+      skip = true;
+    } else if (threadIdx.x == 0) {
+      v.big[t] = 0;
+    }
+  } else if (threadIdx.x == 0) {
+    v.big[t] = 0;
+  }
+  if (skip) {
+    // the phase is repeated or finished elsewhere: record empty CG lists so
+    // nothing reads stale sizes
+    if (!v.marginal && threadIdx.x == 0) {
+      v.cg_cnt[t * 2] = 0;
+      v.cg_cnt[t * 2 + 1] = 0;
+      v.vc_cnt[t] = 0;
+    }
+    return;
+  }
   __shared__ RadixLds lds;
   __shared__ uint32_t s_off;
   __shared__ uint32_t s_sa[kLdsSort], s_sb[kLdsSort];
@@ -271,6 +358,170 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeView v) {
   }
 }
 
+// ---------------------------------------------------------- large results
+//
+// A result whose lists exceed big_list is not sorted by one workgroup: its
+// node ids (or arc positions) are set in a bitmap over all nodes (arcs) by the
+// whole GPU, counted per chunk of kBigChunk words, scanned, and written in id
+// order -- the same sorted, distinct list, in O(n + A) work.  Pass 0 takes the
+// nodes, pass 1 the arcs, pass 2 (CGs only) the V_C nodes: the set nodes with
+// some central hitting level 0.
+
+constexpr uint32_t kBigChunk = 4 * kBlock;   // bitmap words per count / write block
+
+__global__ __launch_bounds__(kBlock) void k_big_clear(uint32_t* bm, uint32_t words) {
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < words; i += gridDim.x * kBlock) bm[i] = 0;
+}
+
+// Sets the ids of every input list of result t (ids outside the node or arc
+// range are never produced; the test only guards the bitmap).
+__global__ __launch_bounds__(kBlock) void k_big_mark(FinalizeView v, int t, int pass, uint32_t* bm) {
+  const uint32_t stride = gridDim.x * kBlock, tid = blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t limit = (pass & 1) ? v.g.A : (uint32_t)v.g.n;
+  if (v.marginal) {
+    const int r = v.ranked[t];
+    const uint32_t cnt = v.cg_cnt[r * 2 + (pass & 1)];
+    const uint32_t* src = (pass & 1) ? v.cg_arcs + v.cg_aoff[r] : v.cg_nodes + v.cg_noff[r];
+    for (uint32_t i = tid; i < cnt; i += stride) {
+      const uint32_t x = src[i];
+      if (x < limit) atomicOr(&bm[x >> 5], 1u << (x & 31u));
+    }
+  }
+  for (int j = 0; j < v.T; ++j) {
+    const int inst = t * v.T + j;
+    const InstCap ic = v.caps[inst];
+    if (pass & 1) {
+      const uint32_t cnt = min(v.cnt[inst * 2 + 1], ic.acap);
+      const uint32_t* src = v.al + ic.aoff;
+      for (uint32_t i = tid; i < cnt; i += stride) {
+        const uint32_t x = src[i];
+        if (x < limit) atomicOr(&bm[x >> 5], 1u << (x & 31u));
+      }
+    } else {
+      const uint32_t cnt = min(v.cnt[inst * 2], ic.ncap);
+      const int32_t* src = v.nl + ic.noff;
+      for (uint32_t i = tid; i < cnt; i += stride) {
+        const uint32_t x = (uint32_t)src[i];
+        if (x < limit) atomicOr(&bm[x >> 5], 1u << (x & 31u));
+      }
+    }
+  }
+}
+
+// Set bits of one word that count for the pass (pass 2: V_C nodes only).
+__device__ inline uint32_t big_bits(const FinalizeView& v, int pass, uint32_t word, uint32_t wi) {
+  if (pass != 2 || word == 0) return word;
+  uint32_t keep = 0;
+  for (uint32_t b = word; b; b &= b - 1) {
+    const int bit = __ffs(b) - 1;
+    const int64_t x = (int64_t)wi * 32 + bit;
+    bool vc = false;
+    for (int c = 0; c < v.Tc; ++c) vc |= v.Hc[x * v.TPc + c] == 0;
+    keep |= (vc ? 1u : 0u) << bit;
+  }
+  return keep;
+}
+
+__global__ __launch_bounds__(kBlock) void k_big_count(FinalizeView v, int pass, const uint32_t* bm,
+                                                      uint32_t words, uint32_t* chunk) {
+  __shared__ uint32_t s32[kBlock / kWave + 1];
+  const uint32_t w0 = blockIdx.x * kBigChunk + threadIdx.x * 4;
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (w0 + k < words) c += __popc(big_bits(v, pass, bm[w0 + k], w0 + k));
+  const uint32_t tot = block_sum<uint32_t, kBlock>(c, s32);
+  if (threadIdx.x == 0) chunk[blockIdx.x] = tot;
+}
+
+// One workgroup: chunk counts -> chunk offsets; places the list (output arena
+// or the CG's lists) and writes its size.  slot[0] receives the list start.
+__global__ __launch_bounds__(kBlock) void k_big_scan(FinalizeView v, int t, int pass, uint32_t* chunk,
+                                                     uint32_t nchunks, uint64_t* slot) {
+  __shared__ uint32_t s32[kBlock / kWave + 1];
+  __shared__ uint32_t s_carry;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (uint32_t b0 = 0; b0 < nchunks; b0 += kBlock) {
+    const uint32_t i = b0 + threadIdx.x;
+    const uint32_t x = i < nchunks ? chunk[i] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<uint32_t, kBlock>(x, s32, &tot);
+    if (i < nchunks) chunk[i] = s_carry + ex;
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const uint32_t m = s_carry;
+  const int r = v.marginal ? v.ranked[t] : t;
+  if (!v.marginal) {
+    if (pass == 2) {
+      v.vc_cnt[r] = m;
+      slot[0] = v.cg_noff[r];
+    } else {
+      v.cg_cnt[r * 2 + pass] = m;
+      slot[0] = pass == 0 ? v.cg_noff[r] : v.cg_aoff[r];
+    }
+    return;
+  }
+  const uint32_t off = atomicAdd(pass == 0 ? &v.gst->out_nodes : &v.gst->out_arcs, m);
+  const uint32_t cap = pass == 0 ? v.out_ncap : v.out_acap;
+  if ((uint64_t)off + m > cap) atomicOr(&v.gst->overflow, 4);
+  slot[0] = off;
+  ResultHdr& hd = v.hdr[t];
+  if (pass == 0) {
+    hd.central = v.sel_node[r];
+    hd.score_c = v.sel_sc[r];
+    hd.score_m = v.sm[r];
+    hd.cg_rank = r;
+    hd.key = v.key[r];
+    hd.node_off = off;
+    hd.n_nodes = m;
+  } else {
+    hd.arc_off = off;
+    hd.n_arcs = m;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_big_write(FinalizeView v, int pass, const uint32_t* bm,
+                                                      uint32_t words, const uint32_t* chunk,
+                                                      const uint64_t* slot) {
+  __shared__ uint32_t s32[kBlock / kWave + 1];
+  const uint32_t w0 = blockIdx.x * kBigChunk + threadIdx.x * 4;
+  uint32_t bits[4], c = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    bits[k] = w0 + k < words ? big_bits(v, pass, bm[w0 + k], w0 + k) : 0u;
+    c += __popc(bits[k]);
+  }
+  uint32_t tot;
+  const uint32_t ex = block_exclusive_scan<uint32_t, kBlock>(c, s32, &tot);
+  const uint64_t base = slot[0] + chunk[blockIdx.x] + ex;
+  if (v.marginal && base + c > (pass == 0 ? v.out_ncap : v.out_acap)) return;   // overflow flagged
+  uint64_t pos = base;
+  const DevGraphView& g = v.g;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    for (uint32_t b = bits[k]; b; b &= b - 1) {
+      const uint32_t id = (w0 + k) * 32 + (uint32_t)(__ffs(b) - 1);
+      if (!v.marginal) {
+        if (pass == 0) v.cg_nodes[pos] = id;
+        else if (pass == 1) v.cg_arcs[pos] = id;
+        else v.vc_tmp[pos] = (int32_t)id;
+      } else if (pass == 0) {
+        v.out_nodes[pos] = (int32_t)id;
+      } else {
+        int32_t* o = v.out_arcs + 3 * pos;
+        o[0] = g.arc_src[id];
+        o[1] = g.col[id];
+        o[2] = g.label[id];
+      }
+      ++pos;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_pack_vc(const uint32_t* vc_cnt, const int32_t* vc_tmp,
                                                     const uint64_t* cg_noff, const int32_t* nsel_p,
                                                     uint32_t* vc_off, int32_t* vc_nodes) {
@@ -314,6 +565,27 @@ void launch_recover(const RecoverView& v, hipStream_t s) {
 
 void launch_finalize(const FinalizeView& v, hipStream_t s) {
   if (v.n_res > 0) k_finalize<<<v.n_res, kBlock, 0, s>>>(v);
+}
+
+void launch_big_finalize(const FinalizeView& v, int t, uint32_t* bm, uint32_t* chunk, uint64_t* slot,
+                         hipStream_t s) {
+  const uint32_t nw = (uint32_t)(((uint64_t)v.g.n + 31) / 32);
+  const uint32_t aw = (uint32_t)(((uint64_t)v.g.A + 31) / 32);
+  // CGs: nodes, V_C (from the node bitmap), then arcs
+  const int order[3] = {0, 2, 1};
+  for (int oi = 0; oi < (v.marginal ? 2 : 3); ++oi) {
+    const int pass = v.marginal ? oi : order[oi];
+    const uint32_t words = (pass == 1) ? aw : nw;
+    const uint32_t nchunks = (words + kBigChunk - 1) / kBigChunk;
+    const unsigned gc = (unsigned)std::min<uint32_t>(4096, (words + kBlock - 1) / kBlock);
+    if (pass != 2) {   // pass 2 reuses the node bitmap of pass 0
+      k_big_clear<<<gc, kBlock, 0, s>>>(bm, words);
+      k_big_mark<<<2048, kBlock, 0, s>>>(v, t, pass, bm);
+    }
+    k_big_count<<<nchunks, kBlock, 0, s>>>(v, pass, bm, words, chunk);
+    k_big_scan<<<1, kBlock, 0, s>>>(v, t, pass, chunk, nchunks, slot);
+    k_big_write<<<nchunks, kBlock, 0, s>>>(v, pass, bm, words, chunk, slot);
+  }
 }
 
 void launch_pack_vc(const uint32_t* vc_cnt, const int32_t* vc_tmp, const uint64_t* cg_noff,

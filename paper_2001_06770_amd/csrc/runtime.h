@@ -90,6 +90,7 @@ struct Lane {
   DevBuf hpool, nl, al, items, sort_a, sort_b;
   DevBuf cg_nodes, cg_arcs, cg_cnt;   // CG lists, kept for the marginal phase
   DevBuf hdr, out_nodes, out_arcs, status;
+  DevBuf bigf, big_bm, big_chunk, big_slot;   // bitmap path of large results
   RecPhase ph[2];                     // [0] CG recovery, [1] RPG recovery + output
   Status* h_status = nullptr;   // pinned
   RunStatus* h_run = nullptr;   // pinned [2]: per-level status, double-buffered
@@ -142,6 +143,7 @@ struct Ctx {
   std::mutex mem_mu;
   hipStream_t user_stream = nullptr;
   uint32_t rec_nc0 = 4096, rec_ac0 = 16384, rec_lcap0 = 1u << 16;   // initial recovery capacities
+  uint64_t big_list = 1u << 20;   // results with longer lists are merged through bitmaps
 
   // graph
   bool loaded = false;
@@ -151,6 +153,7 @@ struct Ctx {
   int32_t mode = 0;
   double abar = 0, alpha = 0;
   DevBuf row_ptr, col, label, nw, kw_nodes, arc_src;
+  DevBuf rev;            // CSR position of every arc's reverse arc
   DevBuf cweight;        // EDGE: label count c of every arc, kept for other alphas
   DevBuf wstat;          // Status holding the c (or node weight) range of the graph
   int32_t nbnd = 1;

@@ -1,9 +1,11 @@
-"""Recovery capacity growth: contexts that start with tiny recovery
-capacities (1-8 nodes, arcs and work chunks per instance) must still give the
-reference implementation's results exactly.  Every query then overflows, so
-this exercises the per-instance growth, the switch from a node table to a
-node bitmap, the repeat of only the CG phase or only the RPG phase, and a
-batch of such queries over two lanes."""
+"""Recovery capacity growth and the bitmap path for large results: contexts
+that start with tiny recovery capacities (1-64 nodes, arcs and work chunks
+per instance), or that send every result with more than a few list entries
+through the bitmap merge, must still give the reference implementation's
+results exactly.  This exercises the per-instance growth, the switch from a
+node table to a node bitmap, the repeat of only the CG phase or only the RPG
+phase, the bitmap merge of CGs (with V_C) and of RPGs, and a batch of such
+queries over two lanes."""
 from __future__ import annotations
 
 import pytest
@@ -27,14 +29,16 @@ def raks():
     return raks
 
 
-@pytest.mark.parametrize("caps", [(1, 1, 1), (8, 8, 4), (64, 2, 1)], ids=["1-1-1", "8-8-4", "64-2-1"])
+@pytest.mark.parametrize("caps,big", [((1, 1, 1), 0), ((8, 8, 4), 0), ((64, 2, 1), 0),
+                                      ((0, 0, 0), 4), ((8, 8, 4), 16)],
+                         ids=["1-1-1", "8-8-4", "64-2-1", "bitmap4", "8-8-4-bitmap16"])
 @pytest.mark.parametrize("name", ["tiny2", "small"])
-def test_tiny_capacities_match_reference(raks, name, caps):
+def test_tiny_capacities_match_reference(raks, name, caps, big):
     g = synth.make_graph(name)
     o = oracle.Oracle(g)
     act = o.activation(g.abar, 0.5)
     qs = synth.make_queries(g, name)[:24]
-    c = raks.Context(0, lanes=2, rec_caps=caps)
+    c = raks.Context(0, lanes=2, rec_caps=caps, big_list=big)
     try:
         c.load_graph(g, alpha=0.5)
         exp = [o.query(act, q) for q in qs]
