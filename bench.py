@@ -82,7 +82,9 @@ def traffic_for(args):
 
 def run_single(ctx, qs, lat, dev_ms):
     arcs = 0
-    for q in qs:
+    for i, q in enumerate(qs):
+        if i and i % 64 == 0:
+            print(f"#   {i}/{len(qs)} queries", file=sys.stderr, flush=True)
         a = time.perf_counter()
         r = ctx.query(q, lean=True)
         lat.append((time.perf_counter() - a) * 1e3)
@@ -149,6 +151,8 @@ def main():
                     help="skip the other path's leg and the serving leg (profiling runs)")
     ap.add_argument("--serve-rates", default="200,1000",
                     help="Poisson arrival rates (queries/s) of the serving leg; '' skips it")
+    ap.add_argument("--queries", type=int, default=0,
+                    help="use only the first N queries of the workload per step (0 = all)")
     ap.add_argument("--serve-queries", type=int, default=256,
                     help="arrivals per rate (at least; see --serve-seconds)")
     ap.add_argument("--serve-seconds", type=float, default=0.0,
@@ -182,6 +186,8 @@ def main():
         sys.exit(1)
     g = synth.make_graph(args.workload)
     qs = synth.make_queries(g, args.workload)
+    if args.queries:
+        qs = qs[:args.queries]
     mode = raks.RAKS_ACT_EDGE if args.mode == "edge" else raks.RAKS_ACT_NODE
     lanes = max(1, args.lanes)
     ctx = raks.Context(0, lanes=lanes)
@@ -225,6 +231,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "activation": args.mode,
                    "queries_per_step": len(qs), "path": args.path,
+                   "queries_used": "all" if not args.queries else f"first {len(qs)}",
                    "lanes": lanes if args.path == "batched" else 1},
         "qps": nq / dt,
         "p50_ms": percentile(lat, 50),

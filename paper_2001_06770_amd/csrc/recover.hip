@@ -161,7 +161,11 @@ __global__ __launch_bounds__(kBlock) void k_rec_seed(RecoverView v) {
 
 template <int TP>
 __global__ __launch_bounds__(kBlock) void k_rec_layer(RecoverView v, int h) {
-  const uint32_t n_items = min(v.lcnt[h], v.lcap);
+  // A layer whose chunk requests ran past its capacity has unwritten slots
+  // below the capacity (a request that did not fit was dropped whole), so it
+  // is not searched at all: the phase is repeated with room for every chunk.
+  if (v.lcnt[h] > v.lcap) return;
+  const uint32_t n_items = v.lcnt[h];
   const uint32_t waves = gridDim.x * (kBlock / kWave);
   const int lane = lane_id();
   const uint64_t below = (1ull << lane) - 1;
