@@ -131,6 +131,14 @@ int raks_get_activations(raks_ctx* ctx, uint8_t* out, int64_t n);
  *   central.  k >= 1 results, beam width w >= k (0 = k) and w <= 256
  *   (Section 3.4); gamma = gamma_num/gamma_den in [0,1] (Eq. 6; 0/0 = 1/2);
  *   max_level in 1..250 (0 = 20, the paper's level bound).
+ *   score_mode (Section 3.3 allows a multiplicative combination): 1 ranks
+ *   by key = S^c * S^m (without marginal keywords: S^c), and Theorem 4 stops
+ *   when the k-th key <= min S^c over CGs without RPG * S^m of the k-th.
+ *   rerank (Section 3.3, ties broken by a sum of edge weights): results of
+ *   equal key are ordered by weight_sum, the sum of the activation levels of
+ *   their arcs, then S^c and CG rank; every RPG whose key does not exceed the
+ *   k-th one's is recovered before the first k are kept, and Theorem 4 stops
+ *   only on a strict inequality.  Values other than 0/1 give RAKS_EINVAL.
  *   alpha: the granularity of Eqs. 1-2 for this query alone, without
  *   reloading (users tune alpha per search, Section 3.1); the levels for an
  *   alpha are built on first use (one pass over the arcs) and the last few
@@ -147,6 +155,8 @@ typedef struct {
     int32_t gamma_den;
     int32_t max_level;
     double alpha;       /* 0: the context's alpha; else in (0,1) for this query only */
+    int32_t score_mode; /* 0: S^r of Eq. 6; 1: the multiplicative combination S^c * S^m */
+    int32_t rerank;     /* 1: RPGs of equal score re-ranked by weight_sum */
 } raks_query_desc;
 
 typedef struct {
@@ -156,7 +166,7 @@ typedef struct {
 /* One result subgraph: a radial pattern graph (Definition 5) or, without
  * marginal keywords, a central graph (Definition 4).  score_c = S^c (Eq. 4),
  * score_m = S^m (Eq. 5), key = gamma_num*S^c + (gamma_den-gamma_num)*S^m,
- * i.e. gamma_den * S^r (Eq. 6).  nodes ascending; arcs in CSR order, i.e. by
+ * i.e. gamma_den * S^r (Eq. 6), or S^c * S^m with score_mode 1.  nodes ascending; arcs in CSR order, i.e. by
  * (src, label, dst); each arc points along the search direction (from a
  * keyword node towards the central node / the central-keyword nodes). */
 typedef struct {
@@ -164,6 +174,7 @@ typedef struct {
     int32_t score_c;
     int32_t score_m;
     int64_t key;
+    int64_t weight_sum;     /* sum of the activation levels of the result's arcs */
     int32_t n_nodes;
     const int32_t* nodes;
     int32_t n_arcs;

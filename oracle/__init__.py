@@ -58,6 +58,7 @@ class _Query(ctypes.Structure):
                 ("marginal", ctypes.c_void_p), ("n_marginal", ctypes.c_int32),
                 ("k", ctypes.c_int32), ("w", ctypes.c_int32), ("gamma_num", ctypes.c_int32),
                 ("gamma_den", ctypes.c_int32), ("max_level", ctypes.c_int32),
+                ("score_mode", ctypes.c_int32), ("rerank", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("shuffle", ctypes.c_uint64)]
 
 
@@ -148,7 +149,8 @@ class Oracle:
         c = np.ascontiguousarray(q.central, np.int32)
         m = np.ascontiguousarray(q.marginal if len(q.marginal) else [0], np.int32)
         cq = _Query(c.ctypes.data, len(q.central), m.ctypes.data, len(q.marginal), q.k,
-                    q.w, q.gamma_num, q.gamma_den, q.max_level, flags, shuffle)
+                    q.w, q.gamma_num, q.gamma_den, q.max_level, getattr(q, "score_mode", 0),
+                    getattr(q, "rerank", 0), flags, shuffle)
         buf = ctypes.POINTER(ctypes.c_int64)()
         ln = ctypes.c_int64(0)
         rc = _lib().orc_query(ctypes.byref(self._cg), act.ctypes.data, ctypes.byref(cq),
@@ -169,8 +171,8 @@ def parse(words: np.ndarray) -> dict:
            "stats": [_stats_dict(w[3:10]), _stats_dict(w[10:17])], "results": []}
     p = 17
     for _ in range(w[1]):
-        central, sc, sm, key, nn = w[p:p + 5]
-        p += 5
+        central, sc, sm, key, wsum, nn = w[p:p + 6]
+        p += 6
         nodes = tuple(w[p:p + nn])
         p += nn
         na = w[p]
@@ -178,5 +180,5 @@ def parse(words: np.ndarray) -> dict:
         arcs = tuple((w[p + 3 * i], w[p + 3 * i + 1], w[p + 3 * i + 2]) for i in range(na))
         p += 3 * na
         out["results"].append({"central": central, "score_c": sc, "score_m": sm, "key": key,
-                               "nodes": nodes, "arcs": arcs})
+                               "weight_sum": wsum, "nodes": nodes, "arcs": arcs})
     return out

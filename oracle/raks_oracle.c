@@ -43,7 +43,15 @@
  *       Lemma 1 test literally;
  *   R19 V_C = CG nodes whose hitting level for some central keyword is 0;
  *   R20 an RPG needs every marginal keyword to reach some node of V_C;
- *       S^m = max over marginal keywords of min over V_C of its hitting level.
+ *       S^m = max over marginal keywords of min over V_C of its hitting level;
+ *   R30 the multiplicative combination of S^c and S^m (Section 3.3 allows
+ *       one) is the integer S^c * S^m (without marginal keywords: S^c), and
+ *       Theorem 4 becomes S^r(k-th) <= min S^c over CGs without RPG * S^m(k-th);
+ *   R31 the re-ranking of ties (Section 3.3) orders RPGs of equal S^r by the
+ *       sum of the activation levels of their arcs; every RPG whose S^r does
+ *       not exceed the k-th one's is recovered before the top k are taken,
+ *       and Theorem 4 must hold strictly, so that no later RPG of equal S^r
+ *       can be missed.  The sum is reported for every result.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -427,10 +435,23 @@ static int cmp_rpg(const void* a, const void* b) {
     return (x->rank > y->rank) - (x->rank < y->rank);
 }
 
+/* R31: (S^r, sum of arc levels, S^c, CG rank) */
+typedef struct { int64_t key; int64_t wsum; int32_t sc; int32_t rank; int64_t t; int64_t sum; } rerank_t;
+
+static int cmp_rerank(const void* a, const void* b) {
+    const rerank_t* x = (const rerank_t*)a; const rerank_t* y = (const rerank_t*)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    if (x->wsum != y->wsum) return x->wsum < y->wsum ? -1 : 1;
+    if (x->sc != y->sc) return x->sc < y->sc ? -1 : 1;
+    return (x->rank > y->rank) - (x->rank < y->rank);
+}
+
 typedef struct {
     const int32_t* central; int32_t n_central;
     const int32_t* marginal; int32_t n_marginal;
     int32_t k, w, gamma_num, gamma_den, max_level;
+    int32_t score_mode;   /* 0: Eq. 6, 1: S^c * S^m (R30) */
+    int32_t rerank;       /* 1: ties of S^r re-ranked by the sum of arc levels (R31) */
     int32_t flags;
     uint64_t shuffle;
 } orc_query_t;
@@ -439,8 +460,8 @@ typedef struct {
  *   [0] status  [1] number of results  [2] number of CGs found
  *   [3..9]  run 1 stats  [10..16] run 2 stats   (levels, end, frontier,
  *                                                e_arc, e_alg, gate_pass, h_writes)
- *   per result: central, S^c, S^m, key, n_nodes, nodes..., n_arcs,
- *               (src, dst, label) per arc.
+ *   per result: central, S^c, S^m, key, sum of arc levels, n_nodes, nodes...,
+ *               n_arcs, (src, dst, label) per arc.
  * Nodes ascending; arcs ascending by CSR position (= by src, label, dst). */
 #define HDR 17
 
@@ -564,7 +585,8 @@ int orc_query(const orc_graph* g, const uint8_t* act, const orc_query_t* q, int6
                     if (!all) continue;
                     has_rpg[r] = 1;
                     sm[r] = smax;                                        /* Eq. 5 */
-                    key[r] = gn * cgs[r].sc + (gd - gn) * (int64_t)smax; /* Eq. 6, scaled by gamma_den */
+                    key[r] = q->score_mode ? (int64_t)cgs[r].sc * smax   /* R30 */
+                                           : gn * cgs[r].sc + (gd - gn) * (int64_t)smax; /* Eq. 6, scaled by gamma_den */
                     ++nrpg;
                 }
                 if (nrpg == nsel) { y.st.end_reason = END_STOP; break; }
@@ -578,7 +600,9 @@ int orc_query(const orc_graph* g, const uint8_t* act, const orc_query_t* q, int6
                     int64_t min_sc = INT64_MAX;
                     for (int64_t r = 0; r < nsel; ++r)
                         if (!has_rpg[r] && cgs[r].sc < min_sc) min_sc = cgs[r].sc;
-                    if (kth.key <= gn * min_sc + (gd - gn) * (int64_t)sm[kth.rank]) {
+                    const int64_t bound = q->score_mode ? min_sc * (int64_t)sm[kth.rank]
+                                                        : gn * min_sc + (gd - gn) * (int64_t)sm[kth.rank];
+                    if (q->rerank ? kth.key < bound : kth.key <= bound) {
                         y.st.end_reason = END_STOP;
                         break;
                     }
@@ -597,39 +621,65 @@ int orc_query(const orc_graph* g, const uint8_t* act, const orc_query_t* q, int6
     /* ---- ranking and output ---- */
     int64_t m = 0;
     for (int64_t r = 0; r < nsel; ++r) {
-        if (M == 0) { has_rpg[r] = 1; sm[r] = 0; key[r] = gn * cgs[r].sc; }
+        if (M == 0) { has_rpg[r] = 1; sm[r] = 0; key[r] = q->score_mode ? cgs[r].sc : gn * cgs[r].sc; }
         if (has_rpg[r]) { ranked[m].key = key[r]; ranked[m].sc = cgs[r].sc; ranked[m].rank = (int32_t)r; ++m; }
     }
     qsort(ranked, (size_t)m, sizeof(rpg_key_t), cmp_rpg);
-    nres = m < q->k ? m : q->k;
-    for (int64_t t = 0; t < nres && rc == 0; ++t) {
+    /* results to build: the top k, or with re-ranking every RPG whose key does
+       not exceed the k-th one's (R31) */
+    int64_t nbuild = m < q->k ? m : q->k;
+    if (q->rerank && nbuild > 0)
+        while (nbuild < m && ranked[nbuild].key <= ranked[q->k - 1].key) ++nbuild;
+    vec_t* rnodes = (vec_t*)calloc((size_t)(nbuild > 0 ? nbuild : 1), sizeof(vec_t));
+    vec_t* rarcs = (vec_t*)calloc((size_t)(nbuild > 0 ? nbuild : 1), sizeof(vec_t));
+    rerank_t* order = (rerank_t*)malloc(sizeof(rerank_t) * (size_t)(nbuild > 0 ? nbuild : 1));
+    for (int64_t t = 0; t < nbuild && rc == 0; ++t) {
         const int32_t r = ranked[t].rank;
-        vec_t nodes = {0}, arcs = {0};
-        for (int64_t k = 0; k < cg_nodes[r].n; ++k) vec_push(&nodes, cg_nodes[r].v[k]);
-        for (int64_t k = 0; k < cg_arcs[r].n; ++k) vec_push(&arcs, cg_arcs[r].v[k]);
+        vec_t* nodes = &rnodes[t];
+        vec_t* arcs = &rarcs[t];
+        for (int64_t k = 0; k < cg_nodes[r].n; ++k) vec_push(nodes, cg_nodes[r].v[k]);
+        for (int64_t k = 0; k < cg_arcs[r].n; ++k) vec_push(arcs, cg_arcs[r].v[k]);
         /* marginal part: SP(m_j, V_C) from the V_C nodes at distance D_j */
         int32_t* starts = (int32_t*)malloc(sizeof(int32_t) * (size_t)(vc[r].n > 0 ? vc[r].n : 1));
         for (int j = 0; j < M && rc == 0; ++j) {
             int64_t ns = 0;
             for (int64_t k = 0; k < vc[r].n; ++k)
                 if (Hm[(size_t)vc[r].v[k] * M + j] == dmin[r * M + j]) starts[ns++] = (int32_t)vc[r].v[k];
-            rc = recover_column(g, act, Hm, M, j, starts, ns, &nodes, &arcs, stamp, stamp_id++, queue);
+            rc = recover_column(g, act, Hm, M, j, starts, ns, nodes, arcs, stamp, stamp_id++, queue);
         }
         free(starts);
-        sort_unique(&nodes);
-        sort_unique(&arcs);
+        sort_unique(nodes);
+        sort_unique(arcs);
+        int64_t wsum = 0;
+        for (int64_t k = 0; k < arcs->n; ++k) wsum += act[arcs->v[k]];
+        order[t].key = ranked[t].key;
+        order[t].wsum = q->rerank ? wsum : 0;
+        order[t].sc = ranked[t].sc;
+        order[t].rank = ranked[t].rank;
+        order[t].t = t;
+        order[t].sum = wsum;
+    }
+    if (q->rerank) qsort(order, (size_t)nbuild, sizeof(rerank_t), cmp_rerank);
+    nres = nbuild < q->k ? nbuild : q->k;
+    for (int64_t i = 0; i < nres && rc == 0; ++i) {
+        const int64_t t = order[i].t;
+        const int32_t r = ranked[t].rank;
+        const vec_t* nodes = &rnodes[t];
+        const vec_t* arcs = &rarcs[t];
         emit(&out, cgs[r].node); emit(&out, cgs[r].sc); emit(&out, sm[r]); emit(&out, key[r]);
-        emit(&out, nodes.n);
-        for (int64_t k = 0; k < nodes.n; ++k) emit(&out, nodes.v[k]);
-        emit(&out, arcs.n);
-        for (int64_t k = 0; k < arcs.n; ++k) {
-            const int64_t e = arcs.v[k];
+        emit(&out, order[i].sum);
+        emit(&out, nodes->n);
+        for (int64_t k = 0; k < nodes->n; ++k) emit(&out, nodes->v[k]);
+        emit(&out, arcs->n);
+        for (int64_t k = 0; k < arcs->n; ++k) {
+            const int64_t e = arcs->v[k];
             int32_t lo = 0, hi = n;   /* source row of arc e */
             while (hi - lo > 1) { int32_t mid = lo + (hi - lo) / 2; if (g->row_ptr[mid] <= e) lo = mid; else hi = mid; }
             emit(&out, lo); emit(&out, g->col[e]); emit(&out, g->label[e]);
         }
-        free(nodes.v); free(arcs.v);
     }
+    for (int64_t t = 0; t < nbuild; ++t) { free(rnodes[t].v); free(rarcs[t].v); }
+    free(rnodes); free(rarcs); free(order);
 
     out.v[0] = status; out.v[1] = nres; out.v[2] = ncg;
     const orc_run_stats* sts[2] = {&st1, &st2};

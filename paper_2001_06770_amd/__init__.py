@@ -49,7 +49,8 @@ class QueryDesc(ctypes.Structure):
                 ("marginal", ctypes.c_void_p), ("n_marginal", ctypes.c_int32),
                 ("k", ctypes.c_int32), ("w", ctypes.c_int32), ("gamma_num", ctypes.c_int32),
                 ("gamma_den", ctypes.c_int32), ("max_level", ctypes.c_int32),
-                ("alpha", ctypes.c_double)]
+                ("alpha", ctypes.c_double), ("score_mode", ctypes.c_int32),
+                ("rerank", ctypes.c_int32)]
 
 
 class Arc(ctypes.Structure):
@@ -59,7 +60,7 @@ class Arc(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("central_node", ctypes.c_int32), ("score_c", ctypes.c_int32),
                 ("score_m", ctypes.c_int32), ("key", ctypes.c_int64),
-                ("n_nodes", ctypes.c_int32), ("nodes", ctypes.POINTER(ctypes.c_int32)),
+                ("weight_sum", ctypes.c_int64), ("n_nodes", ctypes.c_int32), ("nodes", ctypes.POINTER(ctypes.c_int32)),
                 ("n_arcs", ctypes.c_int32), ("arcs", ctypes.POINTER(Arc))]
 
 
@@ -164,6 +165,7 @@ def _results_to_dict(res: Results, lean: bool = False) -> dict:
             arcs = tuple(map(tuple, arcs.tolist()))
         out["results"].append({"central": int(r.central_node), "score_c": int(r.score_c),
                                "score_m": int(r.score_m), "key": int(r.key),
+                               "weight_sum": int(r.weight_sum),
                                "nodes": nodes, "arcs": arcs})
     return out
 
@@ -248,7 +250,8 @@ class Context:
         keep += [c, m]
         return QueryDesc(c.ctypes.data, len(q.central), m.ctypes.data, len(q.marginal), q.k, q.w,
                          getattr(q, "gamma_num", 1), getattr(q, "gamma_den", 2),
-                         getattr(q, "max_level", 20), float(getattr(q, "alpha", 0.0)))
+                         getattr(q, "max_level", 20), float(getattr(q, "alpha", 0.0)),
+                         int(getattr(q, "score_mode", 0)), int(getattr(q, "rerank", 0)))
 
     def query(self, q, lean: bool = False) -> dict:
         keep = []

@@ -380,6 +380,8 @@ void release_view(Lane* L) {
 struct QueryPlan {
   int C, M, TPc, TPm, k, w, L, gn, gd;
   double alpha;   // 0: the context's
+  int score_mode, rerank;
+  int n_build;    // RPGs recovered: k, or w when equal scores are re-ranked
   std::vector<int32_t> central, marginal;
 };
 
@@ -409,6 +411,10 @@ int validate_query(Ctx* c, const raks_query_desc* q, QueryPlan& p) {
   if (p.gn == 0 && p.gd == 0) { p.gn = 1; p.gd = 2; }
   if (p.gd < 1 || p.gd > 1000000 || p.gn < 0 || p.gn > p.gd)
     return fail(RAKS_EINVAL, "gamma must be gamma_num/gamma_den in [0,1]");
+  p.score_mode = q->score_mode;
+  p.rerank = q->rerank;
+  if ((p.score_mode != 0 && p.score_mode != 1) || (p.rerank != 0 && p.rerank != 1))
+    return fail(RAKS_EINVAL, "score_mode and rerank must be 0 or 1");
   p.alpha = q->alpha;
   if (!(p.alpha == 0.0 || (p.alpha > 0.0 && p.alpha < 1.0)))
     return fail(RAKS_EINVAL, "alpha must be 0 (the context's) or in (0,1)");
@@ -416,6 +422,7 @@ int validate_query(Ctx* c, const raks_query_desc* q, QueryPlan& p) {
   if (p.L < 1 || p.L > 250) return fail(RAKS_EINVAL, "max_level must be in 1..250");
   p.TPc = tp_for(p.C);
   p.TPm = tp_for(std::max(p.M, 1));
+  p.n_build = p.rerank ? p.w : p.k;
   return RAKS_OK;
 }
 
@@ -484,6 +491,8 @@ RunView run_view(Lane* L, int kind, int T, DevBuf& H, const QueryPlan& p) {
   r.k = p.k;
   r.gamma_num = p.gn;
   r.gamma_den = p.gd;
+  r.score_mode = p.score_mode;
+  r.rerank = p.rerank;
   r.nsel = &P<Status>(L->status)->nsel;
   r.sel_sc = P<int32_t>(L->sel_sc);
   r.vc_off = P<uint32_t>(L->vc_off);
@@ -952,6 +961,8 @@ int stage_marginal(Lane* L, const QueryPlan& p, QueryRun& q) {
   rv.k = p.k;
   rv.gamma_num = p.gn;
   rv.gamma_den = p.gd;
+  rv.score_mode = p.score_mode;
+  rv.rerank = p.rerank;
   rv.sel_sc = P<int32_t>(L->sel_sc);
   rv.has_rpg = P<int32_t>(L->has_rpg);
   rv.sm = P<int32_t>(L->sm);
@@ -970,6 +981,7 @@ int stage_output(Lane* L, const QueryPlan& p, const QueryRun& q) {
     Timed t(L, 3);
     if (p.M > 0) launch_recover(recover_view(L, 1, L->Hm, p.TPm, &st->nres, q.top2), s);
     launch_finalize(finalize_view(L, 1, &st->nres, p.C, p.TPc), s);
+    if (p.rerank) launch_rerank(P<ResultHdr>(L->hdr), st, p.k, s);
   }
   HIP_OK(hipGetLastError());
   HIP_OK(hipEventRecord(L->q_end, s));
@@ -1028,6 +1040,7 @@ int collect(Lane* L, const QueryPlan& p, raks_results** out, int* ovf) {
     o.score_c = h.score_c;
     o.score_m = h.score_m;
     o.key = h.key;
+    o.weight_sum = h.wsum;
     o.n_nodes = (int32_t)h.n_nodes;
     int32_t* nd = (int32_t*)malloc(sizeof(int32_t) * std::max<uint32_t>(h.n_nodes, 1));
     memcpy(nd, nodes + h.node_off, sizeof(int32_t) * h.n_nodes);
@@ -1068,7 +1081,7 @@ int query_plan_on_lane(Lane* L, const QueryPlan& p, raks_results** out, double t
   RAKS_TRY(dev_alloc(c, L->Hc, (size_t)L->n_pad * p.TPc));
   if (p.M > 0) RAKS_TRY(dev_alloc(c, L->Hm, (size_t)L->n_pad * p.TPm));
   phase_reset(c, L->ph[0], p.w, p.C);
-  phase_reset(c, L->ph[1], p.k, p.M);
+  phase_reset(c, L->ph[1], p.n_build, p.M);
   QueryRun qr;
   RAKS_TRY(ensure_recovery(L, p));   // before any kernel of this query is queued
   RAKS_TRY(stage_central(L, p, qr));
@@ -1085,7 +1098,8 @@ int query_plan_on_lane(Lane* L, const QueryPlan& p, raks_results** out, double t
     const bool redo_cg = (ovf & (1 | kOvfBig0)) != 0;
     if (!redo_cg && !(ovf & 2)) {
       // only RPGs too large for the sort path: their lists are all there
-      RAKS_TRY(big_finalize(L, 1, p, p.k));
+      RAKS_TRY(big_finalize(L, 1, p, p.n_build));
+      if (p.rerank) launch_rerank(P<ResultHdr>(L->hdr), P<Status>(L->status), p.k, L->stream);
       HIP_OK(hipEventRecord(L->q_end, L->stream));
       RAKS_TRY(collect(L, p, out, &ovf));
       continue;

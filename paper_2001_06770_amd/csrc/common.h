@@ -72,6 +72,7 @@ struct ResultHdr {
   int32_t central, score_c, score_m, cg_rank;
   int64_t key;
   uint32_t node_off, n_nodes, arc_off, n_arcs;
+  int64_t wsum;          // sum of the activation levels of the result's arcs
 };
 
 // ------------------------------------------------------------------------

@@ -238,7 +238,7 @@ __device__ int rpg_identify(const RunView& r, RunStatus* st, int level) {
     if (all) {
       s_has[rr] = 1;
       s_sm[rr] = smax;
-      s_key[rr] = gn * r.sel_sc[rr] + (gd - gn) * smax;
+      s_key[rr] = r.score_mode ? (int64_t)r.sel_sc[rr] * smax : gn * r.sel_sc[rr] + (gd - gn) * smax;
       atomicAdd(&s_new, 1);
     }
   }
@@ -267,7 +267,10 @@ __device__ int rpg_identify(const RunView& r, RunStatus* st, int level) {
     __syncthreads();
     if (threadIdx.x == 0) {
       const int kth = s_kth;
-      if (s_key[kth] <= gn * (int64_t)s_minsc + (gd - gn) * (int64_t)s_sm[kth]) s_stop = 1;
+      // Theorem 4; strict when equal scores are re-ranked
+      const int64_t bound = r.score_mode ? (int64_t)s_minsc * s_sm[kth]
+                                         : gn * (int64_t)s_minsc + (gd - gn) * (int64_t)s_sm[kth];
+      if (r.rerank ? s_key[kth] < bound : s_key[kth] <= bound) s_stop = 1;
     }
   }
   __syncthreads();
@@ -558,22 +561,27 @@ __global__ __launch_bounds__(kCtl) void k_select(SelectView v) {
 __global__ __launch_bounds__(kBlock) void k_rank(RankView v) {
   __shared__ int32_t s_has[kMaxW];
   __shared__ int64_t s_key[kMaxW];
-  __shared__ int32_t s_cnt;
+  __shared__ int32_t s_cnt, s_build;
+  __shared__ int64_t s_kkey;
   const int nsel = *v.nsel;
-  if (threadIdx.x == 0) s_cnt = 0;
+  if (threadIdx.x == 0) { s_cnt = 0; s_build = 0; }
   __syncthreads();
   for (int r = threadIdx.x; r < nsel; r += kBlock) {
     if (v.M == 0) {
       v.has_rpg[r] = 1;
       v.sm[r] = 0;
-      v.key[r] = (int64_t)v.gamma_num * v.sel_sc[r];
+      v.key[r] = v.score_mode ? (int64_t)v.sel_sc[r] : (int64_t)v.gamma_num * v.sel_sc[r];
     }
     s_has[r] = v.has_rpg[r];
     s_key[r] = v.key[r];
     if (s_has[r]) atomicAdd(&s_cnt, 1);
   }
   __syncthreads();
-  for (int r = threadIdx.x; r < nsel; r += kBlock) {
+  // results built: the top k; when re-ranking, every RPG whose key does not
+  // exceed the k-th one's
+  int myrank[kMaxW / kBlock + 1];
+  for (int r = threadIdx.x, i = 0; r < nsel; r += kBlock, ++i) {
+    myrank[i] = -1;
     if (!s_has[r]) continue;
     int rank = 0;
     for (int o = 0; o < nsel; ++o) {
@@ -582,9 +590,44 @@ __global__ __launch_bounds__(kBlock) void k_rank(RankView v) {
               (s_key[o] == s_key[r] && (v.sel_sc[o] < v.sel_sc[r] ||
                                         (v.sel_sc[o] == v.sel_sc[r] && o < r)));
     }
-    if (rank < v.k) v.ranked[rank] = r;
+    myrank[i] = rank;
+    if (rank == v.k - 1) s_kkey = s_key[r];
   }
-  if (threadIdx.x == 0) v.gst->nres = min(s_cnt, v.k);
+  __syncthreads();
+  const bool full = s_cnt >= v.k;
+  for (int r = threadIdx.x, i = 0; r < nsel; r += kBlock, ++i) {
+    if (myrank[i] < 0) continue;
+    const bool build = v.rerank ? (!full || s_key[r] <= s_kkey) : myrank[i] < v.k;
+    if (build) {
+      v.ranked[myrank[i]] = r;
+      atomicAdd(&s_build, 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) v.gst->nres = s_build;
+}
+
+// Re-ranking (Section 3.3): results of equal score ordered by the sum of
+// their arcs' activation levels, then S^c and CG rank; the first k are kept.
+__global__ __launch_bounds__(kBlock) void k_rerank(ResultHdr* hdr, Status* gst, int32_t k) {
+  __shared__ ResultHdr s_h[kMaxW];
+  if (gst->overflow) return;   // the pass is incomplete: the host repeats or finishes it first
+  const int n = gst->nres;
+  for (int i = threadIdx.x; i < n; i += kBlock) s_h[i] = hdr[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    const ResultHdr& a = s_h[i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const ResultHdr& b = s_h[j];
+      rank += b.key < a.key ||
+              (b.key == a.key && (b.wsum < a.wsum ||
+              (b.wsum == a.wsum && (b.score_c < a.score_c ||
+              (b.score_c == a.score_c && b.cg_rank < a.cg_rank)))));
+    }
+    hdr[rank] = a;
+  }
+  if (threadIdx.x == 0) gst->nres = min(n, k);
 }
 
 __global__ void k_clear_rpg(int32_t* has, int32_t* sm, int64_t* key, int n) {
@@ -643,5 +686,9 @@ void launch_expand(const RunView& r, int TP, const DevGraphView& g, int level, i
 void launch_select(const SelectView& v, hipStream_t s) { k_select<<<1, kCtl, 0, s>>>(v); }
 
 void launch_rank(const RankView& v, hipStream_t s) { k_rank<<<1, kBlock, 0, s>>>(v); }
+
+void launch_rerank(ResultHdr* hdr, Status* gst, int32_t k, hipStream_t s) {
+  k_rerank<<<1, kBlock, 0, s>>>(hdr, gst, k);
+}
 
 }  // namespace raks

@@ -61,6 +61,8 @@ struct RunView {
   uint64_t* cand;        // central run: identified central nodes (S<<48 | sum<<32 | node)
   int32_t max_level;
   int32_t w, k, gamma_num, gamma_den;
+  int32_t score_mode;        // 0: Eq. 6, 1: S^c * S^m
+  int32_t rerank;            // 1: ties re-ranked by the arcs' level sum (Theorem 4 strict)
   // marginal run: RPG identification over the selected CGs
   const int32_t* nsel;       // device: number of selected CGs (marginal run)
   const int32_t* sel_sc;     // [nsel] S^c of the selected CGs, in CG rank order
@@ -93,11 +95,12 @@ struct RankView {
   Status* gst;
   const int32_t* nsel;       // device: number of selected CGs
   int32_t M, k, gamma_num, gamma_den;
+  int32_t score_mode, rerank;
   const int32_t* sel_sc;
   int32_t* has_rpg;
   int32_t* sm;
   int64_t* key;
-  int32_t* ranked;     // [k] CG rank of result t
+  int32_t* ranked;     // [k] (re-ranking: [w]) CG rank of result t
 };
 
 // Recovery (Algorithm 2) of every (result, keyword) instance of a phase at
@@ -239,6 +242,8 @@ void launch_expand(const RunView& r, int TP, const DevGraphView& g, int level, i
                    hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_select(const SelectView& v, hipStream_t s);
 void launch_rank(const RankView& v, hipStream_t s);
+// Re-ranking of equal scores by the arcs' level sum; keeps the first k.
+void launch_rerank(ResultHdr* hdr, Status* gst, int32_t k, hipStream_t s);
 void launch_recover(const RecoverView& v, hipStream_t s);   // all layers of one phase
 void launch_finalize(const FinalizeView& v, hipStream_t s);
 // Bitmap path for result t (flagged in v.big): bm holds max(n, A) bits, chunk

@@ -257,6 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeView v) {
   }
   __shared__ RadixLds lds;
   __shared__ uint32_t s_off;
+  __shared__ uint64_t s_ws[kBlock / kWave + 1];
   __shared__ uint32_t s_sa[kLdsSort], s_sb[kLdsSort];
   uint32_t* A_g = v.sort_a + v.soff[t];
   uint32_t* B_g = v.sort_b + v.soff[t];
@@ -322,6 +323,12 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeView v) {
       }
     }
     if (v.write_output) {
+      // sum of the arcs' activation levels (the re-ranking weight); integer, so
+      // any summation order gives the same value
+      uint64_t ws = 0;
+      if (pass == 1)
+        for (uint32_t i = threadIdx.x; i < m; i += kBlock) ws += g.act[uniq[i]];
+      ws = block_sum<uint64_t, kBlock>(ws, s_ws);
       if (threadIdx.x == 0) {
         const uint32_t off = atomicAdd(pass == 0 ? &v.gst->out_nodes : &v.gst->out_arcs, m);
         const uint32_t cap = pass == 0 ? v.out_ncap : v.out_acap;
@@ -339,6 +346,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeView v) {
         } else {
           hd.arc_off = off;
           hd.n_arcs = m;
+          hd.wsum = (int64_t)ws;
         }
       }
       __syncthreads();
@@ -485,13 +493,15 @@ __global__ __launch_bounds__(kBlock) void k_big_scan(FinalizeView v, int t, int 
   } else {
     hd.arc_off = off;
     hd.n_arcs = m;
+    hd.wsum = 0;   // k_big_write adds the arcs' levels
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_big_write(FinalizeView v, int pass, const uint32_t* bm,
-                                                      uint32_t words, const uint32_t* chunk,
-                                                      const uint64_t* slot) {
+__global__ __launch_bounds__(kBlock) void k_big_write(FinalizeView v, int t, int pass,
+                                                      const uint32_t* bm, uint32_t words,
+                                                      const uint32_t* chunk, const uint64_t* slot) {
   __shared__ uint32_t s32[kBlock / kWave + 1];
+  __shared__ uint64_t s_ws[kBlock / kWave + 1];
   const uint32_t w0 = blockIdx.x * kBigChunk + threadIdx.x * 4;
   uint32_t bits[4], c = 0;
 #pragma unroll
@@ -502,9 +512,17 @@ __global__ __launch_bounds__(kBlock) void k_big_write(FinalizeView v, int pass, 
   uint32_t tot;
   const uint32_t ex = block_exclusive_scan<uint32_t, kBlock>(c, s32, &tot);
   const uint64_t base = slot[0] + chunk[blockIdx.x] + ex;
+  const DevGraphView& g = v.g;
+  if (v.marginal && pass == 1) {
+    uint64_t ws = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      for (uint32_t b = bits[k]; b; b &= b - 1) ws += g.act[(w0 + k) * 32 + (uint32_t)(__ffs(b) - 1)];
+    ws = block_sum<uint64_t, kBlock>(ws, s_ws);
+    if (threadIdx.x == 0 && ws) atomicAdd((unsigned long long*)&v.hdr[t].wsum, (unsigned long long)ws);
+  }
   if (v.marginal && base + c > (pass == 0 ? v.out_ncap : v.out_acap)) return;   // overflow flagged
   uint64_t pos = base;
-  const DevGraphView& g = v.g;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     for (uint32_t b = bits[k]; b; b &= b - 1) {
@@ -588,7 +606,7 @@ void launch_big_finalize(const FinalizeView& v, int t, uint32_t* bm, uint32_t* c
     }
     k_big_count<<<nchunks, kBlock, 0, s>>>(v, pass, bm, words, chunk);
     k_big_scan<<<1, kBlock, 0, s>>>(v, t, pass, chunk, nchunks, slot);
-    k_big_write<<<nchunks, kBlock, 0, s>>>(v, pass, bm, words, chunk, slot);
+    k_big_write<<<nchunks, kBlock, 0, s>>>(v, t, pass, bm, words, chunk, slot);
   }
 }
 

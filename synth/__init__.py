@@ -137,6 +137,8 @@ class Query:
     gamma_num: int = 1
     gamma_den: int = 2
     alpha: float = 0.0     # 0: the alpha the graph was loaded with
+    score_mode: int = 0    # 0: gamma-weighted sum of S^c and S^m, 1: their product
+    rerank: int = 0        # 1: equal scores re-ranked by the sum of arc levels
 
 
 GRAPHS = {

@@ -557,3 +557,112 @@ def test_graph_contract_rejections():
             bad.col[0], bad.col[1] = bad.col[1], bad.col[0]   # row 0 out of order
         with pytest.raises(ValueError):
             oracle.Oracle(bad)
+
+
+# ----------------------------------------------------- scoring variants ---
+# The multiplicative combination (Section 3.3, "also applicable"), the tie
+# re-ranking by the sum of edge weights (Section 3.3), and the linear
+# coarsening of Section 3.1.
+
+def arc_levels_sum(g, act, arcs):
+    """Sum of the activation levels of the given (src, dst, label) arcs,
+    located in the CSR arrays independently of the reference's own code."""
+    total = 0
+    for s, d, lab in arcs:
+        lo, hi = int(g.row_ptr[s]), int(g.row_ptr[s + 1])
+        hit = [e for e in range(lo, hi) if int(g.col[e]) == d and int(g.label[e]) == lab]
+        assert len(hit) == 1
+        total += int(act[hit[0]])
+    return total
+
+
+def with_score(q, score_mode=0, rerank=0, k=None, w=None):
+    return synth.Query(q.central, q.marginal, q.k if k is None else k, q.w if w is None else w,
+                       q.max_level, q.gamma_num, q.gamma_den, 0.0, score_mode, rerank)
+
+
+@pytest.mark.parametrize("name,n_marginal", [("tiny2", 2), ("small", 2), ("small", 1),
+                                              ("small", 3)])
+def test_multiplicative_score_vs_dial_and_theorem4(name, n_marginal):
+    """S^r = S^c * S^m from Dial distances; early termination with the
+    multiplicative bound gives the same top k as running to the end."""
+    g = synth.make_graph(name)
+    o = oracle.Oracle(g)
+    act = o.activation(g.abar, 0.5)
+    pool = [int(t) for t in synth.top_keywords(g, 60)]
+    rng = np.random.default_rng(30 + n_marginal)
+    qs = synth.make_queries(g, name)[:10]
+    qs = [synth.Query(q.central, tuple(int(t) for t in rng.choice(
+          [t for t in pool if t not in q.central], n_marginal, replace=False)), q.k, q.w,
+          q.max_level) for q in qs]
+    for q in qs:
+        cgs = o.query(act, synth.Query(q.central, (), q.w, q.w, q.max_level))
+        cg_nodes = {r["central"]: r["nodes"] for r in cgs["results"]}
+        order = [(r["score_c"], r["central"]) for r in cgs["results"]]
+        exp = rpg_expectation(g, act, q, cg_nodes, order)
+        exp = sorted((sc * smv, sc, rank, central, smv) for _, sc, rank, central, smv in exp)[:q.k]
+        qm = with_score(q, score_mode=1)
+        full = o.query(act, qm, flags=oracle.FLAG_NO_THM4)
+        got = [(r["key"], r["score_c"], r["central"], r["score_m"]) for r in full["results"]]
+        assert got == [(k, s, c, m) for k, s, _, c, m in exp]
+        early = o.query(act, qm)
+        assert early["results"] == full["results"]
+        assert early["stats"][1]["e_arc"] <= full["stats"][1]["e_arc"]
+
+
+def test_multiplicative_without_marginal_ranks_like_eq6():
+    g = synth.make_graph("small")
+    o = oracle.Oracle(g)
+    act = o.activation(g.abar, 0.5)
+    for q in synth.make_queries(g, "small")[:8]:
+        q0 = synth.Query(q.central, (), q.k, q.w, q.max_level)
+        a = o.query(act, q0)
+        m = o.query(act, with_score(q0, score_mode=1))
+        assert [r["central"] for r in a["results"]] == [r["central"] for r in m["results"]]
+        assert all(r["key"] == r["score_c"] for r in m["results"])
+
+
+@pytest.mark.parametrize("score_mode", [0, 1])
+@pytest.mark.parametrize("name", ["tiny2", "small"])
+def test_rerank_vs_brute_force(name, score_mode):
+    """Re-ranking ties: every RPG (run to the end, k = w) ordered by
+    (S^r, sum of arc levels, S^c, CG rank), first k; the arc-level sums are
+    recomputed from the returned arcs."""
+    g = synth.make_graph(name)
+    o = oracle.Oracle(g)
+    act = o.activation(g.abar, 0.5)
+    qs = synth.make_queries(g, name)[:12]
+    ties = 0
+    for q in qs:
+        cgs = o.query(act, synth.Query(q.central, (), q.w, q.w, q.max_level))
+        rank_of = {r["central"]: i for i, r in enumerate(cgs["results"])}
+        allr = o.query(act, with_score(q, score_mode, k=q.w), flags=oracle.FLAG_NO_THM4)
+        rows = []
+        for r in allr["results"]:
+            ws = arc_levels_sum(g, act, r["arcs"])
+            assert ws == r["weight_sum"]
+            rows.append((r["key"], ws, r["score_c"], rank_of[r["central"]], r["central"],
+                         r["nodes"], r["arcs"]))
+        keys = [x[0] for x in rows]
+        ties += len(keys) - len(set(keys))
+        rows.sort()
+        exp = [(k, ws, c, n, a) for k, ws, _, _, c, n, a in rows[:q.k]]
+        for flags in (0, oracle.FLAG_NO_THM4):
+            got = o.query(act, with_score(q, score_mode, rerank=1), flags=flags)
+            assert [(r["key"], r["weight_sum"], r["central"], r["nodes"], r["arcs"])
+                    for r in got["results"]] == exp
+    assert ties > 0   # the workload has equal scores to re-rank
+
+
+def test_linear_coarsening_is_alpha_half():
+    """A linear map of the rescaled weight onto [0, 2*a_bar] with round half
+    up (the 'simple linear mapping' of Section 3.1) equals Eqs. 1-3 at
+    alpha = 0.5; computed here from independently counted weights."""
+    for name in ("tiny2", "small"):
+        g = synth.make_graph(name)
+        c = independent_label_counts(g).astype(np.float64)
+        x = (np.log(c) - np.log(c.min())) / (np.log(c.max()) - np.log(c.min()))
+        lin = np.floor(2.0 * g.abar * x + 0.5).astype(np.int64)
+        act = oracle.Oracle(g).activation(g.abar, 0.5)
+        close = np.abs(2.0 * g.abar * x - np.round(2.0 * g.abar * x) - 0.5) < 1e-9
+        assert np.array_equal(act[~close], lin[~close])
