@@ -130,7 +130,7 @@ void lane_destroy(Ctx* c, Lane* L) {
   if (!L) return;
   if (L->stream) (void)hipStreamSynchronize(L->stream);
   DevBuf* bufs[] = {&L->Hc, &L->Hm, &L->F, &L->R, &L->tot, &L->off, &L->q_off, &L->q_rs,
-                    &L->q_lo, &L->q_mask, &L->cand, &L->sel_node, &L->sel_sc, &L->sel_sumh,
+                    &L->q_lo, &L->q_mask, &L->cand, &L->s_item, &L->s_cand, &L->sel_node, &L->sel_sc, &L->sel_sumh,
                     &L->has_rpg, &L->sm, &L->key, &L->dmin, &L->ranked, &L->vc_cnt, &L->vc_tmp,
                     &L->vc_off, &L->vc_nodes, &L->hpool, &L->nl, &L->al, &L->items, &L->sort_a,
                     &L->sort_b, &L->cg_nodes, &L->cg_arcs, &L->cg_cnt, &L->hdr, &L->out_nodes,
@@ -429,7 +429,11 @@ int validate_query(Ctx* c, const raks_query_desc* q, QueryPlan& p) {
 int ensure_node_buffers(Lane* L) {
   Ctx* c = L->ctx;
   L->n_pad = (int32_t)(((int64_t)c->n + kScanNodes - 1) / kScanNodes * kScanNodes);
-  L->nblocks = L->n_pad / kScanNodes;
+  // at most kScanGroups scan workgroups, so the control kernel's share of
+  // the totals stays the same on any graph
+  const int32_t chunks = L->n_pad / kScanNodes;
+  L->cpw = (chunks + kScanGroups - 1) / kScanGroups;
+  L->nblocks = (chunks + L->cpw - 1) / L->cpw;
   const size_t np = (size_t)L->n_pad;
   RAKS_TRY(dev_alloc(c, L->F, np));
   RAKS_TRY(dev_alloc(c, L->R, np * 2));
@@ -440,6 +444,8 @@ int ensure_node_buffers(Lane* L) {
   RAKS_TRY(dev_alloc(c, L->q_lo, np * 4));
   RAKS_TRY(dev_alloc(c, L->q_mask, np * 4));
   RAKS_TRY(dev_alloc(c, L->cand, np * 8));
+  RAKS_TRY(dev_alloc(c, L->s_item, np * 16));
+  RAKS_TRY(dev_alloc(c, L->s_cand, np * 8));
   RAKS_TRY(dev_alloc(c, L->sel_node, kMaxW * 4));
   RAKS_TRY(dev_alloc(c, L->sel_sc, kMaxW * 4));
   RAKS_TRY(dev_alloc(c, L->sel_sumh, kMaxW * 4));
@@ -481,6 +487,9 @@ RunView run_view(Lane* L, int kind, int T, DevBuf& H, const QueryPlan& p) {
   r.tot = P<ScanTot>(L->tot);
   r.off = P<ScanOff>(L->off);
   r.nblocks = L->nblocks;
+  r.cpw = L->cpw;
+  r.s_item = P<uint4>(L->s_item);
+  r.s_cand = P<uint64_t>(L->s_cand);
   r.q_lo = P<uint32_t>(L->q_lo);
   r.q_off = P<uint32_t>(L->q_off);
   r.q_rs = P<uint32_t>(L->q_rs);
@@ -542,7 +551,7 @@ int run_levels(Lane* L, RunView& r, int TP, const std::vector<int32_t>& kws, int
     HIP_OK(hipEventRecord(L->lvl_ev[slot], s));
     {
       Timed t(L, 1, level, r.kind);
-      launch_front_write(r, TP, g, level, s);
+      launch_front_move(r, level, s);
     }
     if (c->timing.load() & 1u) {
       // expansion timing: the launch itself stamps the two events

@@ -10,7 +10,9 @@ namespace raks {
 
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kBlock = 256;        // threads per workgroup for most kernels
-constexpr int kScanNodes = 1024;   // nodes per frontier-scan workgroup (4 per thread)
+constexpr int kScanPer = 2;        // frontier flags per scan thread
+constexpr int kScanNodes = 512;    // frontier flags per scan chunk (kBlock * kScanPer)
+constexpr int kScanGroups = 2048;  // at most this many frontier-scan workgroups
 constexpr int kExpandTile = 2048;  // arcs per expansion tile
 constexpr int kMaxKw = 16;         // keywords per run
 constexpr int kMaxW = 256;         // beam width limit
@@ -131,11 +133,10 @@ __device__ inline T block_sum(T v, T* scratch) {
 // exchange (two barriers) for all of them.  `scratch` holds (NT/64 + 1) * N
 // 64-bit words.  v[] is replaced by the exclusive prefixes, tot[] gets the
 // block totals.
-template <int N, int NT>
-__device__ inline void block_exclusive_scan_multi(uint64_t (&v)[N], uint64_t (&tot)[N],
-                                                  uint64_t* scratch) {
+template <int N, int NT, typename T = uint64_t>
+__device__ inline void block_exclusive_scan_multi(T (&v)[N], T (&tot)[N], T* scratch) {
   constexpr int NW = NT / kWave;
-  uint64_t inc[N];
+  T inc[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) inc[k] = wave_inclusive_scan(v[k]);
   if (lane_id() == kWave - 1)
@@ -144,14 +145,14 @@ __device__ inline void block_exclusive_scan_multi(uint64_t (&v)[N], uint64_t (&t
   __syncthreads();
   if (threadIdx.x < N) {
     const int k = threadIdx.x;
-    uint64_t acc = 0;
-    for (int w = 0; w < NW; ++w) { const uint64_t t = scratch[w * N + k]; scratch[w * N + k] = acc; acc += t; }
+    T acc = 0;
+    for (int w = 0; w < NW; ++w) { const T t = scratch[w * N + k]; scratch[w * N + k] = acc; acc += t; }
     scratch[NW * N + k] = acc;
   }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    const uint64_t x = v[k];
+    const T x = v[k];
     v[k] = scratch[wave_id() * N + k] + inc[k] - x;
     tot[k] = scratch[NW * N + k];
   }

@@ -1,17 +1,20 @@
 // explore.hip -- exploration phase (Section 4.2) on gfx950.
 //
 // One level of a run is four launches:
-//   k_front_count   frontier scan: every workgroup takes 4096 frontier flags
-//                   (16 per thread, one 16-byte load), inspects the H rows of
-//                   flagged nodes (complete row -> central node / PTC block,
-//                   keywords with h <= level, degree) and writes its totals;
+//   k_front_count   frontier scan: every workgroup takes a run of 512-flag
+//                   chunks (2 flags per thread), inspects the H row of every
+//                   flagged node once (complete row -> central node / PTC
+//                   block, keywords with h <= level, level slice of the row),
+//                   stages the node's queue entry and central-node key in
+//                   node order, refreshes its reached mask and keeps it in F
+//                   if an expansion retains it; then writes its totals;
 //   k_front_control one workgroup: scans the totals, applies the run's
 //                   identification and termination rules (Theorem identifyCG,
 //                   >= w CGs; the RPG check over each CG's V_C rows and
 //                   Theorem 4), and decides whether this level expands;
-//   k_front_write   Frontier Enqueue: writes the expansion queue in node order
-//                   (node, row start, keyword mask, degree prefix), records
-//                   the identified central nodes and clears F;
+//   k_front_move    Frontier Enqueue: copies the staged entries to the
+//                   expansion queue (node order, arc prefix) and the central
+//                   nodes to the candidate list;
 //   k_expand        Algorithm 1 for every (frontier, arc) pair, balanced by
 //                   arcs: each workgroup takes tiles of 2048 consecutive arcs
 //                   of the concatenated frontier rows, so a hub's arcs spread
@@ -39,9 +42,9 @@ template <> struct RowVec<16> { using T = uint4; };
 template <int TP> struct RMask { using T = uint8_t; };
 template <> struct RMask<16> { using T = uint16_t; };
 template <int TP> using RMaskT = typename RMask<TP>::T;
-// Four consecutive masks as one vector.
-template <int TP> struct RMask4 { using T = uint32_t; };
-template <> struct RMask4<16> { using T = uint2; };
+// The masks of one scan thread's consecutive nodes as one word.
+template <int TP> struct RMaskN { using T = uint16_t; };
+template <> struct RMaskN<16> { using T = uint32_t; };
 
 template <int TP>
 __device__ inline void load_row(const uint8_t* H, int64_t v, uint8_t (&b)[TP]) {
@@ -155,42 +158,102 @@ __device__ inline NodeInfo inspect_node(const RunView& r, const DevGraphView& g,
   return o;
 }
 
+// Every workgroup takes cpw consecutive chunks of kScanNodes frontier flags
+// (kScanPer per thread), inspects each flagged node once and, in node order, stages
+// its queue entry and its central-node key in the workgroup's own slots of
+// the staging arrays (slot = first node of the workgroup + local index).  It
+// also does the node-local parts of Frontier Enqueue at once: the reached
+// mask R of every flagged node is refreshed (every node whose H row changed
+// in the previous expansion is flagged, so R stays equal to H's finite set)
+// and F keeps exactly the frontiers that an expansion retains (line 11).  If
+// the control kernel then ends the run at this level, F is not read again.
 template <int TP>
 __global__ __launch_bounds__(kBlock) void k_front_count(RunView r, DevGraphView g, int level) {
   if (level > r.st->end_level) return;
-  __shared__ uint32_t s32[kBlock / kWave + 1];
-  __shared__ uint64_t s64[kBlock / kWave + 1];
-  const int64_t base = (int64_t)blockIdx.x * kScanNodes + threadIdx.x * 4;
-  const uint32_t fw = *reinterpret_cast<const uint32_t*>(r.F + base);
-  uint32_t nf = 0, nq = 0, nc = 0, wk = 0, hw = 0;
+  __shared__ uint64_t s_multi[(kBlock / kWave + 1) * 5];
+  __shared__ uint32_t s_m32[(kBlock / kWave + 1) * 3];
+  const int64_t wg0 = (int64_t)blockIdx.x * r.cpw * kScanNodes;
+  const int64_t wg1 = min(wg0 + (int64_t)r.cpw * kScanNodes, (int64_t)r.n_pad);
+  uint32_t cq = 0, cc = 0, cw = 0;   // block-uniform running counts of the workgroup
+  uint32_t nf = 0, hw = 0;
   uint64_t dg = 0, dk = 0, gt = 0;
-  if (fw) {
+#pragma unroll 1
+  for (int64_t c0 = wg0; c0 < wg1; c0 += kScanNodes) {
+    const int64_t base = c0 + threadIdx.x * kScanPer;
+    const uint32_t fw = *reinterpret_cast<const uint16_t*>(r.F + base);
+    // what the staging step needs of each node, kept across the block scan
+    uint4 item[kScanPer];        // examined arcs (0: no queue entry), slice start, split, masks
+    uint64_t key[kScanPer];
+    uint32_t bits[kScanPer];     // reached mask | retain << 16 | central node << 17
+    uint32_t v[3] = {0, 0, 0};   // queue entries, central nodes, examined arcs
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kScanPer; ++k) {
+      item[k] = make_uint4(0, 0, 0, 0);
+      key[k] = 0;
+      bits[k] = 0;
       if (!((fw >> (8 * k)) & 0xFF)) continue;
       const NodeInfo o = inspect_node<TP>(r, g, (int32_t)(base + k), level);
       ++nf;
       hw += o.hw;
-      nc += o.cand;
       if (o.active) {
         dg += o.deg;
         dk += (uint64_t)o.deg * __popc(o.mask_new | o.mask_old);
         gt += o.hi;
-        if (o.work) { ++nq; wk += o.work; }
       }
+      item[k] = make_uint4(o.work, o.rs + o.start, o.rs + o.lo, o.mask_new | (o.mask_old << 16));
+      key[k] = o.key;
+      bits[k] = o.reached | (o.retain ? 1u << 16 : 0u) | (o.cand ? 1u << 17 : 0u);
+      v[0] += o.work != 0;
+      v[1] += o.cand;
+      v[2] += o.work;
     }
+    uint32_t t[3];
+    block_exclusive_scan_multi<3, kBlock, uint32_t>(v, t, s_m32);
+    if (fw) {
+      using VN = typename RMaskN<TP>::T;
+      VN* rp = reinterpret_cast<VN*>(reinterpret_cast<RMaskT<TP>*>(r.R) + base);
+      VN cur = *rp;
+      RMaskT<TP> mk[kScanPer];
+      __builtin_memcpy(mk, &cur, sizeof(VN));
+      uint32_t keep = 0;
+      uint32_t q = cq + (uint32_t)v[0], cd = cc + (uint32_t)v[1], wk = cw + (uint32_t)v[2];
+#pragma unroll
+      for (int k = 0; k < kScanPer; ++k) {
+        if (!((fw >> (8 * k)) & 0xFF)) continue;
+        mk[k] = (RMaskT<TP>)(bits[k] & 0xFFFFu);
+        keep |= ((bits[k] >> 16) & 1u) << (8 * k);
+        if (item[k].x) {
+          const uint32_t work = item[k].x;
+          item[k].x = wk;
+          r.s_item[wg0 + q] = item[k];
+          ++q;
+          wk += work;
+        }
+        if (bits[k] & (1u << 17)) r.s_cand[wg0 + cd++] = key[k];
+      }
+      __builtin_memcpy(&cur, mk, sizeof(VN));
+      *rp = cur;
+      *reinterpret_cast<uint16_t*>(r.F + base) = (uint16_t)keep;
+    }
+    cq += (uint32_t)t[0];
+    cc += (uint32_t)t[1];
+    cw += (uint32_t)t[2];
   }
-  ScanTot t;
-  t.nfront = block_sum<uint32_t, kBlock>(nf, s32);
-  t.nq = block_sum<uint32_t, kBlock>(nq, s32);
-  t.ncand = block_sum<uint32_t, kBlock>(nc, s32);
-  t.work = block_sum<uint32_t, kBlock>(wk, s32);
-  t.hw = block_sum<uint32_t, kBlock>(hw, s32);
-  t.pad = 0;
-  t.deg = block_sum<uint64_t, kBlock>(dg, s64);
-  t.degk = block_sum<uint64_t, kBlock>(dk, s64);
-  t.gate = block_sum<uint64_t, kBlock>(gt, s64);
-  if (threadIdx.x == 0) r.tot[blockIdx.x] = t;
+  uint64_t v5[5] = {nf, hw, dg, dk, gt}, t5[5];
+  block_exclusive_scan_multi<5, kBlock>(v5, t5, s_multi);
+  if (threadIdx.x == 0) {
+    ScanTot t;
+    t.nfront = (uint32_t)t5[0];
+    t.nq = cq;
+    t.ncand = cc;
+    t.work = cw;
+    t.hw = (uint32_t)t5[1];
+    t.pad = 0;
+    t.deg = t5[2];
+    t.degk = t5[3];
+    t.gate = t5[4];
+    r.tot[blockIdx.x] = t;
+  }
 }
 
 constexpr int kCtl = 1024;
@@ -354,66 +417,29 @@ __global__ __launch_bounds__(kCtl) void k_front_control(RunView r, int level, Ru
   }
 }
 
-template <int TP>
-__global__ __launch_bounds__(kBlock) void k_front_write(RunView r, DevGraphView g, int level) {
+// Frontier Enqueue, global part: every workgroup of the scan copies its
+// staged queue entries to the workgroup's place in the expansion queue (the
+// control kernel's exclusive prefix), turning the local arc offsets into
+// global ones, and its central nodes to the level's place in the candidate
+// list.  The queue is written only if the level expands.
+__global__ __launch_bounds__(kBlock) void k_front_move(RunView r, int level) {
   const RunStatus* st = r.st;
   if (level > st->end_level) return;
-  __shared__ uint32_t s32[kBlock / kWave + 1];
-  const bool expand = st->expand_on != 0;
-  const int64_t base = (int64_t)blockIdx.x * kScanNodes + threadIdx.x * 4;
-  const uint32_t fw = *reinterpret_cast<const uint32_t*>(r.F + base);
-  NodeInfo o[4];
-  uint32_t nq = 0, nc = 0, wk = 0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    o[k].work = 0;
-    o[k].cand = false;
-    o[k].retain = false;
-    if (!((fw >> (8 * k)) & 0xFF)) continue;
-    o[k] = inspect_node<TP>(r, g, (int32_t)(base + k), level);
-    nq += o[k].work != 0;
-    nc += o[k].cand;
-    wk += o[k].work;
-  }
-  uint32_t t;
-  const uint32_t xq = block_exclusive_scan<uint32_t, kBlock>(nq, s32, &t);
-  const uint32_t xc = block_exclusive_scan<uint32_t, kBlock>(nc, s32, &t);
-  const uint32_t xw = block_exclusive_scan<uint32_t, kBlock>(wk, s32, &t);
-  if (!fw) return;
-  // Every node whose H row changed in the previous expansion is flagged, so
-  // refreshing the masks of the flagged nodes keeps R equal to H's finite set.
-  {
-    using V4 = typename RMask4<TP>::T;
-    V4* rp = reinterpret_cast<V4*>(reinterpret_cast<RMaskT<TP>*>(r.R) + base);
-    V4 cur = *rp;
-    RMaskT<TP> m4[4];
-    __builtin_memcpy(m4, &cur, sizeof(V4));
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if ((fw >> (8 * k)) & 0xFF) m4[k] = (RMaskT<TP>)o[k].reached;
-    __builtin_memcpy(&cur, m4, sizeof(V4));
-    *rp = cur;
-  }
-  const ScanOff bo = r.off[blockIdx.x];
-  uint32_t qpos = bo.q + xq, wpos = bo.work + xw;
-  uint32_t cpos = (st->ncand_total - st->ncand_level) + bo.cand + xc;
-  uint32_t nf = 0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (expand) {
-      if (o[k].work) {
-        r.q_off[qpos] = wpos;
-        r.q_rs[qpos] = o[k].rs + o[k].start;
-        r.q_lo[qpos] = o[k].rs + o[k].lo;
-        r.q_mask[qpos] = o[k].mask_new | (o[k].mask_old << 16);
-        ++qpos;
-        wpos += o[k].work;
-      }
-      nf |= (o[k].retain ? 1u : 0u) << (8 * k);   // line 11: f stays a frontier
+  const ScanTot t = r.tot[blockIdx.x];
+  if (t.nq == 0 && t.ncand == 0) return;
+  const ScanOff o = r.off[blockIdx.x];
+  const int64_t wg0 = (int64_t)blockIdx.x * r.cpw * kScanNodes;
+  if (st->expand_on) {
+    for (uint32_t j = threadIdx.x; j < t.nq; j += kBlock) {
+      const uint4 e = r.s_item[wg0 + j];
+      r.q_off[o.q + j] = o.work + e.x;
+      r.q_rs[o.q + j] = e.y;
+      r.q_lo[o.q + j] = e.z;
+      r.q_mask[o.q + j] = e.w;
     }
-    if (o[k].cand) r.cand[cpos++] = o[k].key;
   }
-  *reinterpret_cast<uint32_t*>(r.F + base) = nf;
+  const uint32_t c0 = (st->ncand_total - st->ncand_level) + o.cand;
+  for (uint32_t j = threadIdx.x; j < t.ncand; j += kBlock) r.cand[c0 + j] = r.s_cand[wg0 + j];
 }
 
 // Algorithm 1 at Glevel `level` over the queued row slices (all of them have
@@ -668,8 +694,8 @@ void launch_front_control(const RunView& r, int TP, int level, RunStatus* mirror
   RAKS_TP_DISPATCH(TP, k_front_control<kTP><<<1, kCtl, 0, s>>>(r, level, mirror));
 }
 
-void launch_front_write(const RunView& r, int TP, const DevGraphView& g, int level, hipStream_t s) {
-  RAKS_TP_DISPATCH(TP, k_front_write<kTP><<<r.nblocks, kBlock, 0, s>>>(r, g, level));
+void launch_front_move(const RunView& r, int level, hipStream_t s) {
+  k_front_move<<<r.nblocks, kBlock, 0, s>>>(r, level);
 }
 
 void launch_expand(const RunView& r, int TP, const DevGraphView& g, int level, int grid,

@@ -135,7 +135,8 @@ __global__ __launch_bounds__(kBlock) void k_act_gather(const uint8_t* act_node,
 
 // Traversal copy of the graph: each row's arcs re-ordered by activation level
 // (counting sort per row, one wavefront per row), plus the row's largest
-// level.  At level l a frontier's arcs with level <= l form a row prefix.
+// level and its entries of the level-major level table.  At level l a
+// frontier's arcs with level <= l form a row prefix.
 __global__ __launch_bounds__(kBlock) void k_sort_rows(const uint32_t* row_ptr, const int32_t* col,
                                                       const uint8_t* act, int32_t n,
                                                       int32_t* col_s, uint8_t* act_s,
@@ -171,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_rows(const uint32_t* row_ptr, c
     hist[4 * lane + 3] = ex + c0 + c1 + c2;
     __builtin_amdgcn_wave_barrier();
     // arcs with level <= l = start of level l + 1
-    if (lane < nbnd) bnd[(size_t)v * nbnd + lane] = hist[lane + 1];
+    if (lane < nbnd) bnd[(size_t)lane * n + v] = hist[lane + 1];
     __builtin_amdgcn_wave_barrier();
     for (uint32_t e = rs + lane; e < re; e += kWave) {
       const uint32_t a = act[e];

@@ -21,7 +21,8 @@ struct DevGraphView {
   const int32_t* arc_src;   // [A] source node of each arc (CSR order)
   const uint32_t* rev;      // [A] CSR position of each arc's reverse arc
   const uint8_t* row_amax;  // [n] largest activation level of the row (0 if empty)
-  const uint32_t* bnd;      // [n][nbnd] arcs of the row with level <= l, l < nbnd
+  const uint32_t* bnd;      // [nbnd][n] arcs of the row with level <= l, l < nbnd
+                            // (level-major: a level's counts of all nodes are contiguous)
   int32_t nbnd;             // levels covered by bnd (1..16)
 };
 
@@ -30,7 +31,7 @@ __device__ inline uint32_t count_le(const DevGraphView& g, int32_t v, int x) {
   if (x < 0) return 0;
   const uint32_t rs = g.row_ptr[v], re = g.row_ptr[v + 1];
   if (x >= (int)g.row_amax[v]) return re - rs;
-  if (x < g.nbnd) return g.bnd[(size_t)v * g.nbnd + x];
+  if (x < g.nbnd) return g.bnd[(size_t)x * g.n + v];
   uint32_t a = rs, b = re;
   while (a < b) {
     const uint32_t m = (a + b) >> 1;
@@ -53,7 +54,10 @@ struct RunView {
   RunStatus* st;
   ScanTot* tot;          // [nblocks]
   ScanOff* off;          // [nblocks]
-  int32_t nblocks;
+  int32_t nblocks;       // frontier-scan workgroups
+  int32_t cpw;           // kScanNodes-chunks per scan workgroup
+  uint4* s_item;         // [n_pad] staged queue entries (local arc prefix, rs, lo, mask)
+  uint64_t* s_cand;      // [n_pad] staged central-node keys
   uint32_t* q_off;       // expansion queue: exclusive prefix of examined arcs [nactive+1]
   uint32_t* q_rs;        // first examined arc (position in the level-sorted row)
   uint32_t* q_lo;        // from here on the arcs have level == l: old keywords join
@@ -236,7 +240,7 @@ void launch_front_count(const RunView& r, int TP, const DevGraphView& g, int lev
 // mirror: device-visible pinned host memory that receives the level's status
 void launch_front_control(const RunView& r, int TP, int level, RunStatus* mirror,
                           hipStream_t s);
-void launch_front_write(const RunView& r, int TP, const DevGraphView& g, int level, hipStream_t s);
+void launch_front_move(const RunView& r, int level, hipStream_t s);
 // ev0 / ev1 (optional): events that receive the kernel's start and end times
 void launch_expand(const RunView& r, int TP, const DevGraphView& g, int level, int grid,
                    hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
