@@ -129,7 +129,7 @@ DevGraphView graph_view(const Lane* L) { return graph_view(L->ctx, *L->view); }
 void lane_destroy(Ctx* c, Lane* L) {
   if (!L) return;
   if (L->stream) (void)hipStreamSynchronize(L->stream);
-  DevBuf* bufs[] = {&L->Hc, &L->Hm, &L->F, &L->R, &L->tot, &L->off, &L->q_off, &L->q_rs,
+  DevBuf* bufs[] = {&L->Hc, &L->Hm, &L->R, &L->tot, &L->off, &L->q_off, &L->q_rs,
                     &L->q_lo, &L->q_mask, &L->cand, &L->s_item, &L->s_cand, &L->sel_node, &L->sel_sc, &L->sel_sumh,
                     &L->has_rpg, &L->sm, &L->key, &L->dmin, &L->ranked, &L->vc_cnt, &L->vc_tmp,
                     &L->vc_off, &L->vc_nodes, &L->hpool, &L->nl, &L->al, &L->items, &L->sort_a,
@@ -296,7 +296,10 @@ int build_view(Ctx* c, Lane* L, AlphaView& v, double alpha) {
   RAKS_TRY(dev_alloc(c, v.col_s, A1 * 4));
   RAKS_TRY(dev_alloc(c, v.act_s, A1));
   RAKS_TRY(dev_alloc(c, v.eid_s, A1 * 4));
-  RAKS_TRY(dev_alloc(c, v.row_amax, (size_t)c->n));
+  // padded to whole scan chunks, which read it in node order
+  const size_t n_pad = ((size_t)c->n + kScanNodes - 1) / kScanNodes * kScanNodes;
+  RAKS_TRY(dev_alloc(c, v.row_amax, n_pad));
+  HIP_OK(hipMemsetAsync(v.row_amax.p, 0, n_pad, s));
   RAKS_TRY(dev_alloc(c, v.bnd, (size_t)c->n * c->nbnd * 4));
   const Status* st = P<Status>(c->wstat);
   DevGraphView g = graph_view(c, v);
@@ -435,7 +438,6 @@ int ensure_node_buffers(Lane* L) {
   L->cpw = (chunks + kScanGroups - 1) / kScanGroups;
   L->nblocks = (chunks + L->cpw - 1) / L->cpw;
   const size_t np = (size_t)L->n_pad;
-  RAKS_TRY(dev_alloc(c, L->F, np));
   RAKS_TRY(dev_alloc(c, L->R, np * 2));
   RAKS_TRY(dev_alloc(c, L->tot, (size_t)L->nblocks * sizeof(ScanTot)));
   RAKS_TRY(dev_alloc(c, L->off, (size_t)L->nblocks * sizeof(ScanOff)));
@@ -480,7 +482,6 @@ RunView run_view(Lane* L, int kind, int T, DevBuf& H, const QueryPlan& p) {
   r.tmask = (T >= 32) ? 0xFFFFFFFFu : ((1u << T) - 1);
   r.block_rule = (kind == RUN_CENTRAL) ? 1 : (T >= 2 ? 1 : 0);
   r.H = P<uint8_t>(H);
-  r.F = P<uint8_t>(L->F);
   r.R = L->R.p;
   r.n_pad = L->n_pad;
   r.st = &P<Status>(L->status)->run[kind];

@@ -1,13 +1,14 @@
 // explore.hip -- exploration phase (Section 4.2) on gfx950.
 //
 // One level of a run is four launches:
-//   k_front_count   frontier scan: every workgroup takes a run of 512-flag
-//                   chunks (2 flags per thread), inspects the H row of every
-//                   flagged node once (complete row -> central node / PTC
-//                   block, keywords with h <= level, level slice of the row),
-//                   stages the node's queue entry and central-node key in
-//                   node order, refreshes its reached mask and keeps it in F
-//                   if an expansion retains it; then writes its totals;
+//   k_front_count   frontier scan: every workgroup takes a run of 512-node
+//                   chunks (2 nodes per thread), reads their H rows and row
+//                   levels in node order, decides frontier membership from
+//                   them, inspects every frontier node once (complete row ->
+//                   central node / PTC block, keywords with h <= level, level
+//                   slice of the row), stages its queue entry and central-node
+//                   key in node order and refreshes its reached mask; then
+//                   writes its totals;
 //   k_front_control one workgroup: scans the totals, applies the run's
 //                   identification and termination rules (Theorem identifyCG,
 //                   >= w CGs; the RPG check over each CG's V_C rows and
@@ -21,9 +22,10 @@
 //                   over many workgroups; one H-row gather serves all keywords
 //                   of the frontier at once.
 // Writes need no atomics (Theorem "lockfree"): every H write of a level
-// stores level+1 into a byte that was INF, every F write stores 1.  The
-// joining flag array is implied by H: a node is blocked exactly when its row
-// is complete, and it is identified at the level equal to its row maximum.
+// stores level+1 into a byte that was INF.  Neither the frontier flags nor
+// the joining flag array is stored, both are implied by H: a node is blocked
+// exactly when its row is complete, and it is identified at the level equal
+// to its row maximum.
 #include <hip/hip_ext.h>
 
 #include <climits>
@@ -66,8 +68,8 @@ __global__ void k_run_reset(RunStatus* st, int32_t empty, const int32_t* nsel) {
 }
 
 template <int TP>
-__global__ __launch_bounds__(kBlock) void k_init_rows(uint8_t* H, uint8_t* F, RMaskT<TP>* R,
-                                                      int32_t n, int32_t n_pad, int32_t T) {
+__global__ __launch_bounds__(kBlock) void k_init_rows(uint8_t* H, RMaskT<TP>* R, int32_t n,
+                                                      int32_t n_pad, int32_t T) {
   uint8_t b[TP];
 #pragma unroll
   for (int i = 0; i < TP; ++i) b[i] = i < T ? kInf : 0;
@@ -77,33 +79,77 @@ __global__ __launch_bounds__(kBlock) void k_init_rows(uint8_t* H, uint8_t* F, RM
   for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n_pad; v += stride) {
     reinterpret_cast<typename RowVec<TP>::T*>(H)[v] = pat;
     R[v] = 0;
-    if (v < n_pad / 16) reinterpret_cast<uint4*>(F)[v] = make_uint4(0, 0, 0, 0);
   }
 }
 
 template <int TP>
-__global__ __launch_bounds__(kBlock) void k_seed(uint8_t* H, uint8_t* F, const int32_t* kw_nodes,
-                                                 SeedList s) {
+__global__ __launch_bounds__(kBlock) void k_seed(uint8_t* H, const int32_t* kw_nodes, SeedList s) {
   const uint32_t total = s.prefix[s.T];
   for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < total; p += gridDim.x * kBlock) {
     int i = 0;
     while (p >= s.prefix[i + 1]) ++i;
     const int32_t v = kw_nodes[s.start[i] + (p - s.prefix[i])];
-    H[(int64_t)v * TP + i] = 0;   // keyword nodes are at distance 0
-    F[v] = 1;                     // and form the first frontier
+    H[(int64_t)v * TP + i] = 0;   // keyword nodes are at distance 0: the first frontier
   }
 }
 
 // --------------------------------------------------------- frontier scan ---
 //
-// Work-efficient form of Algorithm 1 (same H, F and counters).  A frontier f
-// at level l is retained (line 11) exactly when it expands and its row has an
-// arc of level > l: a property of the row, precomputed as row_amax.  A keyword
-// i with h_fi < l expanded f at level l-1 over all arcs of level <= l-1, so
-// only arcs of level exactly l can reach new nodes for it; a keyword with
-// h_fi = l needs all arcs of level <= l.  With rows sorted by level these are
-// the row slices [lo, hi) and [0, hi), read from the per-node level table.
-// Every workgroup scans 1024 frontier flags, 4 per thread.
+// Work-efficient form of Algorithm 1 (same H, frontiers and counters).  A
+// frontier f at level l is retained (line 11) exactly when it expands and its
+// row has an arc of level > l: a property of the row, precomputed as
+// row_amax.  A keyword i with h_fi < l expanded f at level l-1 over all arcs
+// of level <= l-1, so only arcs of level exactly l can reach new nodes for it;
+// a keyword with h_fi = l needs all arcs of level <= l.  With rows sorted by
+// level these are the row slices [lo, hi) and [0, hi), read from the level
+// table.
+//
+// No frontier flags are stored.  By induction over the levels, v is in the
+// level-l frontier exactly when some keyword reached it at level l (line 17
+// set its flag), or it was reached before l, its row has an arc of level
+// > l-1 and it was not blocked at l-1: from the level it is first reached on,
+// a node stays a frontier for as long as it expands and keeps arcs of higher
+// levels, and blocking (a complete row) never ends.  All of this is in the H
+// row and row_amax, which the scan reads in node order.
+
+// What one H row says at level l.
+struct RowState {
+  uint32_t mn, mo, rm;   // keywords with h == l / h < l / h finite
+  uint32_t mx, sum;      // largest finite h and sum of finite h
+  bool complete;         // every byte finite (padding bytes are 0)
+};
+
+template <int TP>
+__device__ inline RowState row_state(const uint8_t (&b)[TP], uint32_t tmask, int level) {
+  RowState st;
+  st.complete = true;
+  uint32_t mn = 0, mo = 0, mx = 0, sum = 0, rm = 0;
+#pragma unroll
+  for (int i = 0; i < TP; ++i) {
+    const uint32_t h = b[i];
+    const bool inf = h == kInf;
+    st.complete &= !inf;
+    rm |= (inf ? 0u : 1u) << i;
+    if (h == (uint32_t)level) mn |= 1u << i;
+    if (h < (uint32_t)level) mo |= 1u << i;
+    mx = (!inf && h > mx) ? h : mx;
+    sum += inf ? 0u : h;
+  }
+  st.mn = mn & tmask;
+  st.mo = mo & tmask;
+  st.rm = rm & tmask;
+  st.mx = mx;
+  st.sum = sum;
+  return st;
+}
+
+__device__ inline bool in_frontier(const RowState& st, uint32_t tmask, uint32_t amax, int level,
+                                   int block_rule) {
+  if (st.mn) return true;   // reached at level l
+  // reached before l, not complete by l-1 where blocking applies, and an arc
+  // of level > l-1 left
+  return st.mo != 0 && (int)amax > level - 1 && !(block_rule && st.mo == tmask);
+}
 
 struct NodeInfo {
   uint32_t mask_new, mask_old;  // keywords with h == level / h < level
@@ -116,36 +162,22 @@ struct NodeInfo {
   uint64_t key;
 };
 
-template <int TP>
+// A frontier node at level l: central-node test, block rule and the slice of
+// its row that the expansion examines.
 __device__ inline NodeInfo inspect_node(const RunView& r, const DevGraphView& g, int32_t v,
-                                        int level) {
-  uint8_t b[TP];
-  load_row<TP>(r.H, v, b);
-  bool complete = true;
-  uint32_t mn = 0, mo = 0, mx = 0, sum = 0, rm = 0;
-#pragma unroll
-  for (int i = 0; i < TP; ++i) {
-    const uint32_t h = b[i];
-    const bool inf = h == kInf;
-    complete &= !inf;
-    rm |= (inf ? 0u : 1u) << i;
-    if (h == (uint32_t)level) mn |= 1u << i;
-    if (h < (uint32_t)level) mo |= 1u << i;
-    mx = (!inf && h > mx) ? h : mx;
-    sum += inf ? 0u : h;
-  }
+                                        const RowState& st, uint32_t amax, int level) {
   NodeInfo o;
-  o.mask_new = mn & r.tmask;
-  o.mask_old = mo & r.tmask;
-  o.reached = rm & r.tmask;
+  o.mask_new = st.mn;
+  o.mask_old = st.mo;
+  o.reached = st.rm;
   o.hw = level >= 1 ? __popc(o.mask_new) : 0;
-  const bool blocked = r.block_rule && complete;
+  const bool blocked = r.block_rule && st.complete;
   o.rs = g.row_ptr[v];
   const uint32_t d = g.row_ptr[v + 1] - o.rs;
   o.active = !blocked && (o.mask_new | o.mask_old) != 0 && d > 0;
   o.deg = o.active ? d : 0;
-  o.cand = (r.kind == RUN_CENTRAL) && complete && mx == (uint32_t)level;
-  o.key = ((uint64_t)mx << 48) | ((uint64_t)sum << 32) | (uint32_t)v;
+  o.cand = (r.kind == RUN_CENTRAL) && st.complete && st.mx == (uint32_t)level;
+  o.key = ((uint64_t)st.mx << 48) | ((uint64_t)st.sum << 32) | (uint32_t)v;
   o.lo = o.hi = o.start = o.work = 0;
   o.retain = false;
   if (o.active) {
@@ -153,20 +185,19 @@ __device__ inline NodeInfo inspect_node(const RunView& r, const DevGraphView& g,
     o.hi = count_le(g, v, level);
     o.start = o.mask_new ? 0 : o.lo;
     o.work = o.hi - o.start;
-    o.retain = g.row_amax[v] > (uint32_t)level;
+    o.retain = amax > (uint32_t)level;
   }
   return o;
 }
 
-// Every workgroup takes cpw consecutive chunks of kScanNodes frontier flags
-// (kScanPer per thread), inspects each flagged node once and, in node order, stages
-// its queue entry and its central-node key in the workgroup's own slots of
-// the staging arrays (slot = first node of the workgroup + local index).  It
-// also does the node-local parts of Frontier Enqueue at once: the reached
-// mask R of every flagged node is refreshed (every node whose H row changed
-// in the previous expansion is flagged, so R stays equal to H's finite set)
-// and F keeps exactly the frontiers that an expansion retains (line 11).  If
-// the control kernel then ends the run at this level, F is not read again.
+// Every workgroup takes cpw consecutive chunks of kScanNodes nodes (kScanPer
+// per thread), reads their H rows and levels in node order, inspects each
+// frontier node once and, in node order, stages its queue entry and its
+// central-node key in the workgroup's own slots of the staging arrays
+// (slot = first node of the workgroup + local index).  It also refreshes the
+// reached mask R of every frontier node: every node whose H row changed in
+// the previous expansion is a frontier now, so R stays equal to H's finite
+// set.
 template <int TP>
 __global__ __launch_bounds__(kBlock) void k_front_count(RunView r, DevGraphView g, int level) {
   if (level > r.st->end_level) return;
@@ -180,19 +211,26 @@ __global__ __launch_bounds__(kBlock) void k_front_count(RunView r, DevGraphView 
 #pragma unroll 1
   for (int64_t c0 = wg0; c0 < wg1; c0 += kScanNodes) {
     const int64_t base = c0 + threadIdx.x * kScanPer;
-    const uint32_t fw = *reinterpret_cast<const uint16_t*>(r.F + base);
+    uint8_t rows[kScanPer][TP];
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) load_row<TP>(r.H, base + k, rows[k]);
+    const uint32_t am2 = *reinterpret_cast<const uint16_t*>(g.row_amax + base);
+    uint32_t fw = 0;   // frontier bit per node
     // what the staging step needs of each node, kept across the block scan
     uint4 item[kScanPer];        // examined arcs (0: no queue entry), slice start, split, masks
     uint64_t key[kScanPer];
-    uint32_t bits[kScanPer];     // reached mask | retain << 16 | central node << 17
+    uint32_t bits[kScanPer];     // reached mask | central node << 17
     uint32_t v[3] = {0, 0, 0};   // queue entries, central nodes, examined arcs
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
       item[k] = make_uint4(0, 0, 0, 0);
       key[k] = 0;
       bits[k] = 0;
-      if (!((fw >> (8 * k)) & 0xFF)) continue;
-      const NodeInfo o = inspect_node<TP>(r, g, (int32_t)(base + k), level);
+      const RowState st = row_state<TP>(rows[k], r.tmask, level);
+      const uint32_t amax = (am2 >> (8 * k)) & 0xFFu;
+      if (!in_frontier(st, r.tmask, amax, level, r.block_rule)) continue;
+      fw |= 1u << k;
+      const NodeInfo o = inspect_node(r, g, (int32_t)(base + k), st, amax, level);
       ++nf;
       hw += o.hw;
       if (o.active) {
@@ -202,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void k_front_count(RunView r, DevGraphView 
       }
       item[k] = make_uint4(o.work, o.rs + o.start, o.rs + o.lo, o.mask_new | (o.mask_old << 16));
       key[k] = o.key;
-      bits[k] = o.reached | (o.retain ? 1u << 16 : 0u) | (o.cand ? 1u << 17 : 0u);
+      bits[k] = o.reached | (o.cand ? 1u << 17 : 0u);
       v[0] += o.work != 0;
       v[1] += o.cand;
       v[2] += o.work;
@@ -215,13 +253,11 @@ __global__ __launch_bounds__(kBlock) void k_front_count(RunView r, DevGraphView 
       VN cur = *rp;
       RMaskT<TP> mk[kScanPer];
       __builtin_memcpy(mk, &cur, sizeof(VN));
-      uint32_t keep = 0;
       uint32_t q = cq + (uint32_t)v[0], cd = cc + (uint32_t)v[1], wk = cw + (uint32_t)v[2];
 #pragma unroll
       for (int k = 0; k < kScanPer; ++k) {
-        if (!((fw >> (8 * k)) & 0xFF)) continue;
+        if (!((fw >> k) & 1u)) continue;
         mk[k] = (RMaskT<TP>)(bits[k] & 0xFFFFu);
-        keep |= ((bits[k] >> 16) & 1u) << (8 * k);
         if (item[k].x) {
           const uint32_t work = item[k].x;
           item[k].x = wk;
@@ -233,7 +269,6 @@ __global__ __launch_bounds__(kBlock) void k_front_count(RunView r, DevGraphView 
       }
       __builtin_memcpy(&cur, mk, sizeof(VN));
       *rp = cur;
-      *reinterpret_cast<uint16_t*>(r.F + base) = (uint16_t)keep;
     }
     cq += (uint32_t)t[0];
     cc += (uint32_t)t[1];
@@ -510,7 +545,6 @@ __global__ __launch_bounds__(kBlock) void k_expand(RunView r, DevGraphView g, in
 #pragma unroll
         for (int t = 0; t < TP; ++t)
           if ((mm >> t) & 1u) r.H[(int64_t)nb * TP + t] = (uint8_t)(level + 1);
-        r.F[nb] = 1;
       }
     }
     __syncthreads();
@@ -676,11 +710,11 @@ void launch_run_init(const RunView& r, int TP, int32_t n, const int32_t* kw_node
   k_run_reset<<<1, 1, 0, s>>>(r.st, empty, r.kind == RUN_MARGINAL ? r.nsel : nullptr);
   const unsigned g = (unsigned)std::min<int64_t>(8192, (r.n_pad + kBlock - 1) / kBlock);
   RAKS_TP_DISPATCH(TP, k_init_rows<kTP><<<g, kBlock, 0, s>>>(
-                           r.H, r.F, reinterpret_cast<RMaskT<kTP>*>(r.R), n, r.n_pad, r.T));
+                           r.H, reinterpret_cast<RMaskT<kTP>*>(r.R), n, r.n_pad, r.T));
   const uint32_t total = seeds.prefix[seeds.T];
   if (total > 0) {
     const unsigned gs = (unsigned)std::min<uint32_t>(4096, (total + kBlock - 1) / kBlock);
-    RAKS_TP_DISPATCH(TP, k_seed<kTP><<<gs, kBlock, 0, s>>>(r.H, r.F, kw_nodes, seeds));
+    RAKS_TP_DISPATCH(TP, k_seed<kTP><<<gs, kBlock, 0, s>>>(r.H, kw_nodes, seeds));
   }
   if (r.kind == RUN_MARGINAL) k_clear_rpg<<<1, kBlock, 0, s>>>(r.has_rpg, r.sm, r.key, kMaxW);
 }

@@ -20,7 +20,8 @@ struct DevGraphView {
   const uint32_t* eid_s;    // [A] CSR position of the arc
   const int32_t* arc_src;   // [A] source node of each arc (CSR order)
   const uint32_t* rev;      // [A] CSR position of each arc's reverse arc
-  const uint8_t* row_amax;  // [n] largest activation level of the row (0 if empty)
+  const uint8_t* row_amax;  // [n_pad] largest activation level of the row (0 if empty;
+                            // 0 past n, up to a multiple of kScanNodes)
   const uint32_t* bnd;      // [nbnd][n] arcs of the row with level <= l, l < nbnd
                             // (level-major: a level's counts of all nodes are contiguous)
   int32_t nbnd;             // levels covered by bnd (1..16)
@@ -47,7 +48,6 @@ struct RunView {
   uint32_t tmask;        // (1 << T) - 1
   int32_t block_rule;    // 1: a node reached by every keyword stops expanding (CF)
   uint8_t* H;            // node-keyword matrix [n_pad][TP]; INF = 0xFF, padding bytes 0
-  uint8_t* F;            // frontier flags [n_pad]
   void* R;               // reached-keyword mask per node [n_pad] (u8; u16 when TP == 16):
                          // bit i set iff h_vi is finite at the start of the level
   int32_t n_pad;         // n rounded up to kScanNodes
