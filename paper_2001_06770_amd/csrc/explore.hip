@@ -40,13 +40,47 @@ template <> struct RowVec<4> { using T = uint32_t; };
 template <> struct RowVec<8> { using T = uint2; };
 template <> struct RowVec<16> { using T = uint4; };
 
-// Per-node mask of the keywords whose hitting level is finite.
+// Per-node mask of the keywords whose hitting level is finite: 4 bits per
+// node for up to 4 keywords (two nodes per byte, so the array that every
+// expansion gathers from is half as large), 8 or 16 bits otherwise.  W holds
+// the masks of the two consecutive nodes of one scan thread.
 template <int TP> struct RMask { using T = uint8_t; };
 template <> struct RMask<16> { using T = uint16_t; };
 template <int TP> using RMaskT = typename RMask<TP>::T;
-// The masks of one scan thread's consecutive nodes as one word.
-template <int TP> struct RMaskN { using T = uint16_t; };
-template <> struct RMaskN<16> { using T = uint32_t; };
+
+template <int TP> struct RBits;
+template <> struct RBits<4> {
+  using W = uint8_t;
+  __device__ static uint32_t get(const void* R, int64_t v) {
+    return (reinterpret_cast<const uint8_t*>(R)[v >> 1] >> ((v & 1) * 4)) & 0xFu;
+  }
+  __device__ static W* pair(void* R, int64_t v) { return reinterpret_cast<uint8_t*>(R) + (v >> 1); }
+  __device__ static uint32_t unpack(W w, int k) { return (w >> (4 * k)) & 0xFu; }
+  __device__ static W pack(uint32_t m0, uint32_t m1) { return (W)((m0 & 0xFu) | ((m1 & 0xFu) << 4)); }
+};
+template <> struct RBits<8> {
+  using W = uint16_t;
+  __device__ static uint32_t get(const void* R, int64_t v) {
+    return reinterpret_cast<const uint8_t*>(R)[v];
+  }
+  __device__ static W* pair(void* R, int64_t v) {
+    return reinterpret_cast<W*>(reinterpret_cast<uint8_t*>(R) + v);
+  }
+  __device__ static uint32_t unpack(W w, int k) { return (w >> (8 * k)) & 0xFFu; }
+  __device__ static W pack(uint32_t m0, uint32_t m1) { return (W)((m0 & 0xFFu) | ((m1 & 0xFFu) << 8)); }
+};
+template <> struct RBits<16> {
+  using W = uint32_t;
+  __device__ static uint32_t get(const void* R, int64_t v) {
+    return reinterpret_cast<const uint16_t*>(R)[v];
+  }
+  __device__ static W* pair(void* R, int64_t v) {
+    return reinterpret_cast<W*>(reinterpret_cast<uint16_t*>(R) + v);
+  }
+  __device__ static uint32_t unpack(W w, int k) { return (w >> (16 * k)) & 0xFFFFu; }
+  __device__ static W pack(uint32_t m0, uint32_t m1) { return (m0 & 0xFFFFu) | (m1 << 16); }
+};
+static_assert(kScanPer == 2, "RBits::W holds the masks of two nodes");
 
 template <int TP>
 __device__ inline void load_row(const uint8_t* H, int64_t v, uint8_t (&b)[TP]) {
@@ -248,16 +282,17 @@ __global__ __launch_bounds__(kBlock) void k_front_count(RunView r, DevGraphView 
     uint32_t t[3];
     block_exclusive_scan_multi<3, kBlock, uint32_t>(v, t, s_m32);
     if (fw) {
-      using VN = typename RMaskN<TP>::T;
-      VN* rp = reinterpret_cast<VN*>(reinterpret_cast<RMaskT<TP>*>(r.R) + base);
-      VN cur = *rp;
-      RMaskT<TP> mk[kScanPer];
-      __builtin_memcpy(mk, &cur, sizeof(VN));
+      using RB = RBits<TP>;
+      typename RB::W* rp = RB::pair(r.R, base);
+      const typename RB::W cur = *rp;
+      uint32_t mk[kScanPer];
+#pragma unroll
+      for (int k = 0; k < kScanPer; ++k) mk[k] = RB::unpack(cur, k);
       uint32_t q = cq + (uint32_t)v[0], cd = cc + (uint32_t)v[1], wk = cw + (uint32_t)v[2];
 #pragma unroll
       for (int k = 0; k < kScanPer; ++k) {
         if (!((fw >> k) & 1u)) continue;
-        mk[k] = (RMaskT<TP>)(bits[k] & 0xFFFFu);
+        mk[k] = bits[k] & 0xFFFFu;
         if (item[k].x) {
           const uint32_t work = item[k].x;
           item[k].x = wk;
@@ -267,8 +302,7 @@ __global__ __launch_bounds__(kBlock) void k_front_count(RunView r, DevGraphView 
         }
         if (bits[k] & (1u << 17)) r.s_cand[wg0 + cd++] = key[k];
       }
-      __builtin_memcpy(&cur, mk, sizeof(VN));
-      *rp = cur;
+      *rp = RB::pack(mk[0], mk[1]);
     }
     cq += (uint32_t)t[0];
     cc += (uint32_t)t[1];
@@ -540,7 +574,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(RunView r, DevGraphView g, in
       const uint32_t want = (e < s_lo[j]) ? (mk & 0xFFFFu) : ((mk & 0xFFFFu) | (mk >> 16));
       const int32_t nb = g.col_s[e];
       // keywords that have not reached nb (as of the start of this level)
-      const uint32_t mm = ~(uint32_t)reinterpret_cast<const RMaskT<TP>*>(r.R)[nb] & want;
+      const uint32_t mm = ~RBits<TP>::get(r.R, nb) & want;
       if (mm) {
 #pragma unroll
         for (int t = 0; t < TP; ++t)

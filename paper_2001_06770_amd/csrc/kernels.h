@@ -48,8 +48,9 @@ struct RunView {
   uint32_t tmask;        // (1 << T) - 1
   int32_t block_rule;    // 1: a node reached by every keyword stops expanding (CF)
   uint8_t* H;            // node-keyword matrix [n_pad][TP]; INF = 0xFF, padding bytes 0
-  void* R;               // reached-keyword mask per node [n_pad] (u8; u16 when TP == 16):
-                         // bit i set iff h_vi is finite at the start of the level
+  void* R;               // reached-keyword mask per node [n_pad] (4 bits, two nodes per byte,
+                         // when TP == 4; u8 when TP == 8; u16 when TP == 16): bit i set
+                         // iff h_vi is finite at the start of the level
   int32_t n_pad;         // n rounded up to kScanNodes
   RunStatus* st;
   ScanTot* tot;          // [nblocks]
