@@ -24,6 +24,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "runtime.h"
@@ -144,8 +145,6 @@ void lane_destroy(Ctx* c, Lane* L) {
   for (DevBuf* b : bufs) dev_free(c, *b);
   for (hipEvent_t e : L->ev_pool) (void)hipEventDestroy(e);
   L->ev_pool.clear();
-  for (hipEvent_t& e : L->lvl_ev)
-    if (e) (void)hipEventDestroy(e);
   if (L->q_start) (void)hipEventDestroy(L->q_start);
   if (L->q_end) (void)hipEventDestroy(L->q_end);
   if (L->h_status) (void)hipHostFree(L->h_status);
@@ -175,12 +174,12 @@ int lane_create(Ctx* c, int id, Lane** out) {
       hipHostMalloc((void**)&L->h_hdr, kMaxW * sizeof(ResultHdr), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&L->h_nodes, kSpecNodes * 4, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&L->h_arcs, kSpecArcs * 12, hipHostMallocDefault) != hipSuccess ||
-      hipEventCreate(&L->lvl_ev[0]) != hipSuccess || hipEventCreate(&L->lvl_ev[1]) != hipSuccess ||
       hipEventCreate(&L->q_start) != hipSuccess || hipEventCreate(&L->q_end) != hipSuccess ||
       hipHostGetDevicePointer((void**)&L->d_run, L->h_run, 0) != hipSuccess) {
     lane_destroy(c, L.get());
     return fail(RAKS_EDEVICE, "lane pinned memory / event allocation failed");
   }
+  std::memset(L->h_run, 0, 2 * sizeof(RunStatus));   // no stamp matches before a launch
   const int rc = dev_alloc(c, L->status, sizeof(Status));
   if (rc) {
     lane_destroy(c, L.get());
@@ -522,6 +521,27 @@ __global__ void k_query_reset(Status* st) {
   st->out_arcs = 0;
 }
 
+// Waits until the control launch numbered `want` has published its status in
+// pinned slot `slot`.  The stream is queried now and then, so that a failed
+// stream ends the wait with an error, and so does a stream that has finished
+// without the status (which would mean the launch never ran).
+int wait_status(Lane* L, int slot, uint64_t want) {
+  const volatile uint64_t* seq = &L->h_run[slot].seq;
+  for (uint32_t spin = 1;; ++spin) {
+    if (__atomic_load_n(seq, __ATOMIC_ACQUIRE) == want) return RAKS_OK;
+    if ((spin & 1023u) == 0) {
+      const hipError_t e = hipStreamQuery(L->stream);
+      if (e != hipSuccess && e != hipErrorNotReady)
+        return fail(RAKS_EDEVICE, std::string("stream failed: ") + hipGetErrorString(e));
+      if (e == hipSuccess && __atomic_load_n(seq, __ATOMIC_ACQUIRE) != want)
+        return fail(RAKS_EDEVICE, "the level status was not published");
+      std::this_thread::yield();
+    } else {
+      __builtin_ia32_pause();
+    }
+  }
+}
+
 // One exploration run: the level loop of Figure 3.  The host enqueues level
 // l+1 before it waits for the status of level l, so the GPU never idles on
 // the host's decision; the kernels of a level after the run's end return at
@@ -537,9 +557,12 @@ int run_levels(Lane* L, RunView& r, int TP, const std::vector<int32_t>& kws, int
     launch_run_init(r, TP, c->n, P<int32_t>(c->kw_nodes), seeds, s);
   }
   const int grid = c->num_cu * 8;
-  // The control kernel writes the level's status into the pinned slot; the
-  // slot's event follows it, so the host learns the decision while the
-  // level's enqueue and expansion still run.
+  // The control kernel writes the level's status into the pinned slot and
+  // then stamps it with the launch's number, so the host learns the decision
+  // while the level's enqueue and expansion still run, without an event
+  // (an event record after every control launch costs the stream several
+  // microseconds per level).
+  uint64_t want[2] = {0, 0};
   auto enqueue = [&](int level, int slot) -> int {
     {
       Timed t(L, 1, level, r.kind);
@@ -547,9 +570,9 @@ int run_levels(Lane* L, RunView& r, int TP, const std::vector<int32_t>& kws, int
     }
     {
       Timed t(L, 2, level, r.kind);
-      launch_front_control(r, TP, level, &L->d_run[slot], s);
+      want[slot] = ++L->ctl_seq;
+      launch_front_control(r, TP, level, &L->d_run[slot], want[slot], s);
     }
-    HIP_OK(hipEventRecord(L->lvl_ev[slot], s));
     {
       Timed t(L, 1, level, r.kind);
       launch_front_move(r, level, s);
@@ -569,7 +592,7 @@ int run_levels(Lane* L, RunView& r, int TP, const std::vector<int32_t>& kws, int
   for (int level = 0;; ++level) {
     const int slot = level & 1;
     if (level + 1 <= r.max_level) RAKS_TRY(enqueue(level + 1, slot ^ 1));
-    HIP_OK(hipEventSynchronize(L->lvl_ev[slot]));
+    RAKS_TRY(wait_status(L, slot, want[slot]));
     const RunStatus rs = L->h_run[slot];
     if (c->timing.load()) {
       for (auto& pe : L->pending) {

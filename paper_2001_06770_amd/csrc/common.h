@@ -39,6 +39,7 @@ struct RunStatus {
   uint32_t ncand_total;  // central nodes identified so far
   uint32_t nrpg;         // CGs with an RPG so far (marginal run)
   uint64_t frontier_sum, e_arc, e_alg, gate_pass, h_writes;
+  uint64_t seq;          // host mirror only: number of the control launch that wrote it
 };
 
 struct Status {

@@ -335,20 +335,23 @@ constexpr int kCtl = 1024;
 template <int TP>
 __device__ int rpg_identify(const RunView& r, RunStatus* st, int level) {
   __shared__ uint32_t s_dm[kMaxW * kMaxKw];
-  __shared__ int32_t s_has[kMaxW], s_sm[kMaxW];
+  __shared__ int32_t s_has[kMaxW], s_sm[kMaxW], s_sc[kMaxW];
+  __shared__ uint32_t s_vc[kMaxW + 1];
   __shared__ int64_t s_key[kMaxW];
   __shared__ int32_t s_new, s_nrpg, s_kth, s_minsc, s_stop;
   const int nsel = *r.nsel, M = r.T;
   const int64_t gn = r.gamma_num, gd = r.gamma_den;
   for (int i = threadIdx.x; i < nsel * kMaxKw; i += kCtl) s_dm[i] = kInf;
   for (int i = threadIdx.x; i < nsel; i += kCtl) {
-    s_has[i] = r.has_rpg[i]; s_sm[i] = r.sm[i]; s_key[i] = r.key[i];
+    s_has[i] = r.has_rpg[i]; s_sm[i] = r.sm[i]; s_key[i] = r.key[i]; s_sc[i] = r.sel_sc[i];
   }
+  for (int i = threadIdx.x; i <= nsel; i += kCtl) s_vc[i] = r.vc_off[i];
   if (threadIdx.x == 0) { s_new = 0; s_kth = -1; s_minsc = INT32_MAX; s_stop = 0; }
   __syncthreads();
-  const uint32_t total = r.vc_off[nsel];
+  // D_j of every CG without an RPG: minimum over its V_C rows
+  const uint32_t total = s_vc[nsel];
   for (uint32_t p = threadIdx.x; p < total; p += kCtl) {
-    const int rr = upper_index<uint32_t>(r.vc_off, 0, nsel + 1, p);
+    const int rr = upper_index<uint32_t>(s_vc, 0, nsel + 1, p);
     if (s_has[rr]) continue;
     uint8_t b[TP];
     load_row<TP>(r.H, r.vc_nodes[p], b);
@@ -370,7 +373,7 @@ __device__ int rpg_identify(const RunView& r, RunStatus* st, int level) {
     if (all) {
       s_has[rr] = 1;
       s_sm[rr] = smax;
-      s_key[rr] = r.score_mode ? (int64_t)r.sel_sc[rr] * smax : gn * r.sel_sc[rr] + (gd - gn) * smax;
+      s_key[rr] = r.score_mode ? (int64_t)s_sc[rr] * smax : gn * s_sc[rr] + (gd - gn) * smax;
       atomicAdd(&s_new, 1);
     }
   }
@@ -387,13 +390,13 @@ __device__ int rpg_identify(const RunView& r, RunStatus* st, int level) {
         for (int o = 0; o < nsel; ++o) {
           if (!s_has[o]) continue;
           const bool less = s_key[o] < s_key[rr] ||
-                            (s_key[o] == s_key[rr] && (r.sel_sc[o] < r.sel_sc[rr] ||
-                                                       (r.sel_sc[o] == r.sel_sc[rr] && o < rr)));
+                            (s_key[o] == s_key[rr] && (s_sc[o] < s_sc[rr] ||
+                                                       (s_sc[o] == s_sc[rr] && o < rr)));
           rank += less;
         }
         if (rank == r.k - 1) s_kth = rr;
       } else {
-        atomicMin(&s_minsc, r.sel_sc[rr]);
+        atomicMin(&s_minsc, s_sc[rr]);
       }
     }
     __syncthreads();
@@ -413,40 +416,57 @@ __device__ int rpg_identify(const RunView& r, RunStatus* st, int level) {
 }
 
 // The final status of the level also goes to `mirror` (pinned host memory),
-// so the host learns it without a copy.
+// so the host learns it without a copy or an event: the status is written,
+// made visible to the host, and then stamped with `seq`, the launch's number,
+// which the host polls for.  Every thread loads its scan totals
+// (at most two workgroups' worth) before anything else, so the kernel waits
+// for memory about once before the scan.
+static_assert(kScanGroups <= 2 * kCtl, "the control kernel keeps two scan totals per thread");
+
+__device__ inline void publish(RunStatus* mirror, const RunStatus* st, uint64_t seq) {
+  *mirror = *st;
+  __threadfence_system();
+  *reinterpret_cast<volatile uint64_t*>(&mirror->seq) = seq;
+}
+
 template <int TP>
-__global__ __launch_bounds__(kCtl) void k_front_control(RunView r, int level, RunStatus* mirror) {
+__global__ __launch_bounds__(kCtl) void k_front_control(RunView r, int level, RunStatus* mirror,
+                                                        uint64_t seq) {
   RunStatus* st = r.st;
+  const int nb = r.nblocks;
+  const int per = (nb + kCtl - 1) / kCtl;   // 1 or 2
+  const int b0 = min(nb, (int)threadIdx.x * per), b1 = min(nb, b0 + per);
+  ScanTot t[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    if (b0 + i < b1) t[i] = r.tot[b0 + i];
+    else t[i] = ScanTot{};
+  }
   if (level > st->end_level) {
-    if (threadIdx.x == 0) *mirror = *st;
+    if (threadIdx.x == 0) publish(mirror, st, seq);
     return;
   }
   __shared__ int32_t s_end;
-  const int nb = r.nblocks;
-  const int per = (nb + kCtl - 1) / kCtl;
-  const int b0 = min(nb, (int)threadIdx.x * per), b1 = min(nb, b0 + per);
-  uint32_t nf = 0, nq = 0, nc = 0, wk = 0, hw = 0;
-  uint64_t dg = 0, dk = 0, gt = 0;
-  for (int b = b0; b < b1; ++b) {
-    const ScanTot t = r.tot[b];
-    nf += t.nfront; nq += t.nq; nc += t.ncand; wk += t.work; hw += t.hw;
-    dg += t.deg; dk += t.degk; gt += t.gate;
-  }
   // one pass for all eight values: q, work, cand prefixes; the rest totals
   __shared__ uint64_t s_multi[(kCtl / kWave + 1) * 8];
-  uint64_t vals[8] = {nq, wk, nc, nf, hw, dg, dk, gt};
+  uint64_t vals[8] = {(uint64_t)t[0].nq + t[1].nq, (uint64_t)t[0].work + t[1].work,
+                      (uint64_t)t[0].ncand + t[1].ncand, (uint64_t)t[0].nfront + t[1].nfront,
+                      (uint64_t)t[0].hw + t[1].hw, t[0].deg + t[1].deg, t[0].degk + t[1].degk,
+                      t[0].gate + t[1].gate};
   uint64_t tots[8];
   block_exclusive_scan_multi<8, kCtl>(vals, tots, s_multi);
   uint32_t xq = (uint32_t)vals[0], xw = (uint32_t)vals[1], xc = (uint32_t)vals[2];
   const uint32_t tnq = (uint32_t)tots[0], twk = (uint32_t)tots[1], tnc = (uint32_t)tots[2];
   const uint32_t tnf = (uint32_t)tots[3], thw = (uint32_t)tots[4];
   const uint64_t tdg = tots[5], tdk = tots[6], tgt = tots[7];
-  for (int b = b0; b < b1; ++b) {
-    const ScanTot t = r.tot[b];
-    ScanOff o;
-    o.q = xq; o.work = xw; o.cand = xc; o.pad = 0;
-    r.off[b] = o;
-    xq += t.nq; xw += t.work; xc += t.ncand;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    if (b0 + i < b1) {
+      ScanOff o;
+      o.q = xq; o.work = xw; o.cand = xc; o.pad = 0;
+      r.off[b0 + i] = o;
+      xq += t[i].nq; xw += t[i].work; xc += t[i].ncand;
+    }
   }
   if (threadIdx.x == 0) {
     st->levels = level + 1;
@@ -482,7 +502,7 @@ __global__ __launch_bounds__(kCtl) void k_front_control(RunView r, int level, Ru
       st->e_alg += tdk;
       st->gate_pass += tgt;
     }
-    *mirror = *st;
+    publish(mirror, st, seq);
   }
 }
 
@@ -757,9 +777,9 @@ void launch_front_count(const RunView& r, int TP, const DevGraphView& g, int lev
   RAKS_TP_DISPATCH(TP, k_front_count<kTP><<<r.nblocks, kBlock, 0, s>>>(r, g, level));
 }
 
-void launch_front_control(const RunView& r, int TP, int level, RunStatus* mirror,
+void launch_front_control(const RunView& r, int TP, int level, RunStatus* mirror, uint64_t seq,
                           hipStream_t s) {
-  RAKS_TP_DISPATCH(TP, k_front_control<kTP><<<1, kCtl, 0, s>>>(r, level, mirror));
+  RAKS_TP_DISPATCH(TP, k_front_control<kTP><<<1, kCtl, 0, s>>>(r, level, mirror, seq));
 }
 
 void launch_front_move(const RunView& r, int level, hipStream_t s) {

@@ -238,8 +238,9 @@ void launch_act_node(const DevGraphView& g, const uint8_t* nw, const Status* st,
 void launch_run_init(const RunView& r, int TP, int32_t n, const int32_t* kw_nodes,
                      const SeedList& seeds, hipStream_t s);
 void launch_front_count(const RunView& r, int TP, const DevGraphView& g, int level, hipStream_t s);
-// mirror: device-visible pinned host memory that receives the level's status
-void launch_front_control(const RunView& r, int TP, int level, RunStatus* mirror,
+// mirror: device-visible pinned host memory that receives the level's status,
+// stamped with seq once the rest of it is visible to the host
+void launch_front_control(const RunView& r, int TP, int level, RunStatus* mirror, uint64_t seq,
                           hipStream_t s);
 void launch_front_move(const RunView& r, int level, hipStream_t s);
 // ev0 / ev1 (optional): events that receive the kernel's start and end times

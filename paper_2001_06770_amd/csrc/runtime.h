@@ -94,11 +94,11 @@ struct Lane {
   RecPhase ph[2];                     // [0] CG recovery, [1] RPG recovery + output
   Status* h_status = nullptr;   // pinned
   RunStatus* h_run = nullptr;   // pinned [2]: per-level status, double-buffered
+  uint64_t ctl_seq = 0;         // control launches so far (stamps of h_run)
   RunStatus* d_run = nullptr;   // the same memory as the device addresses it
   ResultHdr* h_hdr = nullptr;   // pinned [kMaxW]
   int32_t* h_nodes = nullptr;   // pinned [kSpecNodes]
   int32_t* h_arcs = nullptr;    // pinned [3 * kSpecArcs]
-  hipEvent_t lvl_ev[2] = {nullptr, nullptr};
   hipEvent_t q_start = nullptr, q_end = nullptr;
 
   // event timing (enabled by the context)
