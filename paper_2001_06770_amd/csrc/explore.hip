@@ -206,6 +206,11 @@ __device__ inline NodeInfo inspect_node(const RunView& r, const DevGraphView& g,
   o.reached = st.rm;
   o.hw = level >= 1 ? __popc(o.mask_new) : 0;
   const bool blocked = r.block_rule && st.complete;
+  // the row bounds and both level-table entries in one round of loads (the
+  // table entries are in bounds whenever their level is below nbnd)
+  const int xl = level - 1, xh = level;
+  const uint32_t blo = (xl >= 0 && xl < g.nbnd) ? g.bnd[(size_t)xl * g.n + v] : 0u;
+  const uint32_t bhi = (xh < g.nbnd) ? g.bnd[(size_t)xh * g.n + v] : 0u;
   o.rs = g.row_ptr[v];
   const uint32_t d = g.row_ptr[v + 1] - o.rs;
   o.active = !blocked && (o.mask_new | o.mask_old) != 0 && d > 0;
@@ -215,8 +220,10 @@ __device__ inline NodeInfo inspect_node(const RunView& r, const DevGraphView& g,
   o.lo = o.hi = o.start = o.work = 0;
   o.retain = false;
   if (o.active) {
-    o.lo = count_le(g, v, level - 1);
-    o.hi = count_le(g, v, level);
+    // arcs of level <= x: none below 0, the whole row from its largest level
+    // on, else the level table (or a search of the row past the table)
+    o.lo = xl < 0 ? 0u : (xl >= (int)amax ? d : (xl < g.nbnd ? blo : count_le(g, v, xl)));
+    o.hi = xh >= (int)amax ? d : (xh < g.nbnd ? bhi : count_le(g, v, xh));
     o.start = o.mask_new ? 0 : o.lo;
     o.work = o.hi - o.start;
     o.retain = amax > (uint32_t)level;
@@ -242,13 +249,26 @@ __global__ __launch_bounds__(kBlock) void k_front_count(RunView r, DevGraphView 
   uint32_t cq = 0, cc = 0, cw = 0;   // block-uniform running counts of the workgroup
   uint32_t nf = 0, hw = 0;
   uint64_t dg = 0, dk = 0, gt = 0;
+  // the next chunk's rows and levels are loaded while this chunk is inspected
+  uint8_t nrows[kScanPer][TP];
+  uint32_t nam2 = 0;
+  {
+    const int64_t b0 = wg0 + threadIdx.x * kScanPer;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) load_row<TP>(r.H, b0 + k, nrows[k]);
+    nam2 = *reinterpret_cast<const uint16_t*>(g.row_amax + b0);
+  }
 #pragma unroll 1
   for (int64_t c0 = wg0; c0 < wg1; c0 += kScanNodes) {
     const int64_t base = c0 + threadIdx.x * kScanPer;
     uint8_t rows[kScanPer][TP];
+    __builtin_memcpy(rows, nrows, sizeof(rows));
+    const uint32_t am2 = nam2;
+    if (c0 + kScanNodes < wg1) {
 #pragma unroll
-    for (int k = 0; k < kScanPer; ++k) load_row<TP>(r.H, base + k, rows[k]);
-    const uint32_t am2 = *reinterpret_cast<const uint16_t*>(g.row_amax + base);
+      for (int k = 0; k < kScanPer; ++k) load_row<TP>(r.H, base + kScanNodes + k, nrows[k]);
+      nam2 = *reinterpret_cast<const uint16_t*>(g.row_amax + base + kScanNodes);
+    }
     uint32_t fw = 0;   // frontier bit per node
     // what the staging step needs of each node, kept across the block scan
     uint4 item[kScanPer];        // examined arcs (0: no queue entry), slice start, split, masks
