@@ -131,7 +131,7 @@ void lane_destroy(Ctx* c, Lane* L) {
   if (!L) return;
   if (L->stream) (void)hipStreamSynchronize(L->stream);
   DevBuf* bufs[] = {&L->Hc, &L->Hm, &L->R, &L->tot, &L->off, &L->q_off, &L->q_rs,
-                    &L->q_lo, &L->q_mask, &L->cand, &L->s_item, &L->s_cand, &L->sel_node, &L->sel_sc, &L->sel_sumh,
+                    &L->q_lo, &L->q_mask, &L->tile_first, &L->cand, &L->s_item, &L->s_cand, &L->sel_node, &L->sel_sc, &L->sel_sumh,
                     &L->has_rpg, &L->sm, &L->key, &L->dmin, &L->ranked, &L->vc_cnt, &L->vc_tmp,
                     &L->vc_off, &L->vc_nodes, &L->hpool, &L->nl, &L->al, &L->items, &L->sort_a,
                     &L->sort_b, &L->cg_nodes, &L->cg_arcs, &L->cg_cnt, &L->hdr, &L->out_nodes,
@@ -444,6 +444,7 @@ int ensure_node_buffers(Lane* L) {
   RAKS_TRY(dev_alloc(c, L->q_rs, np * 4));
   RAKS_TRY(dev_alloc(c, L->q_lo, np * 4));
   RAKS_TRY(dev_alloc(c, L->q_mask, np * 4));
+  RAKS_TRY(dev_alloc(c, L->tile_first, ((size_t)c->A / kExpandTile + 2) * 4));
   RAKS_TRY(dev_alloc(c, L->cand, np * 8));
   RAKS_TRY(dev_alloc(c, L->s_item, np * 16));
   RAKS_TRY(dev_alloc(c, L->s_cand, np * 8));
@@ -494,6 +495,7 @@ RunView run_view(Lane* L, int kind, int T, DevBuf& H, const QueryPlan& p) {
   r.q_off = P<uint32_t>(L->q_off);
   r.q_rs = P<uint32_t>(L->q_rs);
   r.q_mask = P<uint32_t>(L->q_mask);
+  r.tile_first = P<uint32_t>(L->tile_first);
   r.cand = P<uint64_t>(L->cand);
   r.max_level = p.L;
   r.w = p.w;

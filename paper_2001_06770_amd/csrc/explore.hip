@@ -353,7 +353,7 @@ constexpr int kCtl = 1024;
 // (Eq. 6 scaled by gamma_den).  Then the stop rules: every CG has an RPG, or
 // Theorem 4 with the k-th RPG in (key, S^c, CG rank) order.
 template <int TP>
-__device__ int rpg_identify(const RunView& r, RunStatus* st, int level) {
+__device__ int rpg_identify(const RunView& r, uint32_t* nrpg_io, int level) {
   __shared__ uint32_t s_dm[kMaxW * kMaxKw];
   __shared__ int32_t s_has[kMaxW], s_sm[kMaxW], s_sc[kMaxW];
   __shared__ uint32_t s_vc[kMaxW + 1];
@@ -398,7 +398,7 @@ __device__ int rpg_identify(const RunView& r, RunStatus* st, int level) {
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) { s_nrpg = (int)st->nrpg + s_new; st->nrpg = (uint32_t)s_nrpg; }
+  if (threadIdx.x == 0) { s_nrpg = (int)*nrpg_io + s_new; *nrpg_io = (uint32_t)s_nrpg; }
   __syncthreads();
   const int nrpg = s_nrpg;
   if (nrpg == nsel) {
@@ -443,8 +443,8 @@ __device__ int rpg_identify(const RunView& r, RunStatus* st, int level) {
 // for memory about once before the scan.
 static_assert(kScanGroups <= 2 * kCtl, "the control kernel keeps two scan totals per thread");
 
-__device__ inline void publish(RunStatus* mirror, const RunStatus* st, uint64_t seq) {
-  *mirror = *st;
+__device__ inline void publish(RunStatus* mirror, const RunStatus& st, uint64_t seq) {
+  *mirror = st;
   __threadfence_system();
   *reinterpret_cast<volatile uint64_t*>(&mirror->seq) = seq;
 }
@@ -462,11 +462,15 @@ __global__ __launch_bounds__(kCtl) void k_front_control(RunView r, int level, Ru
     if (b0 + i < b1) t[i] = r.tot[b0 + i];
     else t[i] = ScanTot{};
   }
+  // thread 0 keeps the run's status in registers and stores it once
+  RunStatus cur;
+  if (threadIdx.x == 0) cur = *st;
   if (level > st->end_level) {
-    if (threadIdx.x == 0) publish(mirror, st, seq);
+    if (threadIdx.x == 0) publish(mirror, cur, seq);
     return;
   }
   __shared__ int32_t s_end;
+  __shared__ uint32_t s_nrpg;
   // one pass for all eight values: q, work, cand prefixes; the rest totals
   __shared__ uint64_t s_multi[(kCtl / kWave + 1) * 8];
   uint64_t vals[8] = {(uint64_t)t[0].nq + t[1].nq, (uint64_t)t[0].work + t[1].work,
@@ -489,48 +493,57 @@ __global__ __launch_bounds__(kCtl) void k_front_control(RunView r, int level, Ru
     }
   }
   if (threadIdx.x == 0) {
-    st->levels = level + 1;
-    st->nfront = tnf;
-    st->nactive = tnq;
-    st->W = twk;
-    st->ncand_level = tnc;
-    st->frontier_sum += tnf;
-    st->h_writes += thw;
+    cur.levels = level + 1;
+    cur.nfront = tnf;
+    cur.nactive = tnq;
+    cur.W = twk;
+    cur.ncand_level = tnc;
+    cur.frontier_sum += tnf;
+    cur.h_writes += thw;
     r.q_off[tnq] = twk;
     s_end = END_NONE;
     if (tnf == 0) {
       s_end = END_EXHAUSTED;
     } else if (r.kind == RUN_CENTRAL) {
-      st->ncand_total += tnc;
-      if (st->ncand_total >= (uint32_t)r.w) s_end = END_STOP;
+      cur.ncand_total += tnc;
+      if (cur.ncand_total >= (uint32_t)r.w) s_end = END_STOP;
     }
+    s_nrpg = cur.nrpg;
   }
   __syncthreads();
   if (s_end == END_NONE && r.kind == RUN_MARGINAL) {
-    if (rpg_identify<TP>(r, st, level) && threadIdx.x == 0) s_end = END_STOP;
+    if (rpg_identify<TP>(r, &s_nrpg, level) && threadIdx.x == 0) s_end = END_STOP;
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    if (s_end == END_NONE && level >= r.max_level) s_end = END_LEVEL_BOUND;
-    if (s_end != END_NONE) {
-      st->end_level = level;
-      st->end_reason = s_end;
-      st->expand_on = 0;
+    cur.nrpg = s_nrpg;
+    int end = s_end;
+    if (end == END_NONE && level >= r.max_level) end = END_LEVEL_BOUND;
+    if (end != END_NONE) {
+      cur.end_level = level;
+      cur.end_reason = end;
+      cur.expand_on = 0;
     } else {
-      st->expand_on = 1;
-      st->e_arc += tdg;
-      st->e_alg += tdk;
-      st->gate_pass += tgt;
+      cur.expand_on = 1;
+      cur.e_arc += tdg;
+      cur.e_alg += tdk;
+      cur.gate_pass += tgt;
     }
-    publish(mirror, st, seq);
+    *st = cur;
+    publish(mirror, cur, seq);
   }
 }
+
+constexpr uint32_t kTileAtEntry = 0x80000000u;   // tile_first: the tile starts with the entry
 
 // Frontier Enqueue, global part: every workgroup of the scan copies its
 // staged queue entries to the workgroup's place in the expansion queue (the
 // control kernel's exclusive prefix), turning the local arc offsets into
 // global ones, and its central nodes to the level's place in the candidate
-// list.  The queue is written only if the level expands.
+// list.  For every expansion tile (kExpandTile consecutive arcs of the
+// concatenated slices) it also records the queue entry that holds the tile's
+// first arc, so a tile finds its entries with one load.  The queue is written
+// only if the level expands.
 __global__ __launch_bounds__(kBlock) void k_front_move(RunView r, int level) {
   const RunStatus* st = r.st;
   if (level > st->end_level) return;
@@ -541,26 +554,30 @@ __global__ __launch_bounds__(kBlock) void k_front_move(RunView r, int level) {
   if (st->expand_on) {
     for (uint32_t j = threadIdx.x; j < t.nq; j += kBlock) {
       const uint4 e = r.s_item[wg0 + j];
-      r.q_off[o.q + j] = o.work + e.x;
+      const uint32_t start = o.work + e.x;
+      const uint32_t end = o.work + (j + 1 < t.nq ? r.s_item[wg0 + j + 1].x : t.work);
+      r.q_off[o.q + j] = start;
       r.q_rs[o.q + j] = e.y;
       r.q_lo[o.q + j] = e.z;
       r.q_mask[o.q + j] = e.w;
+      // expansion tiles whose first arc falls in this entry start at it
+      for (uint32_t tl = (start + kExpandTile - 1) / kExpandTile; tl * kExpandTile < end; ++tl)
+        r.tile_first[tl] = (o.q + j) | (tl * kExpandTile == start ? kTileAtEntry : 0u);
     }
   }
   const uint32_t c0 = (st->ncand_total - st->ncand_level) + o.cand;
   for (uint32_t j = threadIdx.x; j < t.ncand; j += kBlock) r.cand[c0 + j] = r.s_cand[wg0 + j];
 }
 
-// Algorithm 1 at Glevel `level` over the queued row slices (all of them have
+// Algorithm 1 at level `level` over the queued row slices (all of them have
 // level <= l).  For arc f -> n every keyword i that f expands for and that has
-// not reached n gets h_ni = level + 1 and n becomes a frontier (lines 13-17).
-// One TP-byte row gather of the neighbour serves every keyword at once.
-// Tile of 2048 consecutive arcs of the concatenated slices: two
-// wavefronts find the first and last queue entry of the tile (64-ary
-// search), the entries go to LDS, each entry marks the tile item where it
-// starts and a block max-scan turns the marks into the owner entry of every
-// item; item i of the tile is handled by thread i mod 256, so consecutive
-// lanes read consecutive arcs.
+// not reached n gets h_ni = level + 1, which makes n a frontier of the next
+// level (lines 13-17).  One gather of the neighbour's reached mask serves
+// every keyword at once.  Tile of 2048 consecutive arcs of the concatenated
+// slices: the tile map gives its first and last queue entry, the entries go
+// to LDS, each entry marks the tile item where it starts and a block max-scan
+// turns the marks into the owner entry of every item; item i of the tile is
+// handled by thread i mod 256, so consecutive lanes read consecutive arcs.
 template <int TP>
 __global__ __launch_bounds__(kBlock) void k_expand(RunView r, DevGraphView g, int level) {
   RunStatus* st = r.st;
@@ -573,17 +590,21 @@ __global__ __launch_bounds__(kBlock) void k_expand(RunView r, DevGraphView g, in
   __shared__ uint32_t s_mask[kExpandTile];
   __shared__ uint16_t s_own[kExpandTile];
   __shared__ uint32_t s_scan[kBlock / kWave + 1];
-  __shared__ int32_t s_e[2];
-  for (uint32_t tile = blockIdx.x; (uint64_t)tile * kExpandTile < W; tile += gridDim.x) {
+  const uint32_t ntiles = (W + kExpandTile - 1) / kExpandTile;
+  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const uint32_t w0 = tile * kExpandTile;
     const uint32_t w1 = min(W, w0 + (uint32_t)kExpandTile);
-    if (wave_id() < 2) {
-      const int j = wave_search(r.q_off, nq, wave_id() == 0 ? w0 : w1 - 1);
-      if (lane_id() == 0) s_e[wave_id()] = j;
+    // first entry: the one holding arc w0; last: the one holding arc w1 - 1,
+    // which is the next tile's first entry unless that entry starts there
+    const int e0 = (int)(r.tile_first[tile] & ~kTileAtEntry);
+    int e1 = nq - 1;
+    if (tile + 1 < ntiles) {
+      const uint32_t f1 = r.tile_first[tile + 1];
+      e1 = (int)(f1 & ~kTileAtEntry) - ((f1 & kTileAtEntry) ? 1 : 0);
     }
     for (int i = threadIdx.x; i < kExpandTile; i += kBlock) s_own[i] = 0;
     __syncthreads();
-    const int e0 = s_e[0], cnt = s_e[1] - s_e[0] + 1;
+    const int cnt = e1 - e0 + 1;
     for (int j = threadIdx.x; j < cnt; j += kBlock) {
       const uint32_t off = r.q_off[e0 + j];
       s_base[j] = r.q_rs[e0 + j] - off + w0;   // arc of tile item i is s_base[j] + i

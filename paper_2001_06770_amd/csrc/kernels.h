@@ -63,6 +63,8 @@ struct RunView {
   uint32_t* q_rs;        // first examined arc (position in the level-sorted row)
   uint32_t* q_lo;        // from here on the arcs have level == l: old keywords join
   uint32_t* q_mask;      // keywords reached at level l | keywords reached before << 16
+  uint32_t* tile_first;  // [A / kExpandTile + 2] queue entry holding each expansion tile's
+                         // first arc (| kTileAtEntry when the tile starts with the entry)
   uint64_t* cand;        // central run: identified central nodes (S<<48 | sum<<32 | node)
   int32_t max_level;
   int32_t w, k, gamma_num, gamma_den;
