@@ -175,7 +175,11 @@ int lane_create(Ctx* c, int id, Lane** out) {
       hipHostMalloc((void**)&L->h_nodes, kSpecNodes * 4, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&L->h_arcs, kSpecArcs * 12, hipHostMallocDefault) != hipSuccess ||
       hipEventCreate(&L->q_start) != hipSuccess || hipEventCreate(&L->q_end) != hipSuccess ||
-      hipHostGetDevicePointer((void**)&L->d_run, L->h_run, 0) != hipSuccess) {
+      hipHostGetDevicePointer((void**)&L->d_run, L->h_run, 0) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&L->d_status, L->h_status, 0) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&L->d_hdr, L->h_hdr, 0) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&L->d_nodes, L->h_nodes, 0) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&L->d_arcs, L->h_arcs, 0) != hipSuccess) {
     lane_destroy(c, L.get());
     return fail(RAKS_EDEVICE, "lane pinned memory / event allocation failed");
   }
@@ -1031,12 +1035,22 @@ int collect(Lane* L, const QueryPlan& p, raks_results** out, int* ovf) {
   Ctx* c = L->ctx;
   hipStream_t s = L->stream;
   Status* st = P<Status>(L->status);
-  HIP_OK(hipMemcpyAsync(L->h_status, st, sizeof(Status), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipMemcpyAsync(L->h_hdr, L->hdr.p, sizeof(ResultHdr) * p.k, hipMemcpyDeviceToHost, s));
   const size_t spec_n = std::min(L->out_nodes.bytes / 4, (size_t)kSpecNodes);
   const size_t spec_a = std::min(L->out_arcs.bytes / 12, (size_t)kSpecArcs);
-  HIP_OK(hipMemcpyAsync(L->h_nodes, L->out_nodes.p, 4 * spec_n, hipMemcpyDeviceToHost, s));
-  HIP_OK(hipMemcpyAsync(L->h_arcs, L->out_arcs.p, 12 * spec_a, hipMemcpyDeviceToHost, s));
+  CollectView cv;
+  cv.st = st;
+  cv.hdr = P<ResultHdr>(L->hdr);
+  cv.n_hdr = (uint32_t)p.k;
+  cv.nodes = P<uint32_t>(L->out_nodes);
+  cv.arcs = P<uint32_t>(L->out_arcs);
+  cv.cap_nodes = (uint32_t)spec_n;
+  cv.cap_arcs = (uint32_t)spec_a;
+  cv.h_st = L->d_status;
+  cv.h_hdr = L->d_hdr;
+  cv.h_nodes = L->d_nodes;
+  cv.h_arcs = L->d_arcs;
+  launch_collect(cv, s);
+  HIP_OK(hipGetLastError());
   HIP_OK(hipStreamSynchronize(s));
   const Status hs = *L->h_status;
   *ovf = hs.overflow;

@@ -254,6 +254,22 @@ void launch_rank(const RankView& v, hipStream_t s);
 void launch_rerank(ResultHdr* hdr, Status* gst, int32_t k, hipStream_t s);
 void launch_recover(const RecoverView& v, hipStream_t s);   // all layers of one phase
 void launch_finalize(const FinalizeView& v, hipStream_t s);
+
+// Results to pinned host memory (device addresses of the host buffers).
+struct CollectView {
+  const Status* st;
+  const ResultHdr* hdr;
+  uint32_t n_hdr;                    // headers to copy
+  const uint32_t* nodes;             // output arena, 1 word per node
+  const uint32_t* arcs;              // output arena, 3 words per arc
+  uint32_t cap_nodes, cap_arcs;      // what the host buffers hold (and the arena has)
+  Status* h_st;
+  ResultHdr* h_hdr;
+  uint32_t* h_nodes;
+  uint32_t* h_arcs;
+};
+constexpr int kCollectGroups = 64;
+void launch_collect(const CollectView& v, hipStream_t s);
 // Bitmap path for result t (flagged in v.big): bm holds max(n, A) bits, chunk
 // one count per kBigChunk words, slot one 64-bit list start.
 void launch_big_finalize(const FinalizeView& v, int t, uint32_t* bm, uint32_t* chunk, uint64_t* slot,

@@ -589,6 +589,30 @@ void launch_finalize(const FinalizeView& v, hipStream_t s) {
   if (v.n_res > 0) k_finalize<<<v.n_res, kBlock, 0, s>>>(v);
 }
 
+// The query's status, its result headers and as much of its output lists as
+// the pinned staging buffers hold go straight into host memory: only the
+// bytes that the query produced cross the bus, and no copy is launched.  The
+// host copies a larger output itself.
+__global__ __launch_bounds__(kBlock) void k_collect(CollectView v) {
+  const uint32_t tn = min(v.st->out_nodes, v.cap_nodes);
+  const uint32_t ta = min(v.st->out_arcs, v.cap_arcs) * 3u;   // 3 words per arc
+  const uint32_t gt = blockIdx.x * kBlock + threadIdx.x, stride = gridDim.x * kBlock;
+  for (uint32_t i = gt; i < tn; i += stride) v.h_nodes[i] = v.nodes[i];
+  for (uint32_t i = gt; i < ta; i += stride) v.h_arcs[i] = v.arcs[i];
+  if (blockIdx.x == 0) {
+    const uint32_t hw = v.n_hdr * (uint32_t)(sizeof(ResultHdr) / 4);
+    for (uint32_t i = threadIdx.x; i < hw; i += kBlock)
+      reinterpret_cast<uint32_t*>(v.h_hdr)[i] = reinterpret_cast<const uint32_t*>(v.hdr)[i];
+    for (uint32_t i = threadIdx.x; i < sizeof(Status) / 4; i += kBlock)
+      reinterpret_cast<uint32_t*>(v.h_st)[i] = reinterpret_cast<const uint32_t*>(v.st)[i];
+  }
+  __threadfence_system();
+}
+
+void launch_collect(const CollectView& v, hipStream_t s) {
+  k_collect<<<kCollectGroups, kBlock, 0, s>>>(v);
+}
+
 void launch_big_finalize(const FinalizeView& v, int t, uint32_t* bm, uint32_t* chunk, uint64_t* slot,
                          hipStream_t s) {
   const uint32_t nw = (uint32_t)(((uint64_t)v.g.n + 31) / 32);

@@ -99,6 +99,12 @@ struct Lane {
   ResultHdr* h_hdr = nullptr;   // pinned [kMaxW]
   int32_t* h_nodes = nullptr;   // pinned [kSpecNodes]
   int32_t* h_arcs = nullptr;    // pinned [3 * kSpecArcs]
+  // device addresses of the pinned buffers above (results are written there
+  // by a kernel)
+  Status* d_status = nullptr;
+  ResultHdr* d_hdr = nullptr;
+  uint32_t* d_nodes = nullptr;
+  uint32_t* d_arcs = nullptr;
   hipEvent_t q_start = nullptr, q_end = nullptr;
 
   // event timing (enabled by the context)
