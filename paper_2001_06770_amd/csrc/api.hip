@@ -1060,28 +1060,17 @@ int collect(Lane* L, const QueryPlan& p, raks_results** out, int* ovf) {
   }
   const int nres = hs.nres, nsel = hs.nsel;
   const uint32_t tn = hs.out_nodes, ta = hs.out_arcs;
-  std::vector<int32_t> big_nodes, big_arcs;
-  const int32_t* nodes = L->h_nodes;
-  const int32_t* arcs = L->h_arcs;
-  if (tn > spec_n) {
-    big_nodes.resize(tn);
-    HIP_OK(hipMemcpyAsync(big_nodes.data(), L->out_nodes.p, 4 * (size_t)tn, hipMemcpyDeviceToHost, s));
-    nodes = big_nodes.data();
-  }
-  if (ta > spec_a) {
-    big_arcs.resize((size_t)ta * 3);
-    HIP_OK(hipMemcpyAsync(big_arcs.data(), L->out_arcs.p, 12 * (size_t)ta, hipMemcpyDeviceToHost, s));
-    arcs = big_arcs.data();
-  }
-  if (tn > spec_n || ta > spec_a) HIP_OK(hipStreamSynchronize(s));
-  float ms = 0;
-  (void)hipEventElapsedTime(&ms, L->q_start, L->q_end);
-  if (c->timing.load()) harvest_timing(L);
-
+  // lists that did not fit the pinned buffers are copied from the device
+  // straight into each result's own arrays
+  const bool dev_nodes = tn > spec_n, dev_arcs = ta > spec_a;
   raks_results* res = (raks_results*)calloc(1, sizeof(raks_results));
   if (!res) return fail(RAKS_ENOMEM, "host allocation failed");
   res->n = nres;
   res->r = (raks_result*)calloc(std::max(nres, 1), sizeof(raks_result));
+  if (!res->r) {
+    raks_results_free(res);
+    return fail(RAKS_ENOMEM, "host allocation failed");
+  }
   for (int t = 0; t < nres; ++t) {
     raks_result& o = res->r[t];
     const ResultHdr& h = L->h_hdr[t];
@@ -1091,14 +1080,46 @@ int collect(Lane* L, const QueryPlan& p, raks_results** out, int* ovf) {
     o.key = h.key;
     o.weight_sum = h.wsum;
     o.n_nodes = (int32_t)h.n_nodes;
-    int32_t* nd = (int32_t*)malloc(sizeof(int32_t) * std::max<uint32_t>(h.n_nodes, 1));
-    memcpy(nd, nodes + h.node_off, sizeof(int32_t) * h.n_nodes);
-    o.nodes = nd;
     o.n_arcs = (int32_t)h.n_arcs;
+    int32_t* nd = (int32_t*)malloc(sizeof(int32_t) * std::max<uint32_t>(h.n_nodes, 1));
     raks_arc* ar = (raks_arc*)malloc(sizeof(raks_arc) * std::max<uint32_t>(h.n_arcs, 1));
-    memcpy(ar, arcs + 3 * (size_t)h.arc_off, sizeof(raks_arc) * h.n_arcs);
+    o.nodes = nd;
     o.arcs = ar;
+    if (!nd || !ar) {
+      raks_results_free(res);
+      return fail(RAKS_ENOMEM, "host allocation failed");
+    }
+    hipError_t e = hipSuccess;
+    if (h.n_nodes) {
+      if (dev_nodes)
+        e = hipMemcpyAsync(nd, P<int32_t>(L->out_nodes) + h.node_off, sizeof(int32_t) * h.n_nodes,
+                           hipMemcpyDeviceToHost, s);
+      else
+        memcpy(nd, L->h_nodes + h.node_off, sizeof(int32_t) * h.n_nodes);
+    }
+    if (h.n_arcs && e == hipSuccess) {
+      if (dev_arcs)
+        e = hipMemcpyAsync(ar, P<int32_t>(L->out_arcs) + 3 * (size_t)h.arc_off,
+                           sizeof(raks_arc) * h.n_arcs, hipMemcpyDeviceToHost, s);
+      else
+        memcpy(ar, L->h_arcs + 3 * (size_t)h.arc_off, sizeof(raks_arc) * h.n_arcs);
+    }
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(s);
+      raks_results_free(res);
+      return fail(RAKS_EDEVICE, std::string("result copy: ") + hipGetErrorString(e));
+    }
   }
+  if (dev_nodes || dev_arcs) {
+    const hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      raks_results_free(res);
+      return fail(RAKS_EDEVICE, std::string("result copy: ") + hipGetErrorString(e));
+    }
+  }
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, L->q_start, L->q_end);
+  if (c->timing.load()) harvest_timing(L);
   for (int k = 0; k < 2; ++k) {
     const RunStatus& rs = hs.run[k];
     const bool ran = (k == 0) || (p.M > 0 && nsel > 0);
