@@ -13,7 +13,7 @@ constexpr int kBlock = 256;        // threads per workgroup for most kernels
 constexpr int kScanPer = 2;        // frontier flags per scan thread
 constexpr int kScanNodes = 512;    // frontier flags per scan chunk (kBlock * kScanPer)
 constexpr int kScanGroups = 2048;  // at most this many frontier-scan workgroups
-constexpr int kExpandTile = 2048;  // arcs per expansion tile
+constexpr int kExpandTile = 1024;  // arcs per expansion tile
 constexpr int kMaxKw = 16;         // keywords per run
 constexpr int kMaxW = 256;         // beam width limit
 constexpr uint8_t kInf = 0xFF;     // "not reached" in the node-keyword matrix

@@ -17,7 +17,7 @@
 //                   expansion queue (node order, arc prefix) and the central
 //                   nodes to the candidate list;
 //   k_expand        Algorithm 1 for every (frontier, arc) pair, balanced by
-//                   arcs: each workgroup takes tiles of 2048 consecutive arcs
+//                   arcs: each workgroup takes tiles of 1024 consecutive arcs
 //                   of the concatenated frontier rows, so a hub's arcs spread
 //                   over many workgroups; one H-row gather serves all keywords
 //                   of the frontier at once.
@@ -573,7 +573,7 @@ __global__ __launch_bounds__(kBlock) void k_front_move(RunView r, int level) {
 // level <= l).  For arc f -> n every keyword i that f expands for and that has
 // not reached n gets h_ni = level + 1, which makes n a frontier of the next
 // level (lines 13-17).  One gather of the neighbour's reached mask serves
-// every keyword at once.  Tile of 2048 consecutive arcs of the concatenated
+// every keyword at once.  Tile of 1024 consecutive arcs of the concatenated
 // slices: the tile map gives its first and last queue entry, the entries go
 // to LDS, each entry marks the tile item where it starts and a block max-scan
 // turns the marks into the owner entry of every item; item i of the tile is
