@@ -668,8 +668,20 @@ __global__ __launch_bounds__(kCtl) void k_select(SelectView v) {
     for (uint32_t i = threadIdx.x; i < prev; i += kCtl) s_sel[i] = v.cand[i];
     for (int i = threadIdx.x; i < 4096; i += kCtl) s_hist[i] = 0;
     __syncthreads();
-    for (uint32_t i = prev + threadIdx.x; i < total; i += kCtl)
-      atomicAdd(&s_hist[(v.cand[i] >> 32) & 0xFFF], 1u);
+    // the level's sums crowd into a few bins: one LDS atomic per distinct bin
+    // of a wavefront instead of one per candidate
+    for (uint32_t base = prev; base < total; base += kCtl) {
+      const uint32_t i = base + threadIdx.x;
+      const int bin = i < total ? (int)((v.cand[i] >> 32) & 0xFFF) : -1;
+      uint64_t pending = __ballot(bin >= 0);
+      while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int lb = __shfl(bin, leader, kWave);
+        const uint64_t same = __ballot(bin == lb);
+        if (lane_id() == leader) atomicAdd(&s_hist[lb], (uint32_t)__popcll(same));
+        pending &= ~same;
+      }
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
       uint32_t cum = 0, thr = 0;
@@ -684,18 +696,30 @@ __global__ __launch_bounds__(kCtl) void k_select(SelectView v) {
     }
     __syncthreads();
     const uint32_t thr = s_thr, take = s_take;
-    uint32_t taken = 0;
-    for (uint32_t b = prev; b < total; b += kCtl) {
-      const uint32_t i = b + threadIdx.x;
-      const uint64_t key = i < total ? v.cand[i] : 0;
+    // every thread walks one contiguous segment of the level's list; one scan
+    // of the per-segment counts of sums equal to the threshold gives each
+    // segment's rank among them, so the first `take` in list order are kept
+    const uint32_t seg = (last + kCtl - 1) / kCtl;
+    const uint32_t a = prev + min(last, threadIdx.x * seg);
+    const uint32_t b = prev + min(last, (threadIdx.x + 1) * seg);
+    uint32_t eq = 0;
+#pragma unroll 8
+    for (uint32_t i = a; i < b; ++i) {
+      const uint64_t key = v.cand[i];
       const uint32_t s = (uint32_t)(key >> 32) & 0xFFFF;
-      const bool lt = i < total && s < thr;
-      const uint32_t eq = (i < total && s == thr) ? 1u : 0u;
-      if (lt) s_sel[atomicAdd(&s_cnt, 1u)] = key;
-      uint32_t tot;
-      const uint32_t ex = block_exclusive_scan<uint32_t, kCtl>(eq, s_scan, &tot);
-      if (eq && taken + ex < take) s_sel[atomicAdd(&s_cnt, 1u)] = key;
-      taken += tot;
+      if (s < thr) s_sel[atomicAdd(&s_cnt, 1u)] = key;
+      eq += s == thr;
+    }
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<uint32_t, kCtl>(eq, s_scan, &tot);
+    uint32_t rank = ex;
+#pragma unroll 4
+    for (uint32_t i = a; i < b && rank < take; ++i) {
+      const uint64_t key = v.cand[i];
+      if (((uint32_t)(key >> 32) & 0xFFFF) == thr) {
+        s_sel[atomicAdd(&s_cnt, 1u)] = key;
+        ++rank;
+      }
     }
   }
   __syncthreads();

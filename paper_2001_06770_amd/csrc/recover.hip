@@ -223,11 +223,13 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeView v) {
     return;
   }
   bool skip = (v.gst->overflow & v.skip_bits) != 0;
+  uint64_t nn = 0, na = 0;   // input sizes of the node and arc lists
   if (!skip) {
     // inputs beyond big_list go to the bitmap path (k_big_*), run by the host
     // once this launch has finished
     const int r0 = v.marginal ? v.ranked[t] : t;
-    uint64_t nn = v.marginal ? v.cg_cnt[r0 * 2] : 0u, na = v.marginal ? v.cg_cnt[r0 * 2 + 1] : 0u;
+    nn = v.marginal ? v.cg_cnt[r0 * 2] : 0u;
+    na = v.marginal ? v.cg_cnt[r0 * 2 + 1] : 0u;
     for (int j = 0; j < v.T; ++j) {
       const InstCap ic = v.caps[t * v.T + j];
       nn += min(v.cnt[(t * v.T + j) * 2], ic.ncap);
@@ -264,7 +266,13 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeView v) {
   const int r = v.marginal ? v.ranked[t] : t;
   const DevGraphView& g = v.g;
 
-  for (int pass = 0; pass < 2; ++pass) {   // 0: nodes, 1: arcs
+  // When both lists fit LDS, the result's two workgroups (y = 0, 1) take the
+  // node and the arc pass at once; otherwise workgroup 0 takes both, since
+  // they share the result's global sort scratch.
+  const bool split = nn <= kLdsSort && na <= kLdsSort;
+  if (!split && blockIdx.y == 1) return;
+  const int p0 = split ? (int)blockIdx.y : 0, p1 = split ? p0 + 1 : 2;
+  for (int pass = p0; pass < p1; ++pass) {   // 0: nodes, 1: arcs
     // total input size first: small lists are sorted in LDS
     uint32_t n = v.marginal ? v.cg_cnt[r * 2 + pass] : 0u;
     for (int j = 0; j < v.T; ++j)
@@ -586,7 +594,7 @@ void launch_recover(const RecoverView& v, hipStream_t s) {
 }
 
 void launch_finalize(const FinalizeView& v, hipStream_t s) {
-  if (v.n_res > 0) k_finalize<<<v.n_res, kBlock, 0, s>>>(v);
+  if (v.n_res > 0) k_finalize<<<dim3(v.n_res, 2), kBlock, 0, s>>>(v);
 }
 
 // The query's status, its result headers and as much of its output lists as
