@@ -130,7 +130,7 @@ DevGraphView graph_view(const Lane* L) { return graph_view(L->ctx, *L->view); }
 void lane_destroy(Ctx* c, Lane* L) {
   if (!L) return;
   if (L->stream) (void)hipStreamSynchronize(L->stream);
-  DevBuf* bufs[] = {&L->Hc, &L->Hm, &L->R, &L->tot, &L->off, &L->q_off, &L->q_rs,
+  DevBuf* bufs[] = {&L->Hc, &L->Hm, &L->R, &L->tot, &L->q_off, &L->q_rs,
                     &L->q_lo, &L->q_mask, &L->tile_first, &L->cand, &L->s_item, &L->s_cand, &L->sel_node, &L->sel_sc, &L->sel_sumh,
                     &L->has_rpg, &L->sm, &L->key, &L->dmin, &L->ranked, &L->vc_cnt, &L->vc_tmp,
                     &L->vc_off, &L->vc_nodes, &L->hpool, &L->nl, &L->al, &L->items, &L->sort_a,
@@ -443,7 +443,6 @@ int ensure_node_buffers(Lane* L) {
   const size_t np = (size_t)L->n_pad;
   RAKS_TRY(dev_alloc(c, L->R, np * 2));
   RAKS_TRY(dev_alloc(c, L->tot, (size_t)L->nblocks * sizeof(ScanTot)));
-  RAKS_TRY(dev_alloc(c, L->off, (size_t)L->nblocks * sizeof(ScanOff)));
   RAKS_TRY(dev_alloc(c, L->q_off, (np + 1) * 4));
   RAKS_TRY(dev_alloc(c, L->q_rs, np * 4));
   RAKS_TRY(dev_alloc(c, L->q_lo, np * 4));
@@ -490,7 +489,6 @@ RunView run_view(Lane* L, int kind, int T, DevBuf& H, const QueryPlan& p) {
   r.n_pad = L->n_pad;
   r.st = &P<Status>(L->status)->run[kind];
   r.tot = P<ScanTot>(L->tot);
-  r.off = P<ScanOff>(L->off);
   r.nblocks = L->nblocks;
   r.cpw = L->cpw;
   r.s_item = P<uint4>(L->s_item);
@@ -577,11 +575,7 @@ int run_levels(Lane* L, RunView& r, int TP, const std::vector<int32_t>& kws, int
     {
       Timed t(L, 2, level, r.kind);
       want[slot] = ++L->ctl_seq;
-      launch_front_control(r, TP, level, &L->d_run[slot], want[slot], s);
-    }
-    {
-      Timed t(L, 1, level, r.kind);
-      launch_front_move(r, level, s);
+      launch_front_enqueue(r, TP, level, &L->d_run[slot], want[slot], s);
     }
     if (c->timing.load() & 1u) {
       // expansion timing: the launch itself stamps the two events

@@ -38,6 +38,7 @@ struct RunStatus {
   uint32_t ncand_level;  // central nodes identified at the current level
   uint32_t ncand_total;  // central nodes identified so far
   uint32_t nrpg;         // CGs with an RPG so far (marginal run)
+  uint32_t cand_base[2]; // [l & 1]: central nodes identified before level l
   uint64_t frontier_sum, e_arc, e_alg, gate_pass, h_writes;
   uint64_t seq;          // host mirror only: number of the control launch that wrote it
 };
@@ -66,9 +67,6 @@ struct ScanTot {
   uint64_t gate;         // arcs with level <= l of expanding frontiers
 };
 
-struct ScanOff {
-  uint32_t q, work, cand, pad;
-};
 
 // Output header of one result.
 struct ResultHdr {

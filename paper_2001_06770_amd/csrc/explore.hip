@@ -1,6 +1,6 @@
 // explore.hip -- exploration phase (Section 4.2) on gfx950.
 //
-// One level of a run is four launches:
+// One level of a run is three launches:
 //   k_front_count   frontier scan: every workgroup takes a run of 512-node
 //                   chunks (2 nodes per thread), reads their H rows and row
 //                   levels in node order, decides frontier membership from
@@ -9,13 +9,14 @@
 //                   slice of the row), stages its queue entry and central-node
 //                   key in node order and refreshes its reached mask; then
 //                   writes its totals;
-//   k_front_control one workgroup: scans the totals, applies the run's
+//   k_front_enqueue workgroup 0 sums the totals, applies the run's
 //                   identification and termination rules (Theorem identifyCG,
 //                   >= w CGs; the RPG check over each CG's V_C rows and
-//                   Theorem 4), and decides whether this level expands;
-//   k_front_move    Frontier Enqueue: copies the staged entries to the
-//                   expansion queue (node order, arc prefix) and the central
-//                   nodes to the candidate list;
+//                   Theorem 4) and decides whether this level expands; the
+//                   other workgroups, one per scan workgroup, do Frontier
+//                   Enqueue: they copy the staged entries to the expansion
+//                   queue (node order, arc prefix) and the central nodes to
+//                   the candidate list;
 //   k_expand        Algorithm 1 for every (frontier, arc) pair, balanced by
 //                   arcs: each workgroup takes tiles of 1024 consecutive arcs
 //                   of the concatenated frontier rows, so a hub's arcs spread
@@ -346,6 +347,7 @@ __global__ __launch_bounds__(kBlock) void k_front_count(RunView r, DevGraphView 
 }
 
 constexpr int kCtl = 1024;
+constexpr uint32_t kTileAtEntry = 0x80000000u;   // tile_first: the tile starts with the entry
 
 // Marginal run identification (Section 4.2.3): for every selected CG without
 // an RPG, D_j = min over its central-keyword nodes of h_j; all finite -> RPG
@@ -450,8 +452,7 @@ __device__ inline void publish(RunStatus* mirror, const RunStatus& st, uint64_t 
 }
 
 template <int TP>
-__global__ __launch_bounds__(kCtl) void k_front_control(RunView r, int level, RunStatus* mirror,
-                                                        uint64_t seq) {
+__device__ void control_level(const RunView& r, int level, RunStatus* mirror, uint64_t seq) {
   RunStatus* st = r.st;
   const int nb = r.nblocks;
   const int per = (nb + kCtl - 1) / kCtl;   // 1 or 2
@@ -479,19 +480,9 @@ __global__ __launch_bounds__(kCtl) void k_front_control(RunView r, int level, Ru
                       t[0].gate + t[1].gate};
   uint64_t tots[8];
   block_exclusive_scan_multi<8, kCtl>(vals, tots, s_multi);
-  uint32_t xq = (uint32_t)vals[0], xw = (uint32_t)vals[1], xc = (uint32_t)vals[2];
   const uint32_t tnq = (uint32_t)tots[0], twk = (uint32_t)tots[1], tnc = (uint32_t)tots[2];
   const uint32_t tnf = (uint32_t)tots[3], thw = (uint32_t)tots[4];
   const uint64_t tdg = tots[5], tdk = tots[6], tgt = tots[7];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    if (b0 + i < b1) {
-      ScanOff o;
-      o.q = xq; o.work = xw; o.cand = xc; o.pad = 0;
-      r.off[b0 + i] = o;
-      xq += t[i].nq; xw += t[i].work; xc += t[i].ncand;
-    }
-  }
   if (threadIdx.x == 0) {
     cur.levels = level + 1;
     cur.nfront = tnf;
@@ -508,6 +499,9 @@ __global__ __launch_bounds__(kCtl) void k_front_control(RunView r, int level, Ru
       cur.ncand_total += tnc;
       if (cur.ncand_total >= (uint32_t)r.w) s_end = END_STOP;
     }
+    // where the next level's central nodes start (the other slot is read by
+    // this launch's copying workgroups)
+    cur.cand_base[(level + 1) & 1] = cur.cand_base[level & 1] + tnc;
     s_nrpg = cur.nrpg;
   }
   __syncthreads();
@@ -534,40 +528,51 @@ __global__ __launch_bounds__(kCtl) void k_front_control(RunView r, int level, Ru
   }
 }
 
-constexpr uint32_t kTileAtEntry = 0x80000000u;   // tile_first: the tile starts with the entry
-
-// Frontier Enqueue, global part: every workgroup of the scan copies its
-// staged queue entries to the workgroup's place in the expansion queue (the
-// control kernel's exclusive prefix), turning the local arc offsets into
-// global ones, and its central nodes to the level's place in the candidate
-// list.  For every expansion tile (kExpandTile consecutive arcs of the
-// concatenated slices) it also records the queue entry that holds the tile's
-// first arc, so a tile finds its entries with one load.  The queue is written
-// only if the level expands.
-__global__ __launch_bounds__(kBlock) void k_front_move(RunView r, int level) {
-  const RunStatus* st = r.st;
-  if (level > st->end_level) return;
-  const ScanTot t = r.tot[blockIdx.x];
-  if (t.nq == 0 && t.ncand == 0) return;
-  const ScanOff o = r.off[blockIdx.x];
-  const int64_t wg0 = (int64_t)blockIdx.x * r.cpw * kScanNodes;
-  if (st->expand_on) {
-    for (uint32_t j = threadIdx.x; j < t.nq; j += kBlock) {
-      const uint4 e = r.s_item[wg0 + j];
-      const uint32_t start = o.work + e.x;
-      const uint32_t end = o.work + (j + 1 < t.nq ? r.s_item[wg0 + j + 1].x : t.work);
-      r.q_off[o.q + j] = start;
-      r.q_rs[o.q + j] = e.y;
-      r.q_lo[o.q + j] = e.z;
-      r.q_mask[o.q + j] = e.w;
-      // expansion tiles whose first arc falls in this entry start at it
-      for (uint32_t tl = (start + kExpandTile - 1) / kExpandTile; tl * kExpandTile < end; ++tl)
-        r.tile_first[tl] = (o.q + j) | (tl * kExpandTile == start ? kTileAtEntry : 0u);
-    }
+// Frontier Enqueue in the same launch: workgroup 0 runs the level's control
+// step; workgroup 1 + b copies scan workgroup b's staged queue entries to
+// its place in the expansion queue (its offsets are the sums of the totals
+// of the scan workgroups before it, read by all its threads at once), its
+// central nodes to the level's place in the candidate list, and, for every
+// expansion tile whose first arc falls in one of its entries, that entry to
+// the tile map.  The copies do not wait for the control step: if the level
+// does not expand, nothing reads the queue.
+template <int TP>
+__global__ __launch_bounds__(kCtl) void k_front_enqueue(RunView r, int level, RunStatus* mirror,
+                                                        uint64_t seq) {
+  if (blockIdx.x == 0) {
+    control_level<TP>(r, level, mirror, seq);
+    return;
   }
-  const uint32_t c0 = (st->ncand_total - st->ncand_level) + o.cand;
-  for (uint32_t j = threadIdx.x; j < t.ncand; j += kBlock) r.cand[c0 + j] = r.s_cand[wg0 + j];
+  const RunStatus* st = r.st;
+  const int b = (int)blockIdx.x - 1;
+  if (level > st->end_level) return;   // (set to this level at most, by workgroup 0)
+  const ScanTot t = r.tot[b];
+  if (t.nq == 0 && t.ncand == 0) return;
+  __shared__ uint32_t s_m32[(kCtl / kWave + 1) * 3];
+  uint32_t v[3] = {0, 0, 0}, tot[3];
+  for (int i = threadIdx.x; i < b; i += kCtl) {
+    const ScanTot x = r.tot[i];
+    v[0] += x.nq; v[1] += x.work; v[2] += x.ncand;
+  }
+  block_exclusive_scan_multi<3, kCtl, uint32_t>(v, tot, s_m32);
+  const uint32_t oq = tot[0], ow = tot[1];
+  const uint32_t oc = st->cand_base[level & 1] + tot[2];
+  const int64_t wg0 = (int64_t)b * r.cpw * kScanNodes;
+  for (uint32_t j = threadIdx.x; j < t.nq; j += kCtl) {
+    const uint4 e = r.s_item[wg0 + j];
+    const uint32_t start = ow + e.x;
+    const uint32_t end = ow + (j + 1 < t.nq ? r.s_item[wg0 + j + 1].x : t.work);
+    r.q_off[oq + j] = start;
+    r.q_rs[oq + j] = e.y;
+    r.q_lo[oq + j] = e.z;
+    r.q_mask[oq + j] = e.w;
+    // expansion tiles whose first arc falls in this entry start at it
+    for (uint32_t tl = (start + kExpandTile - 1) / kExpandTile; tl * kExpandTile < end; ++tl)
+      r.tile_first[tl] = (oq + j) | (tl * kExpandTile == start ? kTileAtEntry : 0u);
+  }
+  for (uint32_t j = threadIdx.x; j < t.ncand; j += kCtl) r.cand[oc + j] = r.s_cand[wg0 + j];
 }
+
 
 // Algorithm 1 at level `level` over the queued row slices (all of them have
 // level <= l).  For arc f -> n every keyword i that f expands for and that has
@@ -842,14 +847,11 @@ void launch_front_count(const RunView& r, int TP, const DevGraphView& g, int lev
   RAKS_TP_DISPATCH(TP, k_front_count<kTP><<<r.nblocks, kBlock, 0, s>>>(r, g, level));
 }
 
-void launch_front_control(const RunView& r, int TP, int level, RunStatus* mirror, uint64_t seq,
+void launch_front_enqueue(const RunView& r, int TP, int level, RunStatus* mirror, uint64_t seq,
                           hipStream_t s) {
-  RAKS_TP_DISPATCH(TP, k_front_control<kTP><<<1, kCtl, 0, s>>>(r, level, mirror, seq));
+  RAKS_TP_DISPATCH(TP, k_front_enqueue<kTP><<<r.nblocks + 1, kCtl, 0, s>>>(r, level, mirror, seq));
 }
 
-void launch_front_move(const RunView& r, int level, hipStream_t s) {
-  k_front_move<<<r.nblocks, kBlock, 0, s>>>(r, level);
-}
 
 void launch_expand(const RunView& r, int TP, const DevGraphView& g, int level, int grid,
                    hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {

@@ -54,7 +54,6 @@ struct RunView {
   int32_t n_pad;         // n rounded up to kScanNodes
   RunStatus* st;
   ScanTot* tot;          // [nblocks]
-  ScanOff* off;          // [nblocks]
   int32_t nblocks;       // frontier-scan workgroups
   int32_t cpw;           // kScanNodes-chunks per scan workgroup
   uint4* s_item;         // [n_pad] staged queue entries (local arc prefix, rs, lo, mask)
@@ -240,11 +239,11 @@ void launch_act_node(const DevGraphView& g, const uint8_t* nw, const Status* st,
 void launch_run_init(const RunView& r, int TP, int32_t n, const int32_t* kw_nodes,
                      const SeedList& seeds, hipStream_t s);
 void launch_front_count(const RunView& r, int TP, const DevGraphView& g, int level, hipStream_t s);
-// mirror: device-visible pinned host memory that receives the level's status,
-// stamped with seq once the rest of it is visible to the host
-void launch_front_control(const RunView& r, int TP, int level, RunStatus* mirror, uint64_t seq,
+// The level's control step and Frontier Enqueue in one launch.  mirror:
+// device-visible pinned host memory that receives the level's status,
+// stamped with seq once the rest of it is visible to the host.
+void launch_front_enqueue(const RunView& r, int TP, int level, RunStatus* mirror, uint64_t seq,
                           hipStream_t s);
-void launch_front_move(const RunView& r, int level, hipStream_t s);
 // ev0 / ev1 (optional): events that receive the kernel's start and end times
 void launch_expand(const RunView& r, int TP, const DevGraphView& g, int level, int grid,
                    hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);

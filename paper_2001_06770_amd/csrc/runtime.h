@@ -83,7 +83,7 @@ struct Lane {
   bool own_stream = false;
 
   int32_t n_pad = 0, nblocks = 0, cpw = 1;
-  DevBuf Hc, Hm, R, tot, off, q_off, q_rs, q_lo, q_mask, tile_first, cand, s_item, s_cand;
+  DevBuf Hc, Hm, R, tot, q_off, q_rs, q_lo, q_mask, tile_first, cand, s_item, s_cand;
   DevBuf sel_node, sel_sc, sel_sumh, has_rpg, sm, key, dmin, ranked;
   DevBuf vc_cnt, vc_tmp, vc_off, vc_nodes;
   // recovery storage, shared by both phases (sized for the larger one)
