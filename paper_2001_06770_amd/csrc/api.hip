@@ -435,7 +435,7 @@ int validate_query(Ctx* c, const raks_query_desc* q, QueryPlan& p) {
 int ensure_node_buffers(Lane* L) {
   Ctx* c = L->ctx;
   L->n_pad = (int32_t)(((int64_t)c->n + kScanNodes - 1) / kScanNodes * kScanNodes);
-  // at most kScanGroups scan workgroups, so the control kernel's share of
+  // at most kScanGroups scan workgroups, so the control step's share of
   // the totals stays the same on any graph
   const int32_t chunks = L->n_pad / kScanNodes;
   L->cpw = (chunks + kScanGroups - 1) / kScanGroups;
@@ -561,7 +561,7 @@ int run_levels(Lane* L, RunView& r, int TP, const std::vector<int32_t>& kws, int
     launch_run_init(r, TP, c->n, P<int32_t>(c->kw_nodes), seeds, s);
   }
   const int grid = c->num_cu * 8;
-  // The control kernel writes the level's status into the pinned slot and
+  // The control step writes the level's status into the pinned slot and
   // then stamps it with the launch's number, so the host learns the decision
   // while the level's enqueue and expansion still run, without an event
   // (an event record after every control launch costs the stream several

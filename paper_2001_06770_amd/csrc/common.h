@@ -26,7 +26,7 @@ enum EndReason : int { END_NONE = 0, END_EXHAUSTED = 1, END_STOP = 2, END_LEVEL_
                        END_EMPTY_KEYWORD = 4 };
 
 // Device-resident state of one run (central or marginal), updated by the
-// single-workgroup control kernel at every level.
+// control step (workgroup 0 of the enqueue launch) at every level.
 struct RunStatus {
   int32_t end_level;     // level at which the run ended; INT32_MAX while running
   int32_t end_reason;
