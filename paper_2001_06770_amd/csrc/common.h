@@ -10,8 +10,8 @@ namespace raks {
 
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kBlock = 256;        // threads per workgroup for most kernels
-constexpr int kScanPer = 2;        // frontier flags per scan thread
-constexpr int kScanNodes = 512;    // frontier flags per scan chunk (kBlock * kScanPer)
+constexpr int kScanPer = 4;        // nodes per frontier-scan thread
+constexpr int kScanNodes = 1024;   // nodes per frontier-scan chunk (kBlock * kScanPer)
 constexpr int kScanGroups = 2048;  // at most this many frontier-scan workgroups
 constexpr int kExpandTile = 1024;  // arcs per expansion tile
 constexpr int kMaxKw = 16;         // keywords per run

@@ -1,8 +1,8 @@
 // explore.hip -- exploration phase (Section 4.2) on gfx950.
 //
 // One level of a run is three launches:
-//   k_front_count   frontier scan: every workgroup takes a run of 512-node
-//                   chunks (2 nodes per thread), reads their H rows and row
+//   k_front_count   frontier scan: every workgroup takes a run of 1024-node
+//                   chunks (4 nodes per thread), reads their H rows and row
 //                   levels in node order, decides frontier membership from
 //                   them, inspects every frontier node once (complete row ->
 //                   central node / PTC block, keywords with h <= level, level
@@ -44,44 +44,42 @@ template <> struct RowVec<16> { using T = uint4; };
 // Per-node mask of the keywords whose hitting level is finite: 4 bits per
 // node for up to 4 keywords (two nodes per byte, so the array that every
 // expansion gathers from is half as large), 8 or 16 bits otherwise.  W holds
-// the masks of the two consecutive nodes of one scan thread.
+// the masks of the kScanPer consecutive nodes of one scan thread.
 template <int TP> struct RMask { using T = uint8_t; };
 template <> struct RMask<16> { using T = uint16_t; };
 template <int TP> using RMaskT = typename RMask<TP>::T;
 
-template <int TP> struct RBits;
-template <> struct RBits<4> {
-  using W = uint8_t;
+template <int Bits> struct UintOf;
+template <> struct UintOf<8> { using T = uint8_t; };
+template <> struct UintOf<16> { using T = uint16_t; };
+template <> struct UintOf<32> { using T = uint32_t; };
+template <> struct UintOf<64> { using T = uint64_t; };
+
+template <int TP> struct RBits {
+  static constexpr int kBits = TP == 4 ? 4 : (TP == 8 ? 8 : 16);   // bits per node
+  using W = typename UintOf<kBits * kScanPer>::T;
   __device__ static uint32_t get(const void* R, int64_t v) {
-    return (reinterpret_cast<const uint8_t*>(R)[v >> 1] >> ((v & 1) * 4)) & 0xFu;
+    if constexpr (kBits == 4)
+      return (reinterpret_cast<const uint8_t*>(R)[v >> 1] >> ((v & 1) * 4)) & 0xFu;
+    else if constexpr (kBits == 8)
+      return reinterpret_cast<const uint8_t*>(R)[v];
+    else
+      return reinterpret_cast<const uint16_t*>(R)[v];
   }
-  __device__ static W* pair(void* R, int64_t v) { return reinterpret_cast<uint8_t*>(R) + (v >> 1); }
-  __device__ static uint32_t unpack(W w, int k) { return (w >> (4 * k)) & 0xFu; }
-  __device__ static W pack(uint32_t m0, uint32_t m1) { return (W)((m0 & 0xFu) | ((m1 & 0xFu) << 4)); }
+  // the word of node v's scan thread (v a multiple of kScanPer)
+  __device__ static W* group(void* R, int64_t v) {
+    return reinterpret_cast<W*>(reinterpret_cast<uint8_t*>(R) + v * kBits / 8);
+  }
+  __device__ static uint32_t unpack(W w, int k) {
+    return (uint32_t)(w >> (kBits * k)) & ((1u << kBits) - 1u);
+  }
+  __device__ static W pack(const uint32_t (&m)[kScanPer]) {
+    W w = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) w |= (W)(m[k] & ((1u << kBits) - 1u)) << (kBits * k);
+    return w;
+  }
 };
-template <> struct RBits<8> {
-  using W = uint16_t;
-  __device__ static uint32_t get(const void* R, int64_t v) {
-    return reinterpret_cast<const uint8_t*>(R)[v];
-  }
-  __device__ static W* pair(void* R, int64_t v) {
-    return reinterpret_cast<W*>(reinterpret_cast<uint8_t*>(R) + v);
-  }
-  __device__ static uint32_t unpack(W w, int k) { return (w >> (8 * k)) & 0xFFu; }
-  __device__ static W pack(uint32_t m0, uint32_t m1) { return (W)((m0 & 0xFFu) | ((m1 & 0xFFu) << 8)); }
-};
-template <> struct RBits<16> {
-  using W = uint32_t;
-  __device__ static uint32_t get(const void* R, int64_t v) {
-    return reinterpret_cast<const uint16_t*>(R)[v];
-  }
-  __device__ static W* pair(void* R, int64_t v) {
-    return reinterpret_cast<W*>(reinterpret_cast<uint16_t*>(R) + v);
-  }
-  __device__ static uint32_t unpack(W w, int k) { return (w >> (16 * k)) & 0xFFFFu; }
-  __device__ static W pack(uint32_t m0, uint32_t m1) { return (m0 & 0xFFFFu) | (m1 << 16); }
-};
-static_assert(kScanPer == 2, "RBits::W holds the masks of two nodes");
 
 template <int TP>
 __device__ inline void load_row(const uint8_t* H, int64_t v, uint8_t (&b)[TP]) {
@@ -251,13 +249,14 @@ __global__ __launch_bounds__(kBlock) void k_front_count(RunView r, DevGraphView 
   uint32_t nf = 0, hw = 0;
   uint64_t dg = 0, dk = 0, gt = 0;
   // the next chunk's rows and levels are loaded while this chunk is inspected
+  using AmW = typename UintOf<8 * kScanPer>::T;   // the row levels of a thread's nodes
   uint8_t nrows[kScanPer][TP];
   uint32_t nam2 = 0;
   {
     const int64_t b0 = wg0 + threadIdx.x * kScanPer;
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) load_row<TP>(r.H, b0 + k, nrows[k]);
-    nam2 = *reinterpret_cast<const uint16_t*>(g.row_amax + b0);
+    nam2 = *reinterpret_cast<const AmW*>(g.row_amax + b0);
   }
 #pragma unroll 1
   for (int64_t c0 = wg0; c0 < wg1; c0 += kScanNodes) {
@@ -268,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_front_count(RunView r, DevGraphView 
     if (c0 + kScanNodes < wg1) {
 #pragma unroll
       for (int k = 0; k < kScanPer; ++k) load_row<TP>(r.H, base + kScanNodes + k, nrows[k]);
-      nam2 = *reinterpret_cast<const uint16_t*>(g.row_amax + base + kScanNodes);
+      nam2 = *reinterpret_cast<const AmW*>(g.row_amax + base + kScanNodes);
     }
     uint32_t fw = 0;   // frontier bit per node
     // what the staging step needs of each node, kept across the block scan
@@ -304,7 +303,7 @@ __global__ __launch_bounds__(kBlock) void k_front_count(RunView r, DevGraphView 
     block_exclusive_scan_multi<3, kBlock, uint32_t>(v, t, s_m32);
     if (fw) {
       using RB = RBits<TP>;
-      typename RB::W* rp = RB::pair(r.R, base);
+      typename RB::W* rp = RB::group(r.R, base);
       const typename RB::W cur = *rp;
       uint32_t mk[kScanPer];
 #pragma unroll
@@ -323,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_front_count(RunView r, DevGraphView 
         }
         if (bits[k] & (1u << 17)) r.s_cand[wg0 + cd++] = key[k];
       }
-      *rp = RB::pack(mk[0], mk[1]);
+      *rp = RB::pack(mk);
     }
     cq += (uint32_t)t[0];
     cc += (uint32_t)t[1];
