@@ -250,7 +250,8 @@ void raks_results_free(raks_results* r);
 
 /* Per-kernel device time, accumulated while timing is enabled
  * (raks_set_timing).  kernel ids: 0 expansion (Algorithm 1), 1 frontier
- * scan/enqueue, 2 identification/control, 3 recovery, 4 other. */
+ * scan, 2 identification/control step with Frontier Enqueue, 3 recovery,
+ * 4 other. */
 typedef struct {
     int64_t launches;
     double ms;               /* summed event-measured duration */
