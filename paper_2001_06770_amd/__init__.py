@@ -155,11 +155,12 @@ def _results_to_dict(res: Results, lean: bool = False) -> dict:
            "queue_ms": float(st.queue_ms)}
     for i in range(res.n):
         r = res.r[i]
-        nodes = (np.ctypeslib.as_array(r.nodes, shape=(r.n_nodes,)).copy() if r.n_nodes
-                 else np.empty(0, np.int32))
-        arcs = (np.ctypeslib.as_array(ctypes.cast(r.arcs, ctypes.POINTER(ctypes.c_int32)),
-                                      shape=(r.n_arcs * 3,)).reshape(-1, 3).copy()
-                if r.n_arcs else np.empty((0, 3), np.int32))
+        nodes = np.empty(r.n_nodes, np.int32)
+        if r.n_nodes:
+            ctypes.memmove(nodes.ctypes.data, r.nodes, 4 * r.n_nodes)
+        arcs = np.empty((r.n_arcs, 3), np.int32)
+        if r.n_arcs:
+            ctypes.memmove(arcs.ctypes.data, r.arcs, 12 * r.n_arcs)
         if not lean:
             nodes = tuple(nodes.tolist())
             arcs = tuple(map(tuple, arcs.tolist()))
