@@ -528,7 +528,9 @@ __global__ void k_query_reset(Status* st) {
 // Waits until the control launch numbered `want` has published its status in
 // pinned slot `slot`.  The stream is queried now and then, so that a failed
 // stream ends the wait with an error, and so does a stream that has finished
-// without the status (which would mean the launch never ran).
+// without the status (which would mean the launch never ran).  A wait that
+// lasts (a level of a very large query) sleeps between looks instead of
+// spinning.
 int wait_status(Lane* L, int slot, uint64_t want) {
   const volatile uint64_t* seq = &L->h_run[slot].seq;
   for (uint32_t spin = 1;; ++spin) {
@@ -539,7 +541,8 @@ int wait_status(Lane* L, int slot, uint64_t want) {
         return fail(RAKS_EDEVICE, std::string("stream failed: ") + hipGetErrorString(e));
       if (e == hipSuccess && __atomic_load_n(seq, __ATOMIC_ACQUIRE) != want)
         return fail(RAKS_EDEVICE, "the level status was not published");
-      std::this_thread::yield();
+      if (spin >= (1u << 16)) std::this_thread::sleep_for(std::chrono::microseconds(20));
+      else std::this_thread::yield();
     } else {
       __builtin_ia32_pause();
     }
@@ -970,7 +973,7 @@ int stage_cg_recovery(Lane* L, const QueryPlan& p, const QueryRun& q) {
       const char* lay0 = static_cast<const char*>(L->ph[0].layout.p);
       launch_pack_vc(P<uint32_t>(L->vc_cnt), P<int32_t>(L->vc_tmp),
                      reinterpret_cast<const uint64_t*>(lay0 + L->ph[0].lay_cg_noff), &st->nsel,
-                     P<uint32_t>(L->vc_off), P<int32_t>(L->vc_nodes), s);
+                     P<uint32_t>(L->vc_off), P<int32_t>(L->vc_nodes), p.w, s);
     }
   }
   HIP_OK(hipGetLastError());

@@ -221,8 +221,10 @@ __device__ inline uint32_t row_of(const uint32_t* row_ptr, int32_t n, uint32_t e
   return (uint32_t)upper_index<uint32_t>(row_ptr, 0, n + 1, e);
 }
 
+// max_sel: an upper bound of the device-side nsel (one workgroup per CG)
 void launch_pack_vc(const uint32_t* vc_cnt, const int32_t* vc_tmp, const uint64_t* cg_noff,
-                    const int32_t* nsel, uint32_t* vc_off, int32_t* vc_nodes, hipStream_t s);
+                    const int32_t* nsel, uint32_t* vc_off, int32_t* vc_nodes, int max_sel,
+                    hipStream_t s);
 void launch_check_and_count(const DevGraphView& g, uint32_t* c_tmp, int32_t* arc_src, uint32_t* rev,
                             Status* st,
                             hipStream_t s);

@@ -552,22 +552,28 @@ __global__ __launch_bounds__(kBlock) void k_big_write(FinalizeView v, int t, int
   }
 }
 
+// V_C of every selected CG packed in CG order: workgroup r sums the counts of
+// the CGs before it and copies CG r's list there.
 __global__ __launch_bounds__(kBlock) void k_pack_vc(const uint32_t* vc_cnt, const int32_t* vc_tmp,
                                                     const uint64_t* cg_noff, const int32_t* nsel_p,
                                                     uint32_t* vc_off, int32_t* vc_nodes) {
-  __shared__ uint32_t s_off[kMaxW + 1];
+  __shared__ uint32_t s32[kBlock / kWave + 1];
   const int nsel = *nsel_p;
+  const int r = blockIdx.x;
+  if (r >= nsel) {
+    if (r == 0 && threadIdx.x == 0) vc_off[0] = 0;   // no CG: empty lists
+    return;
+  }
+  uint32_t part = 0;
+  for (int i = threadIdx.x; i < r; i += kBlock) part += vc_cnt[i];
+  const uint32_t off = block_sum<uint32_t, kBlock>(part, s32);
+  const uint32_t cnt = vc_cnt[r];
   if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (int r = 0; r < nsel; ++r) { s_off[r] = acc; acc += vc_cnt[r]; }
-    s_off[nsel] = acc;
+    vc_off[r] = off;
+    if (r == nsel - 1) vc_off[nsel] = off + cnt;
   }
-  __syncthreads();
-  for (int r = threadIdx.x; r <= nsel; r += kBlock) vc_off[r] = s_off[r];
-  for (int r = 0; r < nsel; ++r) {
-    const int32_t* src = vc_tmp + cg_noff[r];
-    for (uint32_t i = threadIdx.x; i < vc_cnt[r]; i += kBlock) vc_nodes[s_off[r] + i] = src[i];
-  }
+  const int32_t* src = vc_tmp + cg_noff[r];
+  for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) vc_nodes[off + i] = src[i];
 }
 
 void launch_recover(const RecoverView& v, hipStream_t s) {
@@ -643,8 +649,9 @@ void launch_big_finalize(const FinalizeView& v, int t, uint32_t* bm, uint32_t* c
 }
 
 void launch_pack_vc(const uint32_t* vc_cnt, const int32_t* vc_tmp, const uint64_t* cg_noff,
-                    const int32_t* nsel, uint32_t* vc_off, int32_t* vc_nodes, hipStream_t s) {
-  k_pack_vc<<<1, kBlock, 0, s>>>(vc_cnt, vc_tmp, cg_noff, nsel, vc_off, vc_nodes);
+                    const int32_t* nsel, uint32_t* vc_off, int32_t* vc_nodes, int max_sel,
+                    hipStream_t s) {
+  if (max_sel > 0) k_pack_vc<<<max_sel, kBlock, 0, s>>>(vc_cnt, vc_tmp, cg_noff, nsel, vc_off, vc_nodes);
 }
 
 }  // namespace raks
