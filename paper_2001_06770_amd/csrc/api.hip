@@ -1238,11 +1238,13 @@ void serve_worker(Ctx* c, Lane* L) {
   }
 }
 
-// Device bytes one lane holds on this graph (node-sized buffers for up to 16
-// keywords per run plus a recovery allowance).
+// Device bytes one lane holds on this graph: per node the two H matrices for
+// up to 16 keywords per run, the reached masks, the expansion queue, the
+// candidate keys and the scan's staging; the tile map; a recovery allowance.
 size_t lane_bytes_estimate(const Ctx* c) {
   const size_t np = (size_t)c->n + kScanNodes;
-  return np * (16 + 16 + 1 + 16 + 8) + ((size_t)64 << 20);
+  return np * (16 + 16 + 2 + 16 + 8 + 16 + 8) + ((size_t)c->A / kExpandTile + 2) * 4 +
+         ((size_t)64 << 20);
 }
 
 // Drains the queue: queries already submitted still run; their results are
