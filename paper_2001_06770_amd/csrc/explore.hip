@@ -128,18 +128,18 @@ __global__ __launch_bounds__(kBlock) void k_seed(uint8_t* H, const int32_t* kw_n
 
 // --------------------------------------------------------- frontier scan ---
 //
-// Work-efficient form of Algorithm 1 (same H, frontiers and counters).  A
-// frontier f at level l is retained (line 11) exactly when it expands and its
-// row has an arc of level > l: a property of the row, precomputed as
-// row_amax.  A keyword i with h_fi < l expanded f at level l-1 over all arcs
+// Work-efficient form of Algorithm 1 (same H, frontiers and counters).
+// Algorithm 1 keeps a frontier f in the frontier after level l exactly when
+// it expands and its row has an arc of level > l (an arc it could not cross
+// yet): a property of the row, precomputed as row_amax.  A keyword i with h_fi < l expanded f at level l-1 over all arcs
 // of level <= l-1, so only arcs of level exactly l can reach new nodes for it;
 // a keyword with h_fi = l needs all arcs of level <= l.  With rows sorted by
 // level these are the row slices [lo, hi) and [0, hi), read from the level
 // table.
 //
 // No frontier flags are stored.  By induction over the levels, v is in the
-// level-l frontier exactly when some keyword reached it at level l (line 17
-// set its flag), or it was reached before l, its row has an arc of level
+// level-l frontier exactly when some keyword reached it at level l (the
+// expansion set its flag), or it was reached before l, its row has an arc of level
 // > l-1 and it was not blocked at l-1: from the level it is first reached on,
 // a node stays a frontier for as long as it expands and keeps arcs of higher
 // levels, and blocking (a complete row) never ends.  All of this is in the H
@@ -576,7 +576,7 @@ __global__ __launch_bounds__(kCtl) void k_front_enqueue(RunView r, int level, Ru
 // Algorithm 1 at level `level` over the queued row slices (all of them have
 // level <= l).  For arc f -> n every keyword i that f expands for and that has
 // not reached n gets h_ni = level + 1, which makes n a frontier of the next
-// level (lines 13-17).  One gather of the neighbour's reached mask serves
+// level.  One gather of the neighbour's reached mask serves
 // every keyword at once.  Tile of 1024 consecutive arcs of the concatenated
 // slices: the tile map gives its first and last queue entry, the entries go
 // to LDS, each entry marks the tile item where it starts and a block max-scan
