@@ -462,8 +462,9 @@ __device__ void control_level(const RunView& r, int level, RunStatus* mirror, ui
     if (b0 + i < b1) t[i] = r.tot[b0 + i];
     else t[i] = ScanTot{};
   }
-  // thread 0 keeps the run's status in registers and stores it once
-  RunStatus cur;
+  // thread 0 keeps the run's status in LDS (not in private memory, which
+  // every launch of the kernel would then have to set up) and stores it once
+  __shared__ RunStatus cur;
   if (threadIdx.x == 0) cur = *st;
   if (level > st->end_level) {
     if (threadIdx.x == 0) publish(mirror, cur, seq);
