@@ -10,8 +10,10 @@ Parity status per function (what pins it is in ``tests/test_oracle_pins.py``):
                     plain BFS special cases, order-independence)
   query / run 1     pinned (identification vs. brute force, recovery vs.
                     brute-force prefix-optimal paths, invariants)
-  query / run 2     pinned in part (S^m vs. brute force for one marginal
-                    keyword; Theorem 4 vs. a run without early termination);
+  query / run 2     pinned in part (S^m and keys vs. the Dial formulation;
+                    marginal recovery vs. brute force for one marginal keyword
+                    and vs. path enumeration of the blocked H for two and
+                    three; Theorem 4 vs. a run without early termination);
                     the PTC guard, the tie-breaks and gamma follow stated
                     readings and are otherwise parity unpinned.
 """

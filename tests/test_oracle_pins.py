@@ -522,6 +522,43 @@ def test_single_marginal_keyword_recovery_brute_force():
     assert checked > 20
 
 
+@pytest.mark.parametrize("central,marginal", [((0, 1), (2, 3)), ((0,), (1, 2, 3))])
+def test_multi_marginal_recovery_blocked_brute_force(central, marginal):
+    """|M| >= 2 (PTC blocking on the marginal run): each RPG is its CG plus,
+    per marginal keyword j, the Lemma 1 chains of the blocked marginal H
+    (Dial formulation) into the V_C nodes at the minimum D_j (Algorithm 2 on
+    the marginal run, Definition 5), checked by path enumeration; S^m and the
+    key follow Eq. 5 and Eq. 6."""
+    checked = 0
+    for g, act in tiny_cases(80, seed=7):
+        o = oracle.Oracle(g)
+        q = synth.Query(central, marginal, k=4, w=4, max_level=20)
+        cgs = o.query(act, synth.Query(central, (), q.w, q.w, q.max_level))
+        cg = {r["central"]: r for r in cgs["results"]}
+        order = [(r["score_c"], r["central"]) for r in cgs["results"]]
+        res = o.query(act, q, flags=oracle.FLAG_NO_THM4)
+        exp = rpg_expectation(g, act, q, {c: r["nodes"] for c, r in cg.items()}, order)
+        assert [(r["key"], r["central"], r["score_m"]) for r in res["results"]] == \
+            [(k, c, m) for k, _, _, c, m in exp]
+        Dm = dial(g, act, [graphs.keyword_nodes(g, t) for t in marginal], True, q.max_level)
+        Dc = dial(g, act, [graphs.keyword_nodes(g, t) for t in central], True, q.max_level)
+        for r in res["results"]:
+            base = cg[r["central"]]
+            vc = [v for v in base["nodes"] if (Dc[v] == 0).any()]
+            nodes, arcs = set(base["nodes"]), set(base["arcs"])
+            for j in range(len(marginal)):
+                dj = min(int(Dm[v, j]) for v in vc)
+                assert dj <= r["score_m"]
+                for v in vc:
+                    if Dm[v, j] == dj:
+                        nn, aa = lemma1_chains(g, act, Dm, j, v)
+                        nodes |= nn
+                        arcs |= aa
+            assert set(r["nodes"]) == nodes and set(r["arcs"]) == arcs
+            checked += 1
+    assert checked > 20
+
+
 def test_no_marginal_keywords_returns_central_graphs():
     g = synth.make_graph("tiny2")
     o = oracle.Oracle(g)
