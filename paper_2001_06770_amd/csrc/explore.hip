@@ -191,7 +191,7 @@ struct NodeInfo {
   uint32_t work;                // hi - start if the node expands
   uint32_t hw;                  // entries written at the previous level
   uint32_t reached;             // keywords with a finite hitting level
-  bool active, cand, retain;
+  bool active, cand;
   uint64_t key;
 };
 
@@ -217,7 +217,6 @@ __device__ inline NodeInfo inspect_node(const RunView& r, const DevGraphView& g,
   o.cand = (r.kind == RUN_CENTRAL) && st.complete && st.mx == (uint32_t)level;
   o.key = ((uint64_t)st.mx << 48) | ((uint64_t)st.sum << 32) | (uint32_t)v;
   o.lo = o.hi = o.start = o.work = 0;
-  o.retain = false;
   if (o.active) {
     // arcs of level <= x: none below 0, the whole row from its largest level
     // on, else the level table (or a search of the row past the table)
@@ -225,7 +224,6 @@ __device__ inline NodeInfo inspect_node(const RunView& r, const DevGraphView& g,
     o.hi = xh >= (int)amax ? d : (xh < g.nbnd ? bhi : count_le(g, v, xh));
     o.start = o.mask_new ? 0 : o.lo;
     o.work = o.hi - o.start;
-    o.retain = amax > (uint32_t)level;
   }
   return o;
 }
@@ -442,7 +440,7 @@ __device__ int rpg_identify(const RunView& r, uint32_t* nrpg_io, int level) {
 // which the host polls for.  Every thread loads its scan totals
 // (at most two workgroups' worth) before anything else, so the kernel waits
 // for memory about once before the scan.
-static_assert(kScanGroups <= 2 * kCtl, "the control kernel keeps two scan totals per thread");
+static_assert(kScanGroups <= 2 * kCtl, "the control step keeps two scan totals per thread");
 
 __device__ inline void publish(RunStatus* mirror, const RunStatus& st, uint64_t seq) {
   *mirror = st;
