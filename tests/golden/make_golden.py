@@ -7,7 +7,7 @@ and, for each sampled query, the status, the counters of both
 runs and, per result, central node, scores, key, sizes and SHA-256 digests of
 the node list (int32 little-endian) and of the arc list ((src, dst, label)
 int32 triples), so the GPU tests can check full-size outputs without running
-the reference on the GPU machine.
+the reference at those sizes during the test.
 
 usage: python tests/golden/make_golden.py large [n_queries]
 """
