@@ -269,6 +269,9 @@ def main():
                      "avg_launch_us": texp["ms"] * 1e3 / max(texp["launches"], 1),
                      "bytes_per_launch": texp["bytes"] / max(texp["launches"], 1)},
     }
+    # algorithmic efficiency: algorithmic bytes per launch over measured HBM bytes
+    rf = out["roofline"]
+    rf["alg_efficiency"] = rf["bytes_per_launch"] / rf["traffic"] if rf["traffic"] else None
 
     # ---- the other path, same queries (not part of the timed steps)
     if not args.only_timed:
