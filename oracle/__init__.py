@@ -16,6 +16,10 @@ Parity status per function (what pins it is in ``tests/test_oracle_pins.py``):
                     three; Theorem 4 vs. a run without early termination);
                     the PTC guard, the tie-breaks and gamma follow stated
                     readings and are otherwise parity unpinned.
+  work counters     pinned (tests/test_oracle_counters.py: frontier sizes,
+  and status bits   e_arc, e_alg, gate_pass, h_writes and the level-bound
+                    bits derived from Dial distances and Algorithm 1's
+                    frontier rule, plus hand-counted graphs)
 """
 from __future__ import annotations
 
