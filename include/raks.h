@@ -208,21 +208,49 @@ typedef struct {
  * returns its results.  *out is library-owned until raks_results_free. */
 int raks_query(raks_ctx* ctx, const raks_query_desc* q, raks_results** out);
 
-/* Runs n queries on the context's lanes at once (each lane takes the next
- * query when its previous one is done); outs[i] receives the results of
- * qs[i], identical to those of raks_query(qs[i]), each owned independently.
- * On error no output is left allocated. */
+/* Runs n queries and returns outs[i] = the results of qs[i], identical to
+ * those of raks_query(qs[i]), each owned independently.  On error no output
+ * is left allocated.
+ * In the default batch mode (RAKS_BATCH_COHORT) the queries run as cohorts:
+ * up to 32 queries at a time share one level loop on the device, each with
+ * its central and marginal keywords as columns of one query-tagged
+ * node x keyword hitting-level matrix (64 columns); one frontier scan and one
+ * expansion per level serve all of them, so an arc is read once for every
+ * query that expands its source node (Section 4.2.1's shared frontier, taken
+ * from keywords to queries).  Both runs of a query advance together (the
+ * marginal search does not depend on the central graphs, Section 4.2.3); its
+ * RPG check starts once its central graphs are recovered and replays the
+ * levels in between, so every decision is the one of the two sequential
+ * runs.  A finished query frees its slot and columns and the next waiting
+ * one is admitted at the next level boundary.  Queries with a per-query
+ * alpha, more than 16 keywords, an empty keyword or max_level above 125 run
+ * on the single-query path instead.
+ * In RAKS_BATCH_LANES mode each lane runs whole single queries, taking the
+ * next one when its previous one is done. */
 int raks_query_batch(raks_ctx* ctx, const raks_query_desc* qs, int32_t n, raks_results** outs);
 
-/* Serving: a worker thread per lane runs submitted queries in arrival order
- * as lanes become free (continuous admission; results as raks_query gives
- * them).  While serving runs, raks_query / raks_query_batch / raks_load_graph
- * / raks_set_alpha return RAKS_ESTATE. */
-typedef struct {
-    int32_t lanes;      /* 0 = as many as half of the free device memory holds, at most 8 */
-    int32_t queue_cap;  /* waiting queries allowed, 0 = unbounded */
-} raks_serve_opts;
+#define RAKS_BATCH_COHORT 0   /* queries share level loops (default) */
+#define RAKS_BATCH_LANES 1    /* independent single-query runs on the lanes */
+/* Selects how raks_query_batch and serving run queries.  RAKS_EINVAL for an
+ * unknown mode, RAKS_ESTATE while serving runs. */
+int raks_set_batch_mode(raks_ctx* ctx, int32_t mode);
 
+/* Serving (continuous batching).  In RAKS_BATCH_COHORT mode one engine thread
+ * runs the level loop: a submitted query joins the running cohort at the next
+ * level boundary as soon as a slot, |C|+|M| columns and the device memory of
+ * its post-processing state (a lane's recovery buffers; admission waits
+ * while the allocation does not fit) are free, so queries that arrive while
+ * others are on the GPU share their levels; finished queries are completed by
+ * worker threads on their lanes' streams.  In RAKS_BATCH_LANES mode a worker
+ * thread per lane runs submitted queries in arrival order as lanes become
+ * free.  Results are those raks_query gives.  While serving runs,
+ * raks_query / raks_query_batch / raks_load_graph / raks_set_alpha /
+ * raks_set_batch_mode return RAKS_ESTATE. */
+typedef struct {
+    int32_t lanes;      /* lanes mode: 0 = as many as half of the free device memory holds, at most 8 */
+    int32_t queue_cap;  /* queries submitted and not finished allowed (cohort mode) or waiting
+                         * (lanes mode), 0 = unbounded */
+} raks_serve_opts;
 /* Starts serving (opts may be NULL).  RAKS_ESTATE without a graph or when
  * serving already runs. */
 int raks_serve_start(raks_ctx* ctx, const raks_serve_opts* opts);

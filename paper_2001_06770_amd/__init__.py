@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libraks.so")
 
 RAKS_ACT_EDGE, RAKS_ACT_NODE = 0, 1
+RAKS_BATCH_COHORT, RAKS_BATCH_LANES = 0, 1
 END_NAMES = {0: "none", 1: "exhausted", 2: "stop", 3: "level_bound", 4: "empty_keyword"}
 TIMER_EXPAND, TIMER_SCAN, TIMER_CONTROL, TIMER_RECOVER, TIMER_OTHER = range(5)
 
@@ -118,6 +119,7 @@ def lib():
                                 ctypes.POINTER(ctypes.POINTER(Results))]
         L.raks_serve_stop.argtypes = [ctypes.c_void_p]
         L.raks_results_free.restype = None
+        L.raks_set_batch_mode.argtypes = [ctypes.c_void_p, ctypes.c_int32]
         L.raks_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
         L.raks_get_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(KernelTiming)]
         L.raks_last_error.restype = ctypes.c_char_p
@@ -129,7 +131,8 @@ def lib():
 EXPORTED = ("raks_create", "raks_destroy", "raks_load_graph", "raks_set_alpha",
             "raks_get_activations", "raks_query", "raks_query_batch", "raks_results_free",
             "raks_serve_start", "raks_submit", "raks_poll", "raks_wait", "raks_serve_stop",
-            "raks_set_timing", "raks_get_timing", "raks_last_error", "raks_version")
+            "raks_set_timing", "raks_get_timing", "raks_last_error", "raks_version",
+            "raks_set_batch_mode")
 RAKS_EAGAIN = -5
 
 
@@ -175,7 +178,8 @@ class Context:
     """One GPU context holding one graph (``raks_ctx``)."""
 
     def __init__(self, device: int = 0, use_torch: bool = True, mem_budget: int = 0,
-                 lanes: int = 1, rec_caps=(0, 0, 0), big_list: int = 0):
+                 lanes: int = 1, rec_caps=(0, 0, 0), big_list: int = 0,
+                 batch_mode: int = RAKS_BATCH_COHORT):
         self._keep = []
         opts = CtxOpts()
         opts.device = device
@@ -205,6 +209,12 @@ class Context:
             self._keep += [opts.alloc, opts.free, stream]
         self._h = ctypes.c_void_p()
         _check(lib().raks_create(ctypes.byref(self._h), ctypes.byref(opts)))
+        if batch_mode != RAKS_BATCH_COHORT:
+            self.set_batch_mode(batch_mode)
+
+    def set_batch_mode(self, mode: int):
+        """RAKS_BATCH_COHORT (queries share level loops) or RAKS_BATCH_LANES."""
+        _check(lib().raks_set_batch_mode(self._h, int(mode)))
 
     def close(self):
         if self._h:
@@ -265,7 +275,7 @@ class Context:
             lib().raks_results_free(out)
 
     def query_batch(self, qs, lean: bool = False) -> list:
-        """Runs the queries on the context's lanes at once."""
+        """Runs the queries together (cohorts, or lanes in RAKS_BATCH_LANES mode)."""
         keep = []
         n = len(qs)
         arr = (QueryDesc * max(n, 1))(*[self._desc(q, keep) for q in qs])

@@ -27,13 +27,14 @@
 #include <thread>
 #include <vector>
 
+#include "host.h"
 #include "runtime.h"
 
 using namespace raks;
 
 struct raks_ctx : public raks::Ctx {};
 
-namespace {
+namespace raks {
 
 thread_local std::string g_err;
 
@@ -41,19 +42,6 @@ int fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
 }
-
-#define HIP_OK(expr)                                                                  \
-  do {                                                                                \
-    hipError_t _e = (expr);                                                           \
-    if (_e != hipSuccess)                                                             \
-      return fail(RAKS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));   \
-  } while (0)
-
-#define RAKS_TRY(expr)              \
-  do {                              \
-    int _rc = (expr);               \
-    if (_rc != RAKS_OK) return _rc; \
-  } while (0)
 
 double now_ms() {
   return std::chrono::duration<double, std::milli>(
@@ -383,14 +371,6 @@ void release_view(Lane* L) {
 
 // ------------------------------------------------------------- query ---
 
-struct QueryPlan {
-  int C, M, TPc, TPm, k, w, L, gn, gd;
-  double alpha;   // 0: the context's
-  int score_mode, rerank;
-  int n_build;    // RPGs recovered: k, or w when equal scores are re-ranked
-  std::vector<int32_t> central, marginal;
-};
-
 int validate_query(Ctx* c, const raks_query_desc* q, QueryPlan& p) {
   if (!q) return fail(RAKS_EINVAL, "query descriptor is NULL");
   p.C = q->n_central;
@@ -432,6 +412,22 @@ int validate_query(Ctx* c, const raks_query_desc* q, QueryPlan& p) {
   return RAKS_OK;
 }
 
+// Per-query arrays of a lane that do not scale with the graph.
+int ensure_small_buffers(Lane* L) {
+  Ctx* c = L->ctx;
+  RAKS_TRY(dev_alloc(c, L->sel_node, kMaxW * 4));
+  RAKS_TRY(dev_alloc(c, L->sel_sc, kMaxW * 4));
+  RAKS_TRY(dev_alloc(c, L->sel_sumh, kMaxW * 4));
+  RAKS_TRY(dev_alloc(c, L->has_rpg, kMaxW * 4));
+  RAKS_TRY(dev_alloc(c, L->sm, kMaxW * 4));
+  RAKS_TRY(dev_alloc(c, L->key, kMaxW * 8));
+  RAKS_TRY(dev_alloc(c, L->dmin, kMaxW * kMaxKw));
+  RAKS_TRY(dev_alloc(c, L->ranked, kMaxW * 4));
+  RAKS_TRY(dev_alloc(c, L->vc_cnt, kMaxW * 4));
+  RAKS_TRY(dev_alloc(c, L->vc_off, (kMaxW + 1) * 4));
+  return RAKS_OK;
+}
+
 int ensure_node_buffers(Lane* L) {
   Ctx* c = L->ctx;
   L->n_pad = (int32_t)(((int64_t)c->n + kScanNodes - 1) / kScanNodes * kScanNodes);
@@ -451,17 +447,7 @@ int ensure_node_buffers(Lane* L) {
   RAKS_TRY(dev_alloc(c, L->cand, np * 8));
   RAKS_TRY(dev_alloc(c, L->s_item, np * 16));
   RAKS_TRY(dev_alloc(c, L->s_cand, np * 8));
-  RAKS_TRY(dev_alloc(c, L->sel_node, kMaxW * 4));
-  RAKS_TRY(dev_alloc(c, L->sel_sc, kMaxW * 4));
-  RAKS_TRY(dev_alloc(c, L->sel_sumh, kMaxW * 4));
-  RAKS_TRY(dev_alloc(c, L->has_rpg, kMaxW * 4));
-  RAKS_TRY(dev_alloc(c, L->sm, kMaxW * 4));
-  RAKS_TRY(dev_alloc(c, L->key, kMaxW * 8));
-  RAKS_TRY(dev_alloc(c, L->dmin, kMaxW * kMaxKw));
-  RAKS_TRY(dev_alloc(c, L->ranked, kMaxW * 4));
-  RAKS_TRY(dev_alloc(c, L->vc_cnt, kMaxW * 4));
-  RAKS_TRY(dev_alloc(c, L->vc_off, (kMaxW + 1) * 4));
-  return RAKS_OK;
+  return ensure_small_buffers(L);
 }
 
 SeedList seeds_for(Ctx* c, const std::vector<int32_t>& kws) {
@@ -524,6 +510,8 @@ __global__ void k_query_reset(Status* st) {
   st->out_nodes = 0;
   st->out_arcs = 0;
 }
+
+void launch_query_reset(Status* st, hipStream_t s) { k_query_reset<<<1, 1, 0, s>>>(st); }
 
 // Waits until the control launch numbered `want` has published its status in
 // pinned slot `slot`.  The stream is queried now and then, so that a failed
@@ -809,12 +797,12 @@ int grow_phase(Lane* L, int ph, int n_valid, int max_layer) {
   return RAKS_OK;
 }
 
-RecoverView recover_view(Lane* L, int ph, DevBuf& H, int TP, const int32_t* n_valid,
+RecoverView recover_view(Lane* L, int ph, const uint8_t* H, int TP, const int32_t* n_valid,
                          int max_layer) {
   RecPhase& Ph = L->ph[ph];
   RecoverView v = {};
   v.g = graph_view(L);
-  v.H = P<uint8_t>(H);
+  v.H = H;
   v.TP = TP;
   v.T = Ph.T;
   v.marginal = ph;
@@ -841,7 +829,8 @@ RecoverView recover_view(Lane* L, int ph, DevBuf& H, int TP, const int32_t* n_va
   return v;
 }
 
-FinalizeView finalize_view(Lane* L, int ph, const int32_t* n_valid, int C, int TPc) {
+FinalizeView finalize_view(Lane* L, int ph, const int32_t* n_valid, int C, const uint8_t* Hc,
+                           int TPc) {
   RecPhase& Ph = L->ph[ph];
   RecPhase& P0 = L->ph[0];
   char* lay = static_cast<char*>(Ph.layout.p);
@@ -863,7 +852,7 @@ FinalizeView finalize_view(Lane* L, int ph, const int32_t* n_valid, int C, int T
   v.cg_cnt = P<uint32_t>(L->cg_cnt);
   v.cg_noff = reinterpret_cast<const uint64_t*>(lay0 + P0.lay_cg_noff);
   v.cg_aoff = reinterpret_cast<const uint64_t*>(lay0 + P0.lay_cg_aoff);
-  v.Hc = P<uint8_t>(L->Hc);
+  v.Hc = Hc;
   v.TPc = TPc;
   v.Tc = C;
   v.vc_cnt = P<uint32_t>(L->vc_cnt);
@@ -896,6 +885,28 @@ __global__ void k_retry_reset(Status* st) {
   st->out_arcs = 0;
 }
 
+void launch_retry_reset(Status* st, hipStream_t s) { k_retry_reset<<<1, 1, 0, s>>>(st); }
+
+// Ranking input of the lane's query (selected CGs and their RPG records).
+RankView rank_view(Lane* L, const QueryPlan& p) {
+  Status* st = P<Status>(L->status);
+  RankView rv;
+  rv.gst = st;
+  rv.nsel = &st->nsel;
+  rv.M = p.M;
+  rv.k = p.k;
+  rv.gamma_num = p.gn;
+  rv.gamma_den = p.gd;
+  rv.score_mode = p.score_mode;
+  rv.rerank = p.rerank;
+  rv.sel_sc = P<int32_t>(L->sel_sc);
+  rv.has_rpg = P<int32_t>(L->has_rpg);
+  rv.sm = P<int32_t>(L->sm);
+  rv.key = P<int64_t>(L->key);
+  rv.ranked = P<int32_t>(L->ranked);
+  return rv;
+}
+
 struct QueryRun {
   RunStatus s1 = {}, s2 = {};
   int top1 = 0, top2 = 0;
@@ -906,7 +917,7 @@ __global__ void k_clear_flag(Status* st, int32_t bits) { st->overflow &= ~bits; 
 
 // Runs the bitmap path for every result of phase `ph` that its finalize
 // flagged.  Waits for the stream first (the flags are read on the host).
-int big_finalize(Lane* L, int ph, const QueryPlan& p, int n_res) {
+int big_finalize(Lane* L, int ph, const QueryPlan& p, int n_res, const uint8_t* Hc, int TPc) {
   Ctx* c = L->ctx;
   hipStream_t s = L->stream;
   std::vector<uint32_t> flags((size_t)std::max(n_res, 1), 0u);
@@ -922,7 +933,7 @@ int big_finalize(Lane* L, int ph, const QueryPlan& p, int n_res) {
   RAKS_TRY(dev_alloc(c, L->big_chunk, (words / 1024 + 2) * 4));
   RAKS_TRY(dev_alloc(c, L->big_slot, 8));
   const FinalizeView fv = finalize_view(L, ph, ph == 0 ? &P<Status>(L->status)->nsel
-                                                       : &P<Status>(L->status)->nres, p.C, p.TPc);
+                                                       : &P<Status>(L->status)->nres, p.C, Hc, TPc);
   {
     Timed t(L, 3);
     for (int r = 0; r < n_res; ++r)
@@ -963,10 +974,10 @@ int stage_cg_recovery(Lane* L, const QueryPlan& p, const QueryRun& q) {
   Status* st = P<Status>(L->status);
   {
     Timed t(L, 3);
-    launch_recover(recover_view(L, 0, L->Hc, p.TPc, &st->nsel, q.top1), s);
-    launch_finalize(finalize_view(L, 0, &st->nsel, p.C, p.TPc), s);
+    launch_recover(recover_view(L, 0, P<uint8_t>(L->Hc), p.TPc, &st->nsel, q.top1), s);
+    launch_finalize(finalize_view(L, 0, &st->nsel, p.C, P<uint8_t>(L->Hc), p.TPc), s);
   }
-  if (q.big0) RAKS_TRY(big_finalize(L, 0, p, p.w));
+  if (q.big0) RAKS_TRY(big_finalize(L, 0, p, p.w, P<uint8_t>(L->Hc), p.TPc));
   {
     Timed t(L, 3);
     if (p.M > 0) {
@@ -990,22 +1001,9 @@ int stage_marginal(Lane* L, const QueryPlan& p, QueryRun& q) {
     RAKS_TRY(run_levels(L, r2, p.TPm, p.marginal, p.M, &q.s2));
     q.top2 = std::max(0, q.s2.levels - 1);
   }
-  RankView rv;
-  rv.gst = st;
-  rv.nsel = &st->nsel;
-  rv.M = p.M;
-  rv.k = p.k;
-  rv.gamma_num = p.gn;
-  rv.gamma_den = p.gd;
-  rv.score_mode = p.score_mode;
-  rv.rerank = p.rerank;
-  rv.sel_sc = P<int32_t>(L->sel_sc);
-  rv.has_rpg = P<int32_t>(L->has_rpg);
-  rv.sm = P<int32_t>(L->sm);
-  rv.key = P<int64_t>(L->key);
-  rv.ranked = P<int32_t>(L->ranked);
+  (void)st;
   Timed t(L, 2);
-  launch_rank(rv, s);
+  launch_rank(rank_view(L, p), s);
   return RAKS_OK;
 }
 
@@ -1015,8 +1013,9 @@ int stage_output(Lane* L, const QueryPlan& p, const QueryRun& q) {
   Status* st = P<Status>(L->status);
   {
     Timed t(L, 3);
-    if (p.M > 0) launch_recover(recover_view(L, 1, L->Hm, p.TPm, &st->nres, q.top2), s);
-    launch_finalize(finalize_view(L, 1, &st->nres, p.C, p.TPc), s);
+    if (p.M > 0)
+      launch_recover(recover_view(L, 1, P<uint8_t>(L->Hm), p.TPm, &st->nres, q.top2), s);
+    launch_finalize(finalize_view(L, 1, &st->nres, p.C, P<uint8_t>(L->Hc), p.TPc), s);
     if (p.rerank) launch_rerank(P<ResultHdr>(L->hdr), st, p.k, s);
   }
   HIP_OK(hipGetLastError());
@@ -1165,7 +1164,7 @@ int query_plan_on_lane(Lane* L, const QueryPlan& p, raks_results** out, double t
     const bool redo_cg = (ovf & (1 | kOvfBig0)) != 0;
     if (!redo_cg && !(ovf & 2)) {
       // only RPGs too large for the sort path: their lists are all there
-      RAKS_TRY(big_finalize(L, 1, p, p.n_build));
+      RAKS_TRY(big_finalize(L, 1, p, p.n_build, P<uint8_t>(L->Hc), p.TPc));
       if (p.rerank) launch_rerank(P<ResultHdr>(L->hdr), P<Status>(L->status), p.k, L->stream);
       HIP_OK(hipEventRecord(L->q_end, L->stream));
       RAKS_TRY(collect(L, p, out, &ovf));
@@ -1252,6 +1251,18 @@ size_t lane_bytes_estimate(const Ctx* c) {
 void stop_serving(Ctx* c) {
   ServeState& S = c->serve;
   if (!S.running) return;
+  if (S.cohort) {
+    cohort_serve_stop(c);
+    for (auto& kv : S.jobs) {
+      raks_results_free(kv.second->res);
+      delete kv.second;
+    }
+    S.jobs.clear();
+    S.running = false;
+    S.cohort = false;
+    S.stop = false;
+    return;
+  }
   {
     std::lock_guard<std::mutex> lk(S.mu);
     S.stop = true;
@@ -1286,7 +1297,7 @@ int take_job(Ctx* c, uint64_t ticket, raks_results** out, bool wait) {
   return rc;
 }
 
-}  // namespace
+}  // namespace raks
 
 // =================================================================== ABI ===
 
@@ -1337,6 +1348,7 @@ int raks_destroy(raks_ctx* c) {
   if (!c) return RAKS_OK;
   (void)hipSetDevice(c->device);
   stop_serving(c);
+  cohort_destroy(c);
   for (auto& L : c->lanes) lane_destroy(c, L.get());
   c->lanes.clear();
   drop_views(c);
@@ -1352,6 +1364,7 @@ int raks_load_graph(raks_ctx* c, const raks_graph_desc* g) {
   if (!c || !g) return fail(RAKS_EINVAL, "NULL argument");
   if (c->serve.running) return fail(RAKS_ESTATE, "serving is running");
   HIP_OK(hipSetDevice(c->device));
+  cohort_destroy(c);
   const int64_t n = g->n_nodes, A = g->n_arcs;
   if (n < 1 || n >= INT32_MAX) return fail(RAKS_EINVAL, "n_nodes out of range");
   if (A < 0 || A >= (int64_t)UINT32_MAX) return fail(RAKS_EINVAL, "n_arcs must be below 2^32");
@@ -1450,6 +1463,8 @@ int raks_query_batch(raks_ctx* c, const raks_query_desc* qs, int32_t n, raks_res
   if (c->serve.running) return fail(RAKS_ESTATE, "serving is running: use raks_submit");
   HIP_OK(hipSetDevice(c->device));
   for (int32_t i = 0; i < n; ++i) outs[i] = nullptr;
+  if (!c->loaded) return fail(RAKS_ESTATE, "no graph loaded");
+  if (c->batch_mode == 0) return cohort_query_batch(c, qs, n, outs);
   const int lanes = std::min<int>((int)c->lanes.size(), std::max(n, 1));
   std::atomic<int32_t> next{0};
   std::vector<int> rcs(lanes, RAKS_OK);
@@ -1509,6 +1524,12 @@ int raks_serve_start(raks_ctx* c, const raks_serve_opts* o) {
   const int32_t cap = o ? o->queue_cap : 0;
   if (lanes < 0 || lanes > kMaxLanes || cap < 0) return fail(RAKS_EINVAL, "bad serving options");
   HIP_OK(hipSetDevice(c->device));
+  if (c->batch_mode == 0) {
+    c->serve.cohort = true;
+    const int rc = cohort_serve_start(c, cap);
+    if (rc) c->serve.cohort = false;
+    return rc;
+  }
   if (lanes == 0) {
     // as many lanes as half of the free device memory holds, 1..8
     size_t free_b = 0, total_b = 0;
@@ -1532,6 +1553,7 @@ int raks_submit(raks_ctx* c, const raks_query_desc* q, uint64_t* ticket) {
   if (q->n_central < 0 || q->n_central > kMaxKw || q->n_marginal < 0 || q->n_marginal > kMaxKw ||
       (q->n_central > 0 && !q->central) || (q->n_marginal > 0 && !q->marginal))
     return fail(RAKS_EINVAL, "bad keyword arrays");
+  if (S.cohort) return cohort_submit(c, q, ticket);
   Job* job = new Job();
   job->central.assign(q->central, q->central + q->n_central);
   if (q->n_marginal > 0) job->marginal.assign(q->marginal, q->marginal + q->n_marginal);
@@ -1571,6 +1593,14 @@ int raks_wait(raks_ctx* c, uint64_t ticket, raks_results** out) {
 int raks_serve_stop(raks_ctx* c) {
   if (!c) return fail(RAKS_EINVAL, "ctx is NULL");
   stop_serving(c);
+  return RAKS_OK;
+}
+
+int raks_set_batch_mode(raks_ctx* c, int32_t mode) {
+  if (!c) return fail(RAKS_EINVAL, "ctx is NULL");
+  if (mode != RAKS_BATCH_COHORT && mode != RAKS_BATCH_LANES) return fail(RAKS_EINVAL, "unknown batch mode");
+  if (c->serve.running) return fail(RAKS_ESTATE, "serving is running");
+  c->batch_mode = mode;
   return RAKS_OK;
 }
 

@@ -24,7 +24,7 @@ namespace raks {
 constexpr int kTimers = 5;
 constexpr size_t kSpecNodes = 1 << 16;   // output read back with the headers
 constexpr size_t kSpecArcs = 1 << 16;
-constexpr int kMaxLanes = 32;
+constexpr int kMaxLanes = 64;
 constexpr int kMaxViews = 4;       // cached activation views for per-query alphas
 
 struct DevBuf {
@@ -136,6 +136,7 @@ struct ServeState {
   std::unordered_map<uint64_t, Job*> jobs;
   uint64_t next_ticket = 1;
   int in_flight = 0;
+  bool cohort = false;   // served by the cohort engine (else one worker per lane)
 };
 
 struct Ctx {
@@ -170,6 +171,10 @@ struct Ctx {
   std::vector<int64_t> kw_ptr;
 
   std::vector<std::unique_ptr<Lane>> lanes;
+  // batches and serving: 0 = cohort engine (many queries in one level loop),
+  // 1 = independent single-query runs on the lanes
+  int32_t batch_mode = 0;
+  void* engine = nullptr;   // the cohort engine (engine.hip), created on first use
 
   // timing
   std::atomic<uint32_t> timing{0};   // bit k: timer k is recorded

@@ -32,7 +32,7 @@ def small(raks):
     act = o.activation(g.abar, 0.5)
     qs = synth.make_queries(g, "small")
     exp = [o.query(act, q) for q in qs]
-    c = raks.Context(0, lanes=4)
+    c = raks.Context(0, lanes=4, batch_mode=raks.RAKS_BATCH_LANES)
     c.load_graph(g, alpha=0.5)
     yield c, qs, exp
     c.close()
@@ -98,7 +98,7 @@ def test_medium_batch_on_lanes(raks):
     o = oracle.Oracle(g, check=False)
     act = o.activation(g.abar, 0.5)
     qs = synth.make_queries(g, "medium")[6:12]
-    c = raks.Context(0, lanes=4)
+    c = raks.Context(0, lanes=4, batch_mode=raks.RAKS_BATCH_LANES)
     try:
         c.load_graph(g, alpha=0.5)
         got = c.query_batch(qs)
