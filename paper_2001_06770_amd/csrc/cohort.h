@@ -63,12 +63,19 @@ struct CoSlotMirror {
   uint64_t seq;
 };
 
-struct CoMirror {
+// One level's status.  Level l writes section l & 1: the host reads level l
+// while level l+1 already runs, so a single section could be overwritten
+// before the host saw it.
+struct CoLevelMirror {
   uint32_t W, nq;
   uint32_t pad[2];
   uint64_t seq;
   uint64_t pad2;
   CoSlotMirror slot[kCoSlots];
+};
+
+struct CoMirror {
+  CoLevelMirror lvl[2];
   // outcome of each slot's central-graph stage (recovery overflow bits, nsel)
   int32_t cg_ovf[kCoSlots];
   int32_t cg_nsel[kCoSlots];

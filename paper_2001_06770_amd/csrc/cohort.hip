@@ -438,7 +438,7 @@ __device__ int co_rpg_eval(const CohortView& v, const CoSlot& s, int from, int t
 
 // ------------------------------------------------------------- control ---
 
-__device__ inline void co_publish_slot(CoMirror* mir, int q, const CoSlot& s, uint64_t seq) {
+__device__ inline void co_publish_slot(CoLevelMirror* mir, int q, const CoSlot& s, uint64_t seq) {
   CoSlotMirror m;
   m.active = s.active;
   m.c_run = s.c_run;
@@ -489,10 +489,11 @@ __global__ __launch_bounds__(kCtlT) void k_co_control(CohortView v, int level, u
     if (threadIdx.x < kCoSlots) v.acc->ncand[(level + 1) & 1][threadIdx.x] = 0;
     __syncthreads();
     if (threadIdx.x == 0) {
-      v.mirror->W = tt[1];
-      v.mirror->nq = tt[0];
+      CoLevelMirror* mir = &v.mirror->lvl[level & 1];
+      mir->W = tt[1];
+      mir->nq = tt[0];
       __threadfence_system();
-      *reinterpret_cast<volatile uint64_t*>(&v.mirror->seq) = seq;
+      *reinterpret_cast<volatile uint64_t*>(&mir->seq) = seq;
     }
     return;
   }
@@ -551,7 +552,7 @@ __global__ __launch_bounds__(kCtlT) void k_co_control(CohortView v, int level, u
   // query's slot belongs to its post-processing (other streams) until reuse
   if (threadIdx.x == 0) {
     if (s_live) v.slots[q] = s;
-    co_publish_slot(v.mirror, q, s, seq);
+    co_publish_slot(&v.mirror->lvl[level & 1], q, s, seq);
   }
 }
 

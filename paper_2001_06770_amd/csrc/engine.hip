@@ -442,16 +442,25 @@ int enqueue_level(Engine& E, int level, uint64_t seq) {
   return RAKS_OK;
 }
 
-int wait_level(Engine& E, uint64_t want) {
-  for (uint32_t spin = 1;; ++spin) {
-    bool done = __atomic_load_n(&E.h_mir->seq, __ATOMIC_ACQUIRE) == want;
+// Waits until level `level`'s control launch (number `want`) has published
+// its status in the level's mirror section.  A stream that failed, or that
+// has finished without the status, ends the wait with an error.
+int wait_level(Engine& E, int level, uint64_t want) {
+  const CoLevelMirror* m = &E.h_mir->lvl[level & 1];
+  auto published = [&] {
+    bool done = __atomic_load_n(&m->seq, __ATOMIC_ACQUIRE) == want;
     for (int q = 0; done && q < kCoSlots; ++q)
-      done = __atomic_load_n(&E.h_mir->slot[q].seq, __ATOMIC_ACQUIRE) == want;
-    if (done) return RAKS_OK;
+      done = __atomic_load_n(&m->slot[q].seq, __ATOMIC_ACQUIRE) == want;
+    return done;
+  };
+  for (uint32_t spin = 1;; ++spin) {
+    if (published()) return RAKS_OK;
     if ((spin & 1023u) == 0) {
       const hipError_t e = hipStreamQuery(E.stream);
       if (e != hipSuccess && e != hipErrorNotReady)
         return fail(RAKS_EDEVICE, std::string("cohort stream failed: ") + hipGetErrorString(e));
+      if (e == hipSuccess && !published())
+        return fail(RAKS_EDEVICE, "the cohort level status was not published");
       if (spin >= (1u << 16)) std::this_thread::sleep_for(std::chrono::microseconds(20));
       else std::this_thread::yield();
     } else {
@@ -529,7 +538,7 @@ int process_level(Engine& E, int level) {
   for (int i = 0; i < kCoSlots; ++i) {
     CoQuery* q = E.slot[i];
     if (!q || q->x_done || q->start > level) continue;
-    const CoSlotMirror m = E.h_mir->slot[i];
+    const CoSlotMirror m = E.h_mir->lvl[level & 1].slot[i];
     if (!q->c_done && !m.c_run) {
       q->c_done = true;
       q->c_end = m.c_end;
@@ -722,7 +731,7 @@ int engine_loop(Engine& E) {
       const uint64_t sq = ++E.seq;
       RAKS_TRY(enqueue_level(E, E.level, sq));
       if (have_prev) {
-        RAKS_TRY(wait_level(E, prev_seq));
+        RAKS_TRY(wait_level(E, prev_level, prev_seq));
         RAKS_TRY(process_level(E, prev_level));
       }
       have_prev = true;
@@ -733,7 +742,7 @@ int engine_loop(Engine& E) {
       continue;
     }
     if (have_prev) {
-      RAKS_TRY(wait_level(E, prev_seq));
+      RAKS_TRY(wait_level(E, prev_level, prev_seq));
       RAKS_TRY(process_level(E, prev_level));
       have_prev = false;
       RAKS_TRY(poll_cg(E));
@@ -744,6 +753,12 @@ int engine_loop(Engine& E) {
       const hipError_t e = hipStreamQuery(E.stream);
       if (e != hipSuccess && e != hipErrorNotReady)
         return fail(RAKS_EDEVICE, std::string("cohort stream failed: ") + hipGetErrorString(e));
+      if (e == hipSuccess) {
+        // the stream is idle: every CG stage has published its outcome
+        RAKS_TRY(poll_cg(E));
+        if (cg_outstanding(E)) return fail(RAKS_EDEVICE, "a CG stage outcome was not published");
+        continue;
+      }
       std::this_thread::sleep_for(std::chrono::microseconds(20));
       continue;
     }
