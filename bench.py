@@ -218,6 +218,10 @@ def main():
     lanes = max(1, args.lanes)
     ctx = raks.Context(0, lanes=lanes)
     ctx.load_graph(g, alpha=0.5, mode=mode)
+    from paper_2001_06770_amd import autotune
+    tuned = autotune.load(args.workload)
+    if tuned:
+        ctx.set_tuning(**tuned)
     torch.cuda.synchronize()
     print(f"# graph loaded: {g.n_nodes} nodes, {g.n_arcs} arcs", file=sys.stderr, flush=True)
     legs = {"single": run_single, "batched": run_batched}
@@ -258,7 +262,8 @@ def main():
         "config": {"workload": WORKLOADS[args.workload], "activation": args.mode,
                    "queries_per_step": len(qs), "path": args.path,
                    "queries_used": "all" if not args.queries else f"first {len(qs)}",
-                   "lanes": lanes if args.path == "batched" else 1},
+                   "lanes": lanes if args.path == "batched" else 1,
+                   "cohort_tuning": tuned},
         "qps": nq / dt,
         "p50_ms": percentile(lat, 50),
         "p99_ms": percentile(lat, 99),

@@ -118,6 +118,19 @@ typedef struct {
  * Errors: RAKS_EINVAL (contract), RAKS_ENOMEM, RAKS_EDEVICE. */
 int raks_load_graph(raks_ctx* ctx, const raks_graph_desc* g);
 
+/* Host-only: the activation level (Eqs. 1-3, Section 3.1) of every value in
+ * [lo, hi] into out[0 .. hi-lo].  RAKS_ACT_EDGE: the values are label counts
+ * c (c = |arcs of the source with the label| + |arcs into the destination
+ * with the label|) and [lo, hi] is the range of c over the graph, so the
+ * rescaled weight is (ln c - ln lo) / (ln hi - ln lo); RAKS_ACT_NODE: node
+ * weights, rescaled (w - lo) / (hi - lo).  Reward below alpha, penalty above,
+ * round half up, in IEEE binary64 in the order written; a single-valued range
+ * rescales to 0.  raks_load_graph builds this table once per alpha and the
+ * device only looks levels up, so every arc with the same count gets the same
+ * level.  RAKS_EINVAL for an unknown mode, lo < 1 (EDGE), hi < lo, a range of
+ * 2^28 values or more, a_bar <= 0 or alpha outside (0,1). */
+int raks_level_table(int32_t mode, int64_t lo, int64_t hi, double a_bar, double alpha,
+                     uint8_t* out);
 /* Recomputes the activation levels for a new alpha (users adjust the search
  * granularity with alpha, Section 3.1).  RAKS_ESTATE without a graph. */
 int raks_set_alpha(raks_ctx* ctx, double alpha);
@@ -234,6 +247,23 @@ int raks_query_batch(raks_ctx* ctx, const raks_query_desc* qs, int32_t n, raks_r
 /* Selects how raks_query_batch and serving run queries.  RAKS_EINVAL for an
  * unknown mode, RAKS_ESTATE while serving runs. */
 int raks_set_batch_mode(raks_ctx* ctx, int32_t mode);
+
+/* Tuning of the cohort path (chosen per workload by the package's autotuner).
+ *   expand_wg_per_cu: workgroups per compute unit of the expansion launch
+ *     (0 = 8);
+ *   expand_tile: arcs per tile of the expansion (each tile's entries and
+ *     owner map live in LDS);
+ *   admit_below: a batch admits waiting queries only while at most this many
+ *     queries of the cohort are still exploring (32 admits whenever a query
+ *     fits; 0 admits in waves, so a group starts level-aligned and shares more
+ *     frontier nodes).  Serving always admits as soon as a query fits.
+ * RAKS_EINVAL for values out of range, RAKS_ESTATE while serving runs. */
+typedef struct {
+    int32_t expand_wg_per_cu;
+    int32_t admit_below;
+    int32_t expand_tile;    /* examined arcs per expansion tile: 512, 1024 or 2048 (0 = 1024) */
+} raks_tuning;
+int raks_set_tuning(raks_ctx* ctx, const raks_tuning* t);
 
 /* Serving (continuous batching).  In RAKS_BATCH_COHORT mode one engine thread
  * runs the level loop: a submitted query joins the running cohort at the next

@@ -32,6 +32,11 @@ class CtxOpts(ctypes.Structure):
                 ("big_list", ctypes.c_uint64)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("expand_wg_per_cu", ctypes.c_int32), ("admit_below", ctypes.c_int32),
+                ("expand_tile", ctypes.c_int32)]
+
+
 class ServeOpts(ctypes.Structure):
     _fields_ = [("lanes", ctypes.c_int32), ("queue_cap", ctypes.c_int32)]
 
@@ -120,6 +125,9 @@ def lib():
         L.raks_serve_stop.argtypes = [ctypes.c_void_p]
         L.raks_results_free.restype = None
         L.raks_set_batch_mode.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+        L.raks_set_tuning.argtypes = [ctypes.c_void_p, ctypes.POINTER(Tuning)]
+        L.raks_level_table.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
         L.raks_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
         L.raks_get_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(KernelTiming)]
         L.raks_last_error.restype = ctypes.c_char_p
@@ -132,7 +140,7 @@ EXPORTED = ("raks_create", "raks_destroy", "raks_load_graph", "raks_set_alpha",
             "raks_get_activations", "raks_query", "raks_query_batch", "raks_results_free",
             "raks_serve_start", "raks_submit", "raks_poll", "raks_wait", "raks_serve_stop",
             "raks_set_timing", "raks_get_timing", "raks_last_error", "raks_version",
-            "raks_set_batch_mode")
+            "raks_set_batch_mode", "raks_level_table", "raks_set_tuning")
 RAKS_EAGAIN = -5
 
 
@@ -211,6 +219,11 @@ class Context:
         _check(lib().raks_create(ctypes.byref(self._h), ctypes.byref(opts)))
         if batch_mode != RAKS_BATCH_COHORT:
             self.set_batch_mode(batch_mode)
+
+    def set_tuning(self, expand_wg_per_cu: int = 0, admit_below: int = 32, expand_tile: int = 0):
+        """Cohort path parameters (see raks_set_tuning)."""
+        t = Tuning(int(expand_wg_per_cu), int(admit_below), int(expand_tile))
+        _check(lib().raks_set_tuning(self._h, ctypes.byref(t)))
 
     def set_batch_mode(self, mode: int):
         """RAKS_BATCH_COHORT (queries share level loops) or RAKS_BATCH_LANES."""
@@ -333,6 +346,15 @@ class Context:
         t = KernelTiming()
         _check(lib().raks_get_timing(self._h, kernel, ctypes.byref(t)))
         return {"launches": int(t.launches), "ms": float(t.ms), "bytes": float(t.bytes)}
+
+
+def level_table(mode: int, lo: int, hi: int, abar: float, alpha: float) -> np.ndarray:
+    """Host-built activation levels of the values lo..hi (label counts in EDGE
+    mode, node weights in NODE mode), as the library uses them."""
+    out = np.empty(hi - lo + 1, np.uint8)
+    _check(lib().raks_level_table(int(mode), int(lo), int(hi), float(abar), float(alpha),
+                                  out.ctypes.data))
+    return out
 
 
 def version() -> str:

@@ -118,7 +118,7 @@ DevGraphView graph_view(const Lane* L) { return graph_view(L->ctx, *L->view); }
 void lane_destroy(Ctx* c, Lane* L) {
   if (!L) return;
   if (L->stream) (void)hipStreamSynchronize(L->stream);
-  DevBuf* bufs[] = {&L->Hc, &L->Hm, &L->R, &L->tot, &L->q_off, &L->q_rs,
+  DevBuf* bufs[] = {&L->Hc, &L->Hm, &L->Hq, &L->R, &L->tot, &L->sb, &L->q_off, &L->q_rs,
                     &L->q_lo, &L->q_mask, &L->tile_first, &L->cand, &L->s_item, &L->s_cand, &L->sel_node, &L->sel_sc, &L->sel_sumh,
                     &L->has_rpg, &L->sm, &L->key, &L->dmin, &L->ranked, &L->vc_cnt, &L->vc_tmp,
                     &L->vc_off, &L->vc_nodes, &L->hpool, &L->nl, &L->al, &L->items, &L->sort_a,
@@ -247,6 +247,42 @@ void harvest_timing(Lane* L) {
 
 // -------------------------------------------------------------- graph ---
 
+// Eqs. 1-3 for a rescaled weight x in [0, 1]: reward below alpha, penalty
+// above, round half up (IEEE binary64, operations in the order written).
+int level_of_x(double x, double abar, double alpha) {
+  double v;
+  if (x <= alpha) {
+    const double reward = abar * (alpha - x) / alpha;
+    v = abar - reward;
+  } else {
+    const double penalty = abar * (x - alpha) / (1.0 - alpha);
+    v = abar + penalty;
+  }
+  double r = std::floor(v + 0.5);
+  r = r < 0.0 ? 0.0 : (r > 254.0 ? 254.0 : r);
+  return (int)r;
+}
+
+// Levels of every value in [lo, hi]: label counts c in EDGE mode (the
+// fine-grained weight is ln c, min-max rescaled over the graph's counts), node
+// weights in NODE mode (rescaled directly).  Evaluated once per value on the
+// host, so every arc with the same count gets the same level.
+void level_table(int mode, int64_t lo, int64_t hi, double abar, double alpha, uint8_t* out) {
+  if (mode == RAKS_ACT_EDGE) {
+    const double wmin = std::log((double)lo), wmax = std::log((double)hi);
+    for (int64_t c = lo; c <= hi; ++c) {
+      const double w = std::log((double)c);
+      const double x = (hi == lo) ? 0.0 : (w - wmin) / (wmax - wmin);
+      out[c - lo] = (uint8_t)level_of_x(x, abar, alpha);
+    }
+  } else {
+    for (int64_t wt = lo; wt <= hi; ++wt) {
+      const double x = (hi == lo) ? 0.0 : ((double)wt - (double)lo) / ((double)hi - (double)lo);
+      out[wt - lo] = (uint8_t)level_of_x(x, abar, alpha);
+    }
+  }
+}
+
 // Checks the input contract and computes what every alpha's levels derive
 // from: the label count c of every arc (EDGE) and the range of c or of the
 // node weights (in ctx->wstat).
@@ -269,9 +305,15 @@ int check_graph(Ctx* c, Lane* L) {
              "4 row order, 8 missing reverse arc)", L->h_status->err);
     return fail(RAKS_EINVAL, msg);
   }
-  if (c->mode == RAKS_ACT_NODE) launch_node_weight_range(g, P<uint8_t>(c->nw), st, s);
+  if (c->mode == RAKS_ACT_NODE) {
+    launch_node_weight_range(g, P<uint8_t>(c->nw), st, s);
+    HIP_OK(hipMemcpyAsync(L->h_status, st, sizeof(Status), hipMemcpyDeviceToHost, s));
+  }
   HIP_OK(hipGetLastError());
   HIP_OK(hipStreamSynchronize(s));
+  c->wmin = L->h_status->cmin;
+  c->wmax = L->h_status->cmax;
+  if (c->A == 0 && c->mode == RAKS_ACT_EDGE) c->wmin = c->wmax = 1;
   // levels never exceed Round(2 * a_bar) (x <= 1 in Eqs. 1-3)
   c->nbnd = (int32_t)std::min(16.0, std::floor(2.0 * c->abar + 0.5) + 1.0);
   return RAKS_OK;
@@ -292,13 +334,20 @@ int build_view(Ctx* c, Lane* L, AlphaView& v, double alpha) {
   RAKS_TRY(dev_alloc(c, v.row_amax, n_pad));
   HIP_OK(hipMemsetAsync(v.row_amax.p, 0, n_pad, s));
   RAKS_TRY(dev_alloc(c, v.bnd, (size_t)c->n * c->nbnd * 4));
-  const Status* st = P<Status>(c->wstat);
   DevGraphView g = graph_view(c, v);
+  // the level of every label count (or node weight) of the graph, on the host
+  const uint64_t span = c->wmax - c->wmin + 1;
+  if (span > kMaxLevelTable)
+    return fail(RAKS_EINVAL, "label-count range too large for the level table");
+  std::vector<uint8_t> lut(span);
+  level_table(c->mode, (int64_t)c->wmin, (int64_t)c->wmax, c->abar, alpha, lut.data());
+  RAKS_TRY(dev_alloc(c, c->lut, span));
+  HIP_OK(hipMemcpyAsync(c->lut.p, lut.data(), span, hipMemcpyHostToDevice, s));
   if (c->mode == RAKS_ACT_EDGE)
-    launch_act_edge(g, P<uint32_t>(c->cweight), st, c->abar, alpha, P<uint8_t>(v.act), s);
+    launch_act_edge(g, P<uint32_t>(c->cweight), P<uint8_t>(c->lut), c->wmin, P<uint8_t>(v.act), s);
   else
-    launch_act_node(g, P<uint8_t>(c->nw), st, c->abar, alpha, P<uint8_t>(v.act_node),
-                    P<uint8_t>(v.act), s);
+    launch_act_node(g, P<uint8_t>(c->nw), P<uint8_t>(c->lut), (uint32_t)c->wmin,
+                    P<uint8_t>(v.act_node), P<uint8_t>(v.act), s);
   launch_sort_rows(g, P<int32_t>(v.col_s), P<uint8_t>(v.act_s), P<uint32_t>(v.eid_s),
                    P<uint8_t>(v.row_amax), P<uint32_t>(v.bnd), c->nbnd, s);
   HIP_OK(hipGetLastError());
@@ -439,6 +488,7 @@ int ensure_node_buffers(Lane* L) {
   const size_t np = (size_t)L->n_pad;
   RAKS_TRY(dev_alloc(c, L->R, np * 2));
   RAKS_TRY(dev_alloc(c, L->tot, (size_t)L->nblocks * sizeof(ScanTot)));
+  RAKS_TRY(dev_alloc(c, L->sb, (size_t)2 * kSupers * 3 * 4));
   RAKS_TRY(dev_alloc(c, L->q_off, (np + 1) * 4));
   RAKS_TRY(dev_alloc(c, L->q_rs, np * 4));
   RAKS_TRY(dev_alloc(c, L->q_lo, np * 4));
@@ -475,6 +525,7 @@ RunView run_view(Lane* L, int kind, int T, DevBuf& H, const QueryPlan& p) {
   r.n_pad = L->n_pad;
   r.st = &P<Status>(L->status)->run[kind];
   r.tot = P<ScanTot>(L->tot);
+  r.sb = P<uint32_t>(L->sb);
   r.nblocks = L->nblocks;
   r.cpw = L->cpw;
   r.s_item = P<uint4>(L->s_item);
@@ -598,6 +649,9 @@ int run_levels(Lane* L, RunView& r, int TP, const std::vector<int32_t>& kws, int
       }
     }
     if (rs.end_level != INT32_MAX || level >= r.max_level) {
+      // the launches queued past the run's end return at once: not timed
+      for (auto& pe : L->pending)
+        if (pe.kind == 0 && pe.run == r.kind && pe.level > level) pe.kind = -1;
       *last = rs;
       break;
     }
@@ -1354,7 +1408,7 @@ int raks_destroy(raks_ctx* c) {
   drop_views(c);
   free_view(c, c->base);
   DevBuf* bufs[] = {&c->row_ptr, &c->col, &c->label, &c->nw, &c->kw_nodes, &c->arc_src,
-                    &c->rev, &c->cweight, &c->wstat};
+                    &c->rev, &c->cweight, &c->wstat, &c->lut};
   for (DevBuf* b : bufs) dev_free(c, *b);
   delete c;
   return RAKS_OK;
@@ -1593,6 +1647,30 @@ int raks_wait(raks_ctx* c, uint64_t ticket, raks_results** out) {
 int raks_serve_stop(raks_ctx* c) {
   if (!c) return fail(RAKS_EINVAL, "ctx is NULL");
   stop_serving(c);
+  return RAKS_OK;
+}
+
+int raks_level_table(int32_t mode, int64_t lo, int64_t hi, double a_bar, double alpha,
+                     uint8_t* out) {
+  if (mode != RAKS_ACT_EDGE && mode != RAKS_ACT_NODE) return fail(RAKS_EINVAL, "unknown mode");
+  if (!out || hi < lo || (mode == RAKS_ACT_EDGE && lo < 1) ||
+      (uint64_t)(hi - lo) >= kMaxLevelTable)
+    return fail(RAKS_EINVAL, "bad value range");
+  if (!(alpha > 0.0 && alpha < 1.0) || !(a_bar > 0.0)) return fail(RAKS_EINVAL, "bad a_bar or alpha");
+  level_table(mode, lo, hi, a_bar, alpha, out);
+  return RAKS_OK;
+}
+
+int raks_set_tuning(raks_ctx* c, const raks_tuning* t) {
+  if (!c || !t) return fail(RAKS_EINVAL, "NULL argument");
+  if (t->expand_wg_per_cu < 0 || t->expand_wg_per_cu > 64 || t->admit_below < 0 ||
+      (t->expand_tile != 0 && t->expand_tile != 512 && t->expand_tile != 1024 &&
+       t->expand_tile != 2048))
+    return fail(RAKS_EINVAL, "tuning values out of range");
+  if (c->serve.running) return fail(RAKS_ESTATE, "serving is running");
+  c->co_wpc = t->expand_wg_per_cu ? t->expand_wg_per_cu : 8;
+  c->co_admit_below = t->admit_below;
+  c->co_tile = t->expand_tile ? t->expand_tile : 1024;
   return RAKS_OK;
 }
 

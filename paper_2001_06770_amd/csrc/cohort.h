@@ -103,6 +103,8 @@ struct CohortView {
   int32_t n, n_pad;
   int32_t nblocks, cpw;          // scan workgroups and 1024-node chunks per workgroup
   uint8_t* H;                    // [kCoSegs][n_pad][16]
+  unsigned long long* R;         // [n_pad] reached mask: bit c set iff column c expands and
+                                 // its hitting level is finite at the start of the level
   CoSlot* slots;                 // [kCoSlots]
   CoAcc* acc;
   uint2* tot;                    // [nblocks] per scan workgroup: entries, examined arcs
@@ -124,12 +126,16 @@ struct CoCandView {
   RunStatus* st;                 // receives ncand_total / ncand_level for the selection
 };
 
-// Work counters of both runs of one slot from the final hitting levels.
-struct CoCountView {
-  const uint8_t* Hs;             // segment base + c0 (stride 16)
-  int32_t C, M, m_block;
+// End of a query's exploration: the work counters of both runs from its
+// final hitting levels, its columns copied out to its lane (rows of 16 bytes:
+// its levels first, then INF) and reset to INF in the cohort matrix.
+struct CoFinishView {
+  uint8_t* seg;                  // the query's segment [n_pad][16]
+  int32_t c0, C, M, m_block;
+  int32_t n_pad;
   const CoSlot* slot;            // end levels
   Status* gst;                   // the lane's status: run[0], run[1] counters
+  uint8_t* Hq;                   // the lane's copy [n_pad][16]
 };
 
 void launch_co_init(const CohortView& v, hipStream_t s);
@@ -139,7 +145,8 @@ void launch_co_seed(const CohortView& v, int seg, int c0, const int32_t* kw_node
                     const SeedList& seeds, hipStream_t s);
 void launch_co_scan(const CohortView& v, const DevGraphView& g, int level, hipStream_t s);
 void launch_co_control(const CohortView& v, int level, uint64_t seq, hipStream_t s);
-void launch_co_expand(const CohortView& v, const DevGraphView& g, int level, int grid,
+// tile: examined arcs per expansion tile (512, 1024 or 2048)
+void launch_co_expand(const CohortView& v, const DevGraphView& g, int level, int grid, int tile,
                       hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // CG selection input of slot q (three launches), then the selection kernel
 void launch_co_cand(const CoCandView& cv, const CohortView& v, hipStream_t s);
@@ -148,8 +155,6 @@ void launch_co_cg_done(const CohortView& v, int q, const Status* gst, uint64_t s
                        hipStream_t s);
 // Final marginal decision (Theorem 4 replayed up to the exploration's end)
 void launch_co_rpg_final(const CohortView& v, int q, hipStream_t s);
-void launch_co_counters(const CoCountView& cv, const DevGraphView& g, hipStream_t s);
-// Resets columns [c0, c0 + T) of a segment to INF for every node
-void launch_co_clear(const CohortView& v, int seg, int c0, int T, hipStream_t s);
+void launch_co_finish(const CoFinishView& fv, const DevGraphView& g, hipStream_t s);
 
 }  // namespace raks

@@ -63,19 +63,6 @@ __device__ inline RowMasks row_masks(const uint4 row, const uint32_t (&lvw)[4]) 
   return m;
 }
 
-// Exact INF (0xFF) bytes of a 16-byte row as a 16-bit mask.
-__device__ inline uint32_t inf_mask(const uint4 row) {
-  const uint32_t w[4] = {row.x, row.y, row.z, row.w};
-  uint32_t m = 0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const uint32_t x = ~w[k];
-    const uint32_t y = (x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
-    m |= msb4(~(y | x | 0x7F7F7F7Fu)) << (4 * k);
-  }
-  return m;
-}
-
 // Arcs of row v with level <= x, given its degree d and largest level.
 __device__ inline uint32_t cnt_le(const DevGraphView& g, int32_t v, int x, uint32_t rs,
                                   uint32_t d, uint32_t amax) {
@@ -102,6 +89,7 @@ struct CoCfg {
   int32_t first[kCoSegs + 1];      // slots of segment s: sl[first[s] .. first[s+1])
   SlotCfg sl[kCoSlots];
   uint32_t lvw[kCoSegs][4];        // per-column local level (127 where no run expands)
+  unsigned long long run;          // columns of running runs
 };
 
 // The fields of a slot that the level kernels use.
@@ -156,6 +144,10 @@ __device__ void build_cfg(const SlotLite* lite, int level, CoCfg& cfg) {
   for (int i = 0; i < nt; ++i) cfg.sl[pos[tmp[i].seg]++] = tmp[i];
   cfg.nslot = nt;
   cfg.seg_mask = segm;
+  unsigned long long run = 0;
+  for (int i = 0; i < nt; ++i)
+    run |= (unsigned long long)(tmp[i].gc | tmp[i].gm) << (16 * tmp[i].seg);
+  cfg.run = run;
   for (int s = 0; s < kCoSegs; ++s)
     for (int k = 0; k < 4; ++k)
       cfg.lvw[s][k] = (uint32_t)lv[s * 16 + 4 * k] | ((uint32_t)lv[s * 16 + 4 * k + 1] << 8) |
@@ -189,6 +181,9 @@ __global__ __launch_bounds__(kBlock) void k_co_init(CohortView v) {
   const uint4 inf = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < words; i += (size_t)gridDim.x * kBlock)
     h[i] = inf;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < (size_t)v.n_pad;
+       i += (size_t)gridDim.x * kBlock)
+    v.R[i] = 0;
   if (blockIdx.x == 0) {
     for (int i = threadIdx.x; i < kCoSlots; i += kBlock) v.slots[i] = CoSlot{};
     if (threadIdx.x == 0) *v.acc = CoAcc{};
@@ -224,12 +219,6 @@ __global__ __launch_bounds__(kBlock) void k_co_seed(uint8_t* Hs, const int32_t* 
   }
 }
 
-// Byte stores only: the cohort's other queries write the same rows meanwhile.
-__global__ __launch_bounds__(kBlock) void k_co_clear(uint8_t* Hs, int32_t n_pad, int32_t T) {
-  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n_pad; v += (int64_t)gridDim.x * kBlock)
-    for (int j = 0; j < T; ++j) Hs[v * 16 + j] = kInf;
-}
-
 // --------------------------------------------------------- frontier scan ---
 //
 // Node v is in run g's level-l frontier (l the query's local level) exactly
@@ -263,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_co_scan(CohortView v, DevGraphView g
     for (int64_t b0 = wg0; b0 < wg1; b0 += kBlock) {
       const int64_t vv = b0 + threadIdx.x;
       const int32_t node = (int32_t)vv;
-      unsigned long long en = 0, eo = 0;
+      unsigned long long en = 0, eo = 0, rfin = 0;
       int hi_lv = -1, lo_lv = INT_MAX;
       uint32_t amax = 0;
       if (vv < v.n) {
@@ -274,6 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_co_scan(CohortView v, DevGraphView g
           const uint4 row = reinterpret_cast<const uint4*>(seg_base(v, s))[vv];
           if ((row.x & row.y & row.z & row.w) == 0xFFFFFFFFu) continue;
           const RowMasks m = row_masks(row, cfg.lvw[s]);
+          rfin |= (unsigned long long)m.fin << (16 * s);
           for (int i = cfg.first[s]; i < cfg.first[s + 1]; ++i) {
             const SlotCfg sc = cfg.sl[i];
 #pragma unroll
@@ -295,6 +285,11 @@ __global__ __launch_bounds__(kBlock) void k_co_scan(CohortView v, DevGraphView g
             }
           }
         }
+      }
+      if (vv < v.n) {
+        // the reached mask of the running columns, as the expansion reads it
+        const unsigned long long rnew = rfin & cfg.run;
+        if (v.R[vv] != rnew) v.R[vv] = rnew;
       }
       CoEntry e = {};
       uint32_t work = 0;
@@ -567,14 +562,15 @@ __global__ __launch_bounds__(kCtlT) void k_co_control(CohortView v, int level, u
 // still INF at n gets its query's level + 1.  Writes need no atomics: every
 // write of a level stores the same value into a byte that was INF (Theorem
 // "lockfree").
+template <int TILE>
 __global__ __launch_bounds__(kBlock) void k_co_expand(CohortView v, DevGraphView g, int level) {
   __shared__ unsigned long long s_ge[256], s_eq[256];
   __shared__ uint8_t s_lv1[kCoCols];
   __shared__ uint8_t s_lvc[kCoCols];
   __shared__ unsigned long long s_run;
-  __shared__ uint32_t s_base[kExpandTile];
-  __shared__ unsigned long long s_nm[kExpandTile], s_om[kExpandTile];
-  __shared__ uint16_t s_own[kExpandTile];
+  __shared__ uint32_t s_base[TILE];
+  __shared__ unsigned long long s_nm[TILE], s_om[TILE];
+  __shared__ uint16_t s_own[TILE];
   __shared__ uint32_t s_scan[kBlock / kWave + 1];
   __shared__ int32_t s_e[4];
   __shared__ SlotLite s_lite[kCoSlots];
@@ -614,13 +610,13 @@ __global__ __launch_bounds__(kBlock) void k_co_expand(CohortView v, DevGraphView
   }
   __syncthreads();
   if (s_run == 0) return;
-  constexpr int IPT = kExpandTile / kBlock;
+  constexpr int IPT = TILE / kBlock;
   const int nb = v.nblocks;
   const int64_t per_wg = (int64_t)v.cpw * kScanNodes;
-  const uint32_t ntiles = (W + kExpandTile - 1) / kExpandTile;
+  const uint32_t ntiles = (W + TILE - 1) / TILE;
   for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const uint32_t w0 = tile * kExpandTile;
-    const uint32_t w1 = min(W, w0 + (uint32_t)kExpandTile);
+    const uint32_t w0 = tile * TILE;
+    const uint32_t w1 = min(W, w0 + (uint32_t)TILE);
     if (wave_id() == 0) {
       // entries holding the tile's first and last arcs (global entry numbers)
 #pragma unroll 1
@@ -633,7 +629,7 @@ __global__ __launch_bounds__(kBlock) void k_co_expand(CohortView v, DevGraphView
         if (lane_id() == 0) { s_e[2 * k] = (int)(v.qpre[b] + j); s_e[2 * k + 1] = b; }
       }
     }
-    for (int i = threadIdx.x; i < kExpandTile; i += kBlock) s_own[i] = 0;
+    for (int i = threadIdx.x; i < TILE; i += kBlock) s_own[i] = 0;
     __syncthreads();
     const int E0 = s_e[0], bA = s_e[1], E1 = s_e[2], bB = s_e[3];
     const int cnt = E1 - E0 + 1;
@@ -673,17 +669,12 @@ __global__ __launch_bounds__(kBlock) void k_co_expand(CohortView v, DevGraphView
       const unsigned long long want = (s_nm[j] & s_ge[a]) | (s_om[j] & s_eq[a]);
       if (!want) continue;
       const int32_t nb2 = g.col_s[e];
-#pragma unroll
-      for (int sg = 0; sg < kCoSegs; ++sg) {
-        const uint32_t ws = (uint32_t)(want >> (16 * sg)) & 0xFFFFu;
-        if (!ws) continue;
-        uint8_t* row = seg_base(v, sg) + (size_t)nb2 * 16;
-        uint32_t mm = inf_mask(*reinterpret_cast<const uint4*>(row)) & ws;
-        while (mm) {
-          const int t = __ffs(mm) - 1;
-          mm &= mm - 1;
-          row[t] = s_lv1[sg * 16 + t];
-        }
+      // columns that have not reached nb2 (as of the start of the level)
+      unsigned long long mm = ~v.R[nb2] & want;
+      while (mm) {
+        const int c = __ffsll(mm) - 1;
+        mm &= mm - 1;
+        seg_base(v, c >> 4)[(size_t)nb2 * 16 + (c & 15)] = s_lv1[c];
       }
     }
     __syncthreads();
@@ -892,29 +883,49 @@ __device__ inline void run_counts(const uint8_t* h, int T, int L, bool blk, cons
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_co_counters(CoCountView cv, DevGraphView g) {
+// One pass over the query's rows: counters, copy-out and reset.  Runs on the
+// cohort stream between levels, so whole rows are rewritten safely.
+__global__ __launch_bounds__(kBlock) void k_co_finish(CoFinishView fv, DevGraphView g) {
   __shared__ uint64_t s_multi[(kBlock / kWave + 1) * 10];
-  const CoSlot s = *cv.slot;
+  const CoSlot s = *fv.slot;
   const int Lc = s.c_end, Lm = s.m_end;
+  const int T = fv.C + fv.M;
+  const uint32_t qmask = ((1u << T) - 1u) << fv.c0;
   uint64_t acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < g.n;
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < fv.n_pad;
        v += (int64_t)gridDim.x * kBlock) {
-    const uint8_t* r = cv.Hs + v * 16;
-    const uint32_t rs = g.row_ptr[v], d = g.row_ptr[v + 1] - rs, amax = g.row_amax[v];
-    RunCnt a = {0, 0, 0, 0, 0};
-    run_counts(r, cv.C, Lc, true, g, (int32_t)v, rs, d, amax, a);
-    acc[0] += a.fr; acc[1] += a.ea; acc[2] += a.eg; acc[3] += a.gp; acc[4] += a.hw;
-    if (Lm >= 0) {
-      RunCnt b = {0, 0, 0, 0, 0};
-      run_counts(r + cv.C, cv.M, Lm, cv.m_block != 0, g, (int32_t)v, rs, d, amax, b);
-      acc[5] += b.fr; acc[6] += b.ea; acc[7] += b.eg; acc[8] += b.gp; acc[9] += b.hw;
+    uint4* rowp = reinterpret_cast<uint4*>(fv.seg) + v;
+    const uint4 row = *rowp;
+    uint8_t b[16], out[16], keep[16];
+    __builtin_memcpy(b, &row, 16);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      out[j] = kInf;
+      keep[j] = ((qmask >> j) & 1u) ? kInf : b[j];
     }
+    for (int j = 0; j < T; ++j) out[j] = b[fv.c0 + j];
+    if (v < g.n && ((row.x & row.y & row.z & row.w) != 0xFFFFFFFFu)) {
+      const uint32_t rs = g.row_ptr[v], d = g.row_ptr[v + 1] - rs, amax = g.row_amax[v];
+      RunCnt a = {0, 0, 0, 0, 0};
+      run_counts(out, fv.C, Lc, true, g, (int32_t)v, rs, d, amax, a);
+      acc[0] += a.fr; acc[1] += a.ea; acc[2] += a.eg; acc[3] += a.gp; acc[4] += a.hw;
+      if (Lm >= 0) {
+        RunCnt c = {0, 0, 0, 0, 0};
+        run_counts(out + fv.C, fv.M, Lm, fv.m_block != 0, g, (int32_t)v, rs, d, amax, c);
+        acc[5] += c.fr; acc[6] += c.ea; acc[7] += c.eg; acc[8] += c.gp; acc[9] += c.hw;
+      }
+    }
+    uint4 o, k;
+    __builtin_memcpy(&o, out, 16);
+    __builtin_memcpy(&k, keep, 16);
+    reinterpret_cast<uint4*>(fv.Hq)[v] = o;
+    *rowp = k;
   }
   uint64_t tot[10];
   block_exclusive_scan_multi<10, kBlock>(acc, tot, s_multi);
   if (threadIdx.x < 10 && tot[threadIdx.x]) {
     const int k = threadIdx.x;
-    RunStatus& rs = cv.gst->run[k / 5];
+    RunStatus& rs = fv.gst->run[k / 5];
     unsigned long long* dst = nullptr;
     switch (k % 5) {
       case 0: dst = reinterpret_cast<unsigned long long*>(&rs.frontier_sum); break;
@@ -964,12 +975,21 @@ void launch_co_control(const CohortView& v, int level, uint64_t seq, hipStream_t
   k_co_control<<<1 + kCoSlots, kCtlT, 0, s>>>(v, level, seq);
 }
 
-void launch_co_expand(const CohortView& v, const DevGraphView& g, int level, int grid,
-                      hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+template <int TILE>
+void co_expand_at(const CohortView& v, const DevGraphView& g, int level, int grid, hipStream_t s,
+                  hipEvent_t ev0, hipEvent_t ev1) {
   if (ev0 && ev1)
-    hipExtLaunchKernelGGL(k_co_expand, dim3(grid), dim3(kBlock), 0, s, ev0, ev1, 0, v, g, level);
+    hipExtLaunchKernelGGL(k_co_expand<TILE>, dim3(grid), dim3(kBlock), 0, s, ev0, ev1, 0, v, g,
+                          level);
   else
-    k_co_expand<<<grid, kBlock, 0, s>>>(v, g, level);
+    k_co_expand<TILE><<<grid, kBlock, 0, s>>>(v, g, level);
+}
+
+void launch_co_expand(const CohortView& v, const DevGraphView& g, int level, int grid, int tile,
+                      hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  if (tile == 512) co_expand_at<512>(v, g, level, grid, s, ev0, ev1);
+  else if (tile == 2048) co_expand_at<2048>(v, g, level, grid, s, ev0, ev1);
+  else co_expand_at<1024>(v, g, level, grid, s, ev0, ev1);
 }
 
 void launch_co_cand(const CoCandView& cv, const CohortView& v, hipStream_t s) {
@@ -987,15 +1007,10 @@ void launch_co_rpg_final(const CohortView& v, int q, hipStream_t s) {
   k_co_rpg_final<<<1, kCtlT, 0, s>>>(v, q);
 }
 
-void launch_co_counters(const CoCountView& cv, const DevGraphView& g, hipStream_t s) {
-  k_co_post_init<<<1, 1, 0, s>>>(cv.slot, cv.gst);
-  const unsigned grid = (unsigned)std::min<int64_t>(4096, ((int64_t)g.n + kBlock - 1) / kBlock);
-  k_co_counters<<<std::max(1u, grid), kBlock, 0, s>>>(cv, g);
-}
-
-void launch_co_clear(const CohortView& v, int seg, int c0, int T, hipStream_t s) {
-  const unsigned g = (unsigned)std::min<int64_t>(8192, ((int64_t)v.n_pad + kBlock - 1) / kBlock);
-  k_co_clear<<<g, kBlock, 0, s>>>(v.H + (size_t)seg * v.n_pad * 16 + c0, v.n_pad, T);
+void launch_co_finish(const CoFinishView& fv, const DevGraphView& g, hipStream_t s) {
+  k_co_post_init<<<1, 1, 0, s>>>(fv.slot, fv.gst);
+  const unsigned grid = (unsigned)std::min<int64_t>(8192, ((int64_t)fv.n_pad + kBlock - 1) / kBlock);
+  k_co_finish<<<std::max(1u, grid), kBlock, 0, s>>>(fv, g);
 }
 
 }  // namespace raks

@@ -13,6 +13,8 @@ constexpr int kBlock = 256;        // threads per workgroup for most kernels
 constexpr int kScanPer = 4;        // nodes per frontier-scan thread
 constexpr int kScanNodes = 1024;   // nodes per frontier-scan chunk (kBlock * kScanPer)
 constexpr int kScanGroups = 2048;  // at most this many frontier-scan workgroups
+constexpr int kSuper = 64;         // scan workgroups per superblock of the enqueue prefix
+constexpr int kSupers = kScanGroups / kSuper;
 constexpr int kExpandTile = 1024;  // arcs per expansion tile
 constexpr int kMaxKw = 16;         // keywords per run
 constexpr int kMaxW = 256;         // beam width limit

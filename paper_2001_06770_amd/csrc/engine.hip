@@ -78,7 +78,7 @@ struct Engine {
   Ctx* c = nullptr;
   hipStream_t stream = nullptr;
   CohortView v = {};
-  DevBuf H, slots, acc, tot, wpre, qpre, wtot, stage, cand, ccnt, coff, ccur, cst;
+  DevBuf H, R, slots, acc, tot, wpre, qpre, wtot, stage, cand, ccnt, coff, ccur, cst;
   CoMirror* h_mir = nullptr;
   CoMirror* d_mir = nullptr;
   uint64_t seq = 0, cg_no = 0;
@@ -106,6 +106,7 @@ struct Engine {
   int fail_rc = RAKS_OK;
   std::function<void(CoQuery*)> on_done;
   std::thread serve_thr;
+  bool batch = false;   // admission follows the batch policy (waves)
 };
 
 namespace {
@@ -117,6 +118,7 @@ int engine_alloc(Engine& E) {
   const int32_t cpw = (chunks + kScanGroups - 1) / kScanGroups;
   const int32_t nb = (chunks + cpw - 1) / cpw;
   RAKS_TRY(dev_alloc(c, E.H, (size_t)kCoSegs * n_pad * 16));
+  RAKS_TRY(dev_alloc(c, E.R, (size_t)n_pad * 8));
   RAKS_TRY(dev_alloc(c, E.slots, sizeof(CoSlot) * kCoSlots));
   RAKS_TRY(dev_alloc(c, E.acc, sizeof(CoAcc)));
   RAKS_TRY(dev_alloc(c, E.tot, (size_t)nb * sizeof(uint2)));
@@ -145,6 +147,7 @@ int engine_alloc(Engine& E) {
   v.nblocks = nb;
   v.cpw = cpw;
   v.H = P<uint8_t>(E.H);
+  v.R = P<unsigned long long>(E.R);
   v.slots = P<CoSlot>(E.slots);
   v.acc = P<CoAcc>(E.acc);
   v.tot = P<uint2>(E.tot);
@@ -170,7 +173,7 @@ int engine_create(Ctx* c, Engine** out) {
   }
   const int rc = engine_alloc(*E);
   if (rc) {
-    for (DevBuf* b : {&E->H, &E->slots, &E->acc, &E->tot, &E->wpre, &E->qpre, &E->wtot, &E->stage,
+    for (DevBuf* b : {&E->H, &E->R, &E->slots, &E->acc, &E->tot, &E->wpre, &E->qpre, &E->wtot, &E->stage,
                       &E->cand, &E->ccnt, &E->coff, &E->ccur, &E->cst})
       dev_free(c, *b);
     if (E->h_mir) (void)hipHostFree(E->h_mir);
@@ -272,6 +275,12 @@ struct Borrow {
   ~Borrow() { L->stream = saved; }
 };
 
+int explorers(const Engine& E) {
+  int k = 0;
+  for (int i = 0; i < kCoSlots; ++i) k += E.slot[i] && !E.slot[i]->x_done;
+  return k;
+}
+
 bool slots_busy(const Engine& E) {
   for (int i = 0; i < kCoSlots; ++i)
     if (E.slot[i]) return true;
@@ -310,6 +319,7 @@ int admit(Engine& E) {
       E.cv.notify_all();
       continue;
     }
+    if (E.batch && explorers(E) > c->co_admit_below) break;
     int qs = -1;
     for (int i = 0; i < kCoSlots; ++i)
       if (!E.slot[i]) { qs = i; break; }
@@ -324,6 +334,7 @@ int admit(Engine& E) {
     {
       Borrow b(L, E.stream);
       rc = ensure_small_buffers(L);
+      if (!rc) rc = dev_alloc(c, L->Hq, (size_t)E.v.n_pad * 16);
       if (!rc) {
         phase_reset(c, L->ph[0], q->p.w, q->p.C);
         phase_reset(c, L->ph[1], q->p.n_build, q->p.M);
@@ -433,10 +444,10 @@ int enqueue_level(Engine& E, int level, uint64_t seq) {
   timed(2, [&] { launch_co_control(E.v, level, seq, s); });
   if (tm & 1u) {
     hipEvent_t a = timing_event(E), b = timing_event(E);
-    launch_co_expand(E.v, g, level, c->num_cu * 8, s, a, b);
+    launch_co_expand(E.v, g, level, c->num_cu * c->co_wpc, c->co_tile, s, a, b);
     if (a && b) E.timed.push_back({a, b, 0, 0.0, level});
   } else {
-    launch_co_expand(E.v, g, level, c->num_cu * 8, s);
+    launch_co_expand(E.v, g, level, c->num_cu * c->co_wpc, c->co_tile, s);
   }
   HIP_OK(hipGetLastError());
   return RAKS_OK;
@@ -535,6 +546,13 @@ int redo_cg(Engine& E, CoQuery* q, int ovf, int nsel) {
 }
 
 int process_level(Engine& E, int level) {
+  {
+    // algorithmic bytes of the level's expansion: per examined arc its
+    // neighbour id, its level and the neighbour's reached mask; per entry 24
+    const CoLevelMirror& lm = E.h_mir->lvl[level & 1];
+    for (auto& t : E.timed)
+      if (t.kind == 0 && t.level == level) t.bytes = (4.0 + 1.0 + 8.0) * lm.W + 24.0 * lm.nq;
+  }
   for (int i = 0; i < kCoSlots; ++i) {
     CoQuery* q = E.slot[i];
     if (!q || q->x_done || q->start > level) continue;
@@ -565,9 +583,27 @@ int poll_cg(Engine& E) {
   for (int i = 0; i < kCoSlots; ++i) {
     CoQuery* q = E.slot[i];
     if (!q || q->handed || !q->x_done || !q->cg_ok) continue;
+    // the final marginal decision, the counters, and the query's levels moved
+    // to its lane; slot and columns are free for the next level
+    launch_co_rpg_final(E.v, q->slot, E.stream);
+    CoFinishView fv;
+    fv.seg = E.v.H + (size_t)q->seg * E.v.n_pad * 16;
+    fv.c0 = q->c0;
+    fv.C = q->p.C;
+    fv.M = q->p.M;
+    fv.m_block = q->p.M >= 2 ? 1 : 0;
+    fv.n_pad = E.v.n_pad;
+    fv.slot = E.v.slots + q->slot;
+    fv.gst = P<Status>(q->L->status);
+    fv.Hq = P<uint8_t>(q->L->Hq);
+    launch_co_finish(fv, graph_view(E.c, E.c->base), E.stream);
+    HIP_OK(hipGetLastError());
     q->ready = take_event(E);
     if (!q->ready) return fail(RAKS_EDEVICE, "event creation failed");
     HIP_OK(hipEventRecord(q->ready, E.stream));
+    E.used[q->seg] &= (uint16_t)~(((1u << q->T) - 1u) << q->c0);
+    E.slot[i] = nullptr;
+    q->slot = -1;
     q->handed = true;
     {
       std::lock_guard<std::mutex> lk(E.mu);
@@ -604,23 +640,13 @@ void take_releases(Engine& E) {
 // ------------------------------------------------------------- post ---
 
 int post_output(Engine& E, CoQuery* q, raks_results** out) {
-  Ctx* c = E.c;
   Lane* L = q->L;
   hipStream_t s = L->stream;
   Status* st = P<Status>(L->status);
   const QueryPlan& p = q->p;
-  const uint8_t* Hc = seg_ptr(E, q->seg, q->c0);
+  const uint8_t* Hc = P<uint8_t>(L->Hq);
   const uint8_t* Hm = Hc + p.C;
   HIP_OK(hipStreamWaitEvent(s, q->ready, 0));
-  launch_co_rpg_final(E.v, q->slot, s);
-  CoCountView ccv;
-  ccv.Hs = Hc;
-  ccv.C = p.C;
-  ccv.M = p.M;
-  ccv.m_block = p.M >= 2 ? 1 : 0;
-  ccv.slot = E.v.slots + q->slot;
-  ccv.gst = st;
-  launch_co_counters(ccv, graph_view(c, c->base), s);
   launch_rank(rank_view(L, p), s);
   auto stage_out = [&]() -> int {
     if (p.M > 0) launch_recover(recover_view(L, 1, Hm, 16, &st->nres, q->m_bound), s);
@@ -671,12 +697,6 @@ void post_worker(Engine* E) {
       rc = query_on_lane(q->L, &q->desc, &res);
     } else {
       rc = post_output(*E, q, &res);
-      if (rc == RAKS_OK) {
-        // the query's columns back to INF before they are reused
-        launch_co_clear(E->v, q->seg, q->c0, q->T, q->L->stream);
-        const hipError_t e = hipStreamSynchronize(q->L->stream);
-        if (e != hipSuccess) rc = fail(RAKS_EDEVICE, std::string("clear: ") + hipGetErrorString(e));
-      }
     }
     if (rc != RAKS_OK) {
       raks_results_free(res);
@@ -806,7 +826,7 @@ void cohort_destroy(Ctx* c) {
   }
   stop_workers(*E);
   (void)hipStreamSynchronize(E->stream);
-  for (DevBuf* b : {&E->H, &E->slots, &E->acc, &E->tot, &E->wpre, &E->qpre, &E->wtot, &E->stage,
+  for (DevBuf* b : {&E->H, &E->R, &E->slots, &E->acc, &E->tot, &E->wpre, &E->qpre, &E->wtot, &E->stage,
                     &E->cand, &E->ccnt, &E->coff, &E->ccur, &E->cst})
     dev_free(c, *b);
   for (hipEvent_t e : E->ev_pool) (void)hipEventDestroy(e);
@@ -845,7 +865,9 @@ int cohort_query_batch(Ctx* c, const raks_query_desc* qs, int32_t n, raks_result
     }
   }
   start_workers(*E);
+  E->batch = true;
   rc = engine_loop(*E);
+  E->batch = false;
   if (rc) {
     // stop: queries not finished are abandoned with the batch
     std::lock_guard<std::mutex> lk(E->mu);

@@ -92,7 +92,8 @@ __device__ inline void load_row(const uint8_t* H, int64_t v, uint8_t (&b)[TP]) {
 
 // A run with a keyword that has no node ends before level 0; the marginal
 // run does not run at all when the central run selected no CG.
-__global__ void k_run_reset(RunStatus* st, int32_t empty, const int32_t* nsel) {
+__global__ void k_run_reset(RunStatus* st, int32_t empty, const int32_t* nsel, uint32_t* sb) {
+  for (int i = 0; i < 2 * kSupers * 3; ++i) sb[i] = 0;
   RunStatus s = {};
   const bool skip = nsel != nullptr && *nsel == 0;
   s.end_level = (skip || empty) ? -1 : INT32_MAX;
@@ -340,6 +341,12 @@ __global__ __launch_bounds__(kBlock) void k_front_count(RunView r, DevGraphView 
     t.degk = t5[3];
     t.gate = t5[4];
     r.tot[blockIdx.x] = t;
+    // superblock sums, so that every copying workgroup of the enqueue finds
+    // its offsets with at most kSupers + kSuper loads
+    uint32_t* sb = r.sb + ((level & 1) * kSupers + blockIdx.x / kSuper) * 3;
+    if (t.nq) atomicAdd(&sb[0], t.nq);
+    if (t.work) atomicAdd(&sb[1], t.work);
+    if (t.ncand) atomicAdd(&sb[2], t.ncand);
   }
 }
 
@@ -502,6 +509,9 @@ __device__ void control_level(const RunView& r, int level, RunStatus* mirror, ui
     cur.cand_base[(level + 1) & 1] = cur.cand_base[level & 1] + tnc;
     s_nrpg = cur.nrpg;
   }
+  // the next level's superblock sums start from zero (this level's are read
+  // by the copying workgroups of this launch)
+  if (threadIdx.x < kSupers * 3) r.sb[((level + 1) & 1) * kSupers * 3 + threadIdx.x] = 0;
   __syncthreads();
   if (s_end == END_NONE && r.kind == RUN_MARGINAL) {
     if (rpg_identify<TP>(r, &s_nrpg, level) && threadIdx.x == 0) s_end = END_STOP;
@@ -547,10 +557,16 @@ __global__ __launch_bounds__(kCtl) void k_front_enqueue(RunView r, int level, Ru
   const ScanTot t = r.tot[b];
   if (t.nq == 0 && t.ncand == 0) return;
   __shared__ uint32_t s_m32[(kCtl / kWave + 1) * 3];
+  // offsets: the superblocks before b's, then the scan workgroups of b's
+  // superblock before b (one load per thread)
   uint32_t v[3] = {0, 0, 0}, tot[3];
-  for (int i = threadIdx.x; i < b; i += kCtl) {
-    const ScanTot x = r.tot[i];
-    v[0] += x.nq; v[1] += x.work; v[2] += x.ncand;
+  const int sup = b / kSuper, first = sup * kSuper;
+  const uint32_t* sb = r.sb + (level & 1) * kSupers * 3;
+  if ((int)threadIdx.x < sup) {
+    v[0] = sb[threadIdx.x * 3]; v[1] = sb[threadIdx.x * 3 + 1]; v[2] = sb[threadIdx.x * 3 + 2];
+  } else if ((int)threadIdx.x >= kSupers && (int)threadIdx.x - kSupers < b - first) {
+    const ScanTot x = r.tot[first + threadIdx.x - kSupers];
+    v[0] = x.nq; v[1] = x.work; v[2] = x.ncand;
   }
   block_exclusive_scan_multi<3, kCtl, uint32_t>(v, tot, s_m32);
   const uint32_t oq = tot[0], ow = tot[1];
@@ -829,7 +845,7 @@ void launch_run_init(const RunView& r, int TP, int32_t n, const int32_t* kw_node
                      const SeedList& seeds, hipStream_t s) {
   int empty = 0;
   for (int i = 0; i < seeds.T; ++i) empty |= seeds.count[i] == 0;
-  k_run_reset<<<1, 1, 0, s>>>(r.st, empty, r.kind == RUN_MARGINAL ? r.nsel : nullptr);
+  k_run_reset<<<1, 1, 0, s>>>(r.st, empty, r.kind == RUN_MARGINAL ? r.nsel : nullptr, r.sb);
   const unsigned g = (unsigned)std::min<int64_t>(8192, (r.n_pad + kBlock - 1) / kBlock);
   RAKS_TP_DISPATCH(TP, k_init_rows<kTP><<<g, kBlock, 0, s>>>(
                            r.H, reinterpret_cast<RMaskT<kTP>*>(r.R), n, r.n_pad, r.T));

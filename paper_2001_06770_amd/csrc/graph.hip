@@ -71,31 +71,14 @@ __global__ __launch_bounds__(kBlock) void k_check_and_count(const uint32_t* row_
   }
 }
 
-// Eqs. 1-3: reward below alpha, penalty above, round half up.
-__device__ inline uint8_t coarsen(double x, double abar, double alpha) {
-  double v;
-  if (x <= alpha) {
-    const double reward = abar * (alpha - x) / alpha;
-    v = abar - reward;
-  } else {
-    const double penalty = abar * (x - alpha) / (1.0 - alpha);
-    v = abar + penalty;
-  }
-  double r = floor(v + 0.5);
-  r = r < 0.0 ? 0.0 : (r > 254.0 ? 254.0 : r);
-  return (uint8_t)r;
-}
-
+// Activation level of every arc: a lookup of its label count c in the table
+// of levels the host built for c in [cmin, cmax] (Eqs. 1-3 evaluated once per
+// count, on the host).
 __global__ __launch_bounds__(kBlock) void k_act_edge(const uint32_t* c, uint32_t A,
-                                                     const Status* st, double abar,
-                                                     double alpha, uint8_t* act) {
-  const uint64_t cmin = st->cmin, cmax = st->cmax;
-  const double lmin = log((double)cmin), lmax = log((double)cmax);
-  for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < A; e += gridDim.x * kBlock) {
-    const double lc = log((double)c[e]);
-    const double x = (cmax == cmin) ? 0.0 : (lc - lmin) / (lmax - lmin);
-    act[e] = coarsen(x, abar, alpha);
-  }
+                                                     const uint8_t* lut, uint64_t cmin,
+                                                     uint8_t* act) {
+  for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < A; e += gridDim.x * kBlock)
+    act[e] = lut[c[e] - cmin];
 }
 
 __global__ __launch_bounds__(kBlock) void k_node_weight_range(const uint8_t* nw, int32_t n,
@@ -116,14 +99,13 @@ __global__ __launch_bounds__(kBlock) void k_node_weight_range(const uint8_t* nw,
   }
 }
 
+// NODE mode: the level of every node from the host's table over the node
+// weights in [wmin, wmax].
 __global__ __launch_bounds__(kBlock) void k_act_node(const uint8_t* nw, int32_t n,
-                                                     const Status* st, double abar,
-                                                     double alpha, uint8_t* act_node) {
-  const double mn = (double)st->cmin, mx = (double)st->cmax;
-  for (int32_t v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
-    const double x = (st->cmax == st->cmin) ? 0.0 : ((double)nw[v] - mn) / (mx - mn);
-    act_node[v] = coarsen(x, abar, alpha);
-  }
+                                                     const uint8_t* lut, uint32_t wmin,
+                                                     uint8_t* act_node) {
+  for (int32_t v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock)
+    act_node[v] = lut[nw[v] - wmin];
 }
 
 __global__ __launch_bounds__(kBlock) void k_act_gather(const uint8_t* act_node,
@@ -215,9 +197,9 @@ void launch_check_and_count(const DevGraphView& g, uint32_t* c_tmp, int32_t* arc
                                                         arc_src, rev, st);
 }
 
-void launch_act_edge(const DevGraphView& g, const uint32_t* c_tmp, const Status* st, double abar,
-                     double alpha, uint8_t* act, hipStream_t s) {
-  if (g.A > 0) k_act_edge<<<grid_for(g.A), kBlock, 0, s>>>(c_tmp, g.A, st, abar, alpha, act);
+void launch_act_edge(const DevGraphView& g, const uint32_t* c_tmp, const uint8_t* lut,
+                     uint64_t cmin, uint8_t* act, hipStream_t s) {
+  if (g.A > 0) k_act_edge<<<grid_for(g.A), kBlock, 0, s>>>(c_tmp, g.A, lut, cmin, act);
 }
 
 void launch_node_weight_range(const DevGraphView& g, const uint8_t* nw, Status* st,
@@ -226,9 +208,9 @@ void launch_node_weight_range(const DevGraphView& g, const uint8_t* nw, Status* 
   k_node_weight_range<<<grid_for(g.n), kBlock, 0, s>>>(nw, g.n, st);
 }
 
-void launch_act_node(const DevGraphView& g, const uint8_t* nw, const Status* st, double abar,
-                     double alpha, uint8_t* act_node, uint8_t* act, hipStream_t s) {
-  k_act_node<<<grid_for(g.n), kBlock, 0, s>>>(nw, g.n, st, abar, alpha, act_node);
+void launch_act_node(const DevGraphView& g, const uint8_t* nw, const uint8_t* lut, uint32_t wmin,
+                     uint8_t* act_node, uint8_t* act, hipStream_t s) {
+  k_act_node<<<grid_for(g.n), kBlock, 0, s>>>(nw, g.n, lut, wmin, act_node);
   if (g.A > 0) k_act_gather<<<grid_for(g.A), kBlock, 0, s>>>(act_node, g.col, g.A, act);
 }
 

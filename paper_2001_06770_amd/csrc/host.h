@@ -45,6 +45,11 @@ struct QueryPlan {
 };
 
 int validate_query(Ctx* c, const raks_query_desc* q, QueryPlan& p);
+
+// activation levels (Eqs. 1-3) of every value in [lo, hi], built on the host
+constexpr uint64_t kMaxLevelTable = 1ull << 28;
+int level_of_x(double x, double abar, double alpha);
+void level_table(int mode, int64_t lo, int64_t hi, double abar, double alpha, uint8_t* out);
 SeedList seeds_for(Ctx* c, const std::vector<int32_t>& kws);
 int ensure_small_buffers(Lane* L);
 int query_on_lane(Lane* L, const raks_query_desc* q, raks_results** out);

@@ -54,6 +54,8 @@ struct RunView {
   int32_t n_pad;         // n rounded up to kScanNodes
   RunStatus* st;
   ScanTot* tot;          // [nblocks]
+  uint32_t* sb;          // [2][kScanGroups / 64][3] sums of nq, work, ncand per 64 scan
+                         // workgroups, double-buffered by level parity
   int32_t nblocks;       // frontier-scan workgroups
   int32_t cpw;           // kScanNodes-chunks per scan workgroup
   uint4* s_item;         // [n_pad] staged queue entries (local arc prefix, rs, lo, mask)
@@ -228,15 +230,17 @@ void launch_pack_vc(const uint32_t* vc_cnt, const int32_t* vc_tmp, const uint64_
 void launch_check_and_count(const DevGraphView& g, uint32_t* c_tmp, int32_t* arc_src, uint32_t* rev,
                             Status* st,
                             hipStream_t s);
-void launch_act_edge(const DevGraphView& g, const uint32_t* c_tmp, const Status* st, double abar,
-                     double alpha, uint8_t* act, hipStream_t s);
+// act[e] = lut[c[e] - cmin] (lut: levels of the label counts, built on the host)
+void launch_act_edge(const DevGraphView& g, const uint32_t* c_tmp, const uint8_t* lut,
+                     uint64_t cmin, uint8_t* act, hipStream_t s);
 void launch_sort_rows(const DevGraphView& g, int32_t* col_s, uint8_t* act_s, uint32_t* eid_s,
                       uint8_t* row_amax, uint32_t* bnd, int32_t nbnd, hipStream_t s);
 // node weight range into st->cmin / st->cmax (NODE mode, once per graph)
 void launch_node_weight_range(const DevGraphView& g, const uint8_t* nw, Status* st,
                               hipStream_t s);
-void launch_act_node(const DevGraphView& g, const uint8_t* nw, const Status* st, double abar,
-                     double alpha, uint8_t* act_node, uint8_t* act, hipStream_t s);
+// act_node[v] = lut[nw[v] - wmin]; act[e] = act_node[col[e]]
+void launch_act_node(const DevGraphView& g, const uint8_t* nw, const uint8_t* lut, uint32_t wmin,
+                     uint8_t* act_node, uint8_t* act, hipStream_t s);
 
 void launch_run_init(const RunView& r, int TP, int32_t n, const int32_t* kw_nodes,
                      const SeedList& seeds, hipStream_t s);

@@ -83,13 +83,14 @@ struct Lane {
   bool own_stream = false;
 
   int32_t n_pad = 0, nblocks = 0, cpw = 1;
-  DevBuf Hc, Hm, R, tot, q_off, q_rs, q_lo, q_mask, tile_first, cand, s_item, s_cand;
+  DevBuf Hc, Hm, R, tot, sb, q_off, q_rs, q_lo, q_mask, tile_first, cand, s_item, s_cand;
   DevBuf sel_node, sel_sc, sel_sumh, has_rpg, sm, key, dmin, ranked;
   DevBuf vc_cnt, vc_tmp, vc_off, vc_nodes;
   // recovery storage, shared by both phases (sized for the larger one)
   DevBuf hpool, nl, al, items, sort_a, sort_b;
   DevBuf cg_nodes, cg_arcs, cg_cnt;   // CG lists, kept for the marginal phase
   DevBuf hdr, out_nodes, out_arcs, status;
+  DevBuf Hq;                          // cohort path: the query's hitting levels, [n_pad][16]
   DevBuf bigf, big_bm, big_chunk, big_slot;   // bitmap path of large results
   RecPhase ph[2];                     // [0] CG recovery, [1] RPG recovery + output
   Status* h_status = nullptr;   // pinned
@@ -163,6 +164,8 @@ struct Ctx {
   DevBuf rev;            // CSR position of every arc's reverse arc
   DevBuf cweight;        // EDGE: label count c of every arc, kept for other alphas
   DevBuf wstat;          // Status holding the c (or node weight) range of the graph
+  uint64_t wmin = 0, wmax = 0;   // the same range on the host
+  DevBuf lut;            // levels of every c (or node weight) in the range, for one alpha
   int32_t nbnd = 1;
   AlphaView base;        // levels for the context's alpha
   std::vector<std::unique_ptr<AlphaView>> views;   // other alphas, least recently used evicted
@@ -175,6 +178,9 @@ struct Ctx {
   // 1 = independent single-query runs on the lanes
   int32_t batch_mode = 0;
   void* engine = nullptr;   // the cohort engine (engine.hip), created on first use
+  // cohort tuning: expansion workgroups per CU; a batch admits new queries
+  // only while at most admit_below queries of the cohort are exploring
+  int32_t co_wpc = 8, co_admit_below = 32, co_tile = 1024;
 
   // timing
   std::atomic<uint32_t> timing{0};   // bit k: timer k is recorded

@@ -9,7 +9,12 @@ the node list (int32 little-endian) and of the arc list ((src, dst, label)
 int32 triples), so the GPU tests can check full-size outputs without running
 the reference at those sizes during the test.
 
-usage: python tests/golden/make_golden.py large [n_queries]
+usage: python tests/golden/make_golden.py large [n_queries] [--shard K/N PART_FILE]
+       python tests/golden/make_golden.py merge large PART_FILE...
+
+With --shard, only every N-th sampled query starting at K is run and the
+entries go to PART_FILE; merge combines the parts of all N shards into
+tests/golden/<workload>_queries.json (the same file one unsharded run writes).
 """
 from __future__ import annotations
 
@@ -44,9 +49,41 @@ def summarize(res: dict) -> dict:
             "results": [digest(r) for r in res["results"]]}
 
 
+def write(name, out):
+    path = os.path.join(HERE, f"{name}_queries.json")
+    with open(path + ".tmp", "w") as f:
+        json.dump(out, f, indent=1)
+    os.replace(path + ".tmp", path)
+    return path
+
+
+def merge(name, parts):
+    out = None
+    entries = []
+    for p in parts:
+        with open(p) as f:
+            d = json.load(f)
+        if out is None:
+            out = {k: v for k, v in d.items() if k != "queries"}
+        assert all(d[k] == out[k] for k in out), "parts of different runs"
+        entries += d["queries"]
+    entries.sort(key=lambda e: e["index"])
+    assert len({e["index"] for e in entries}) == len(entries)
+    out["queries"] = entries
+    print(f"wrote {write(name, out)} ({len(entries)} queries)")
+
+
 def main():
+    if sys.argv[1] == "merge":
+        merge(sys.argv[2], sys.argv[3:])
+        return
     name = sys.argv[1]
-    count = int(sys.argv[2]) if len(sys.argv) > 2 else 8
+    count = int(sys.argv[2]) if len(sys.argv) > 2 and not sys.argv[2].startswith("--") else 8
+    shard, part = None, None
+    if "--shard" in sys.argv:
+        i = sys.argv.index("--shard")
+        k, n = (int(x) for x in sys.argv[i + 1].split("/"))
+        shard, part = (k, n), sys.argv[i + 2]
     t0 = time.time()
     g = synth.make_graph(name)
     print(f"graph {name}: {g.n_nodes} nodes {g.n_arcs} arcs abar {g.abar} "
@@ -58,6 +95,8 @@ def main():
     qs = synth.make_queries(g, name)
     stride = max(1, len(qs) // count)
     picked = list(range(0, len(qs), stride))[:count]
+    if shard:
+        picked = picked[shard[0]::shard[1]]
     out = {"workload": name, "alpha": 0.5, "abar_x100": g.abar_x100, "n_arcs": g.n_arcs,
            "act_sha256": act_sha, "queries": []}
     for i in picked:
@@ -71,11 +110,12 @@ def main():
         print(f"query {i}: {len(res['results'])} results, e_arc "
               f"{res['stats'][0]['e_arc'] + res['stats'][1]['e_arc']} ({time.time() - t1:.1f} s)",
               flush=True)
-    path = os.path.join(HERE, f"{name}_queries.json")
-    with open(path + ".tmp", "w") as f:
-        json.dump(out, f, indent=1)
-    os.replace(path + ".tmp", path)
-    print(f"wrote {path} ({time.time() - t0:.0f} s total)")
+    if part:
+        with open(part, "w") as f:
+            json.dump(out, f)
+        print(f"wrote {part}")
+    else:
+        print(f"wrote {write(name, out)} ({time.time() - t0:.0f} s total)")
 
 
 if __name__ == "__main__":

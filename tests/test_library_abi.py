@@ -61,7 +61,7 @@ LAYOUT_STRUCTS = {
     "raks_ctx_opts": "CtxOpts", "raks_serve_opts": "ServeOpts", "raks_graph_desc": "GraphDesc",
     "raks_query_desc": "QueryDesc", "raks_arc": "Arc", "raks_result": "Result",
     "raks_query_stats": "QueryStats", "raks_results": "Results",
-    "raks_kernel_timing": "KernelTiming",
+    "raks_kernel_timing": "KernelTiming", "raks_tuning": "Tuning",
 }
 
 
