@@ -21,8 +21,8 @@ _LIB = os.path.join(_HERE, "libraks_cpu.so")
 def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp,
-                               os.path.join(_HERE, "raks_cpu.c")])
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+                               "-o", tmp, os.path.join(_HERE, "raks_cpu.c"), "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -50,6 +50,11 @@ def _lib():
                                ctypes.c_int, ctypes.POINTER(ctypes.POINTER(ctypes.c_int64)),
                                ctypes.POINTER(ctypes.c_int64)]
     lib.rcpu_free.argtypes = [ctypes.c_void_p]
+    lib.rcpu_activation.argtypes = [ctypes.POINTER(_Graph), ctypes.c_void_p, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    lib.rcpu_explore.argtypes = [ctypes.POINTER(_Graph), ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int,
+                                 ctypes.c_void_p]
     return lib
 
 
@@ -89,8 +94,34 @@ class CpuRaks:
                       np.ascontiguousarray(g.label, np.uint16), np.ascontiguousarray(g.kw_ptr, np.int64),
                       np.ascontiguousarray(g.kw_nodes, np.int32)]
         rp, col, lab, kp, kn = self._arrs
+        self._nw = np.ascontiguousarray(g.node_weight, np.uint8)
         self._g = _Graph(int(g.n_nodes), int(col.shape[0]), rp.ctypes.data, col.ctypes.data,
                          lab.ctypes.data, int(kp.shape[0] - 1), kp.ctypes.data, kn.ctypes.data)
+
+    def activation(self, abar: float, alpha: float, mode: int = 0, threads: int = 0):
+        """Per-arc activation levels (uint8 [A]) computed by this variant on
+        ``threads`` host threads (0 = all); mode 0 per arc, 1 per node."""
+        act = np.empty(self._arrs[1].shape[0], np.uint8)
+        rc = _lib().rcpu_activation(ctypes.byref(self._g), self._nw.ctypes.data, float(abar),
+                                    float(alpha), int(mode), int(threads), act.ctypes.data)
+        if rc != 0:
+            raise ValueError(f"activation failed ({rc})")
+        return act
+
+    def explore(self, act, keywords, block: bool = False, max_level: int = 20,
+                threads: int = 0) -> dict:
+        """Exploration alone (Algorithm 1) from the keywords' node sets; its counters."""
+        act = np.ascontiguousarray(act, np.uint8)
+        kws = np.ascontiguousarray(keywords, np.int32)
+        out = np.zeros(7, np.int64)
+        rc = _lib().rcpu_explore(ctypes.byref(self._g), act.ctypes.data, kws.ctypes.data,
+                                 int(kws.shape[0]), int(bool(block)), int(max_level), int(threads),
+                                 out.ctypes.data)
+        if rc != 0:
+            raise ValueError(f"exploration failed ({rc})")
+        d = {k: int(v) for k, v in zip(_STATS, out)}
+        d["end"] = _END.get(d["end_reason"], "?")
+        return d
 
     def query(self, act, q, threads: int = 0) -> dict:
         act = np.ascontiguousarray(act, np.uint8)

@@ -10,12 +10,15 @@
  * and work counters equal the reference's on every query (the writes of one
  * level all store the same value, Theorem "lockfree"; a compare-and-swap on
  * the H byte makes the count of written entries exact).  Activation levels
- * are an input (as for the reference's query entry point).
+ * are an input of the query entry point; rcpu_activation computes them with
+ * OpenMP (its own code: label runs counted per row, the destination's count
+ * by a search of its row, Eqs. 1-3 once per distinct count).
  *
  * Output: the same int64 words as the reference implementation (status,
  * result count, CG count, two blocks of run counters, then per result:
  * central node, S^c, S^m, key, arc-level sum, nodes, arcs as triples).
  */
+#include <math.h>
 #include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -188,6 +191,122 @@ static void run_expand(run_t* r, int l, int use_cf) {
     r->c.e_alg += e_alg;
     r->c.gate += gate;
     r->c.hw += hw;
+}
+
+/* --------------------------------------------- activation (Eqs. 1-3) --- */
+
+/* Level of a rescaled weight x in [0,1]: reward below alpha, penalty above,
+ * rounded half up; IEEE binary64 in the order the equations are written. */
+static int level_x(double x, double abar, double alpha) {
+    double v;
+    if (x <= alpha) v = abar - abar * (alpha - x) / alpha;
+    else v = abar + abar * (x - alpha) / (1.0 - alpha);
+    double r = floor(v + 0.5);
+    if (r < 0.0) r = 0.0;
+    if (r > 254.0) r = 254.0;
+    return (int)r;
+}
+
+/* Arcs of row v with label lab (rows sorted by label, then destination). */
+static int64_t label_run(const rcpu_graph* g, int32_t v, uint16_t lab) {
+    int64_t lo = g->row_ptr[v], hi = g->row_ptr[v + 1];
+    int64_t a = lo, b = hi;
+    while (a < b) { const int64_t m = a + (b - a) / 2; if (g->label[m] < lab) a = m + 1; else b = m; }
+    int64_t c = a, d = hi;
+    while (c < d) { const int64_t m = c + (d - c) / 2; if (g->label[m] <= lab) c = m + 1; else d = m; }
+    return c - a;
+}
+
+/* Per-arc levels act[A].  mode 0 (per arc): c = |arcs of the source with the
+ * label| + |arcs of the destination with the label| (the in-arcs of the
+ * destination are the reverses of its out-arcs), weight ln c min-max
+ * rescaled; mode 1 (per node): the destination's node weight min-max
+ * rescaled.  Returns 0, or -1 for bad arguments / -2 when memory runs out. */
+int rcpu_activation(const rcpu_graph* g, const uint8_t* node_weight, double abar, double alpha,
+                    int mode, int threads, uint8_t* act) {
+    if (!(alpha > 0.0 && alpha < 1.0) || !(abar > 0.0)) return -1;
+    if (threads > 0) omp_set_num_threads(threads);
+    const int64_t A = g->A;
+    if (mode == 1) {
+        int wmin = 255, wmax = 0;
+        for (int32_t v = 0; v < g->n; ++v) {
+            if (node_weight[v] < wmin) wmin = node_weight[v];
+            if (node_weight[v] > wmax) wmax = node_weight[v];
+        }
+        uint8_t lut[256];
+        for (int w = wmin; w <= wmax; ++w) {
+            const double x = (wmax == wmin) ? 0.0 : ((double)w - (double)wmin) / ((double)wmax - (double)wmin);
+            lut[w] = (uint8_t)level_x(x, abar, alpha);
+        }
+#pragma omp parallel for schedule(static)
+        for (int64_t e = 0; e < A; ++e) act[e] = lut[node_weight[g->col[e]]];
+        return 0;
+    }
+    if (mode != 0) return -1;
+    int64_t* c = (int64_t*)malloc(sizeof(int64_t) * (size_t)(A > 0 ? A : 1));
+    if (!c) return -2;
+    /* label runs of each row, then the destination's count of the same label */
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int32_t v = 0; v < g->n; ++v) {
+        for (int64_t s = g->row_ptr[v]; s < g->row_ptr[v + 1];) {
+            int64_t t = s + 1;
+            while (t < g->row_ptr[v + 1] && g->label[t] == g->label[s]) ++t;
+            for (int64_t e = s; e < t; ++e) c[e] = t - s;
+            s = t;
+        }
+    }
+    int64_t cmin = INT64_MAX, cmax = 0;
+#pragma omp parallel for schedule(static) reduction(min : cmin) reduction(max : cmax)
+    for (int64_t e = 0; e < A; ++e) {
+        c[e] += label_run(g, g->col[e], g->label[e]);
+        if (c[e] < cmin) cmin = c[e];
+        if (c[e] > cmax) cmax = c[e];
+    }
+    if (A == 0) { free(c); return 0; }
+    const int64_t span = cmax - cmin + 1;
+    uint8_t* lut = (uint8_t*)malloc((size_t)span);
+    if (!lut) { free(c); return -2; }
+    const double wmin = log((double)cmin), wmax = log((double)cmax);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < span; ++k) {
+        const double w = log((double)(cmin + k));
+        const double x = (cmax == cmin) ? 0.0 : (w - wmin) / (wmax - wmin);
+        lut[k] = (uint8_t)level_x(x, abar, alpha);
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < A; ++e) act[e] = lut[c[e] - cmin];
+    free(lut);
+    free(c);
+    return 0;
+}
+
+/* Exploration alone (Algorithm 1, Sections 4.2.2-4.2.4) from the keywords'
+ * node sets until the frontier is empty or the level bound: with `block`, a
+ * node reached by every keyword stops expanding.  counters: levels, end
+ * reason, frontier sum, e_arc, e_alg, gate passes, entries written. */
+int rcpu_explore(const rcpu_graph* g, const uint8_t* act, const int32_t* kws, int32_t T,
+                 int32_t block, int32_t max_level, int threads, int64_t* counters) {
+    if (T < 1) return -1;
+    if (threads > 0) omp_set_num_threads(threads);
+    run_t x;
+    if (run_init(&x, g, act, kws, T)) { run_free(&x); return -1; }
+    for (int l = 0;; ++l) {
+        run_enqueue(&x);
+        x.c.levels = l + 1;
+        if (x.nq == 0) { x.c.end = E_EXHAUSTED; break; }
+        if (block) {
+#pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < x.nq; ++i)
+                if (!x.CF[x.Q[i]] && complete(&x, x.Q[i])) x.CF[x.Q[i]] = 1;
+        }
+        if (l == max_level) { x.c.end = E_BOUND; break; }
+        run_expand(&x, l, block);
+    }
+    const counters_t k = x.c;
+    counters[0] = k.levels; counters[1] = k.end; counters[2] = k.frontier; counters[3] = k.e_arc;
+    counters[4] = k.e_alg; counters[5] = k.gate; counters[6] = k.hw;
+    run_free(&x);
+    return 0;
 }
 
 /* ----------------------------------------------------------- recovery --- */

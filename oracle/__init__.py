@@ -149,8 +149,10 @@ class Oracle:
             raise ValueError(f"explore failed ({rc})")
         return H, _stats_dict([getattr(st, f) for f, _ in _Stats._fields_])
 
-    def query(self, act, q, flags: int = 0, shuffle: int = 0) -> dict:
-        """Both runs, recovery and ranking for one radial pattern query."""
+    def query(self, act, q, flags: int = 0, shuffle: int = 0, lean: bool = False) -> dict:
+        """Both runs, recovery and ranking for one radial pattern query.  With
+        ``lean`` the node and arc lists come back as int32 numpy arrays (for
+        results of hundreds of millions of arcs)."""
         act = np.ascontiguousarray(act, np.uint8)
         c = np.ascontiguousarray(q.central, np.int32)
         m = np.ascontiguousarray(q.marginal if len(q.marginal) else [0], np.int32)
@@ -167,7 +169,28 @@ class Oracle:
             words = np.ctypeslib.as_array(buf, shape=(ln.value,)).copy()
         finally:
             _lib().orc_free(buf)
-        return parse(words)
+        return parse_lean(words) if lean else parse(words)
+
+
+def parse_lean(words: np.ndarray) -> dict:
+    """As parse, with each result's node list as an int32 array and its arc
+    list as an int32 array of (src, dst, label) rows."""
+    head = [int(x) for x in words[:17]]
+    out = {"status": head[0], "n_cg": head[2],
+           "stats": [_stats_dict(head[3:10]), _stats_dict(head[10:17])], "results": []}
+    p = 17
+    for _ in range(head[1]):
+        central, sc, sm, key, wsum, nn = (int(x) for x in words[p:p + 6])
+        p += 6
+        nodes = words[p:p + nn].astype(np.int32)
+        p += nn
+        na = int(words[p])
+        p += 1
+        arcs = words[p:p + 3 * na].astype(np.int32).reshape(-1, 3)
+        p += 3 * na
+        out["results"].append({"central": central, "score_c": sc, "score_m": sm, "key": key,
+                               "weight_sum": wsum, "nodes": nodes, "arcs": arcs})
+    return out
 
 
 def parse(words: np.ndarray) -> dict:

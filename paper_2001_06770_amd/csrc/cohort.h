@@ -113,6 +113,8 @@ struct CohortView {
   uint32_t* wtot;                // [2] arcs and entries of the level
   CoEntry* stage;                // [n_pad] entries, in each scan workgroup's node range
   CoMirror* mirror;              // device address of the pinned mirror
+  uint32_t* dmin;                // [kCoSlots][kMaxW][kMaxKw] running minima of the marginal
+                                 // levels over each CG's V_C (the RPG check's D_j)
 };
 
 // Candidate keys of one slot's central run (CG selection after the run).
@@ -155,6 +157,9 @@ void launch_co_cg_done(const CohortView& v, int q, const Status* gst, uint64_t s
                        hipStream_t s);
 // Final marginal decision (Theorem 4 replayed up to the exploration's end)
 void launch_co_rpg_final(const CohortView& v, int q, hipStream_t s);
+// D_j minima over V_C for every slot whose marginal run is checked (q < 0), or
+// for slot q alone; many workgroups, before the control step reads them
+void launch_co_dmin(const CohortView& v, int q, int grid, hipStream_t s);
 void launch_co_finish(const CoFinishView& fv, const DevGraphView& g, hipStream_t s);
 
 }  // namespace raks

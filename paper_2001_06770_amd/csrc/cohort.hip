@@ -338,33 +338,27 @@ __global__ __launch_bounds__(kBlock) void k_co_scan(CohortView v, DevGraphView g
 // checked level by level from `from` on.  Returns the first level where a
 // rule holds, or -1.  The CGs with an RPG at that level (or at `to`) are
 // written back with S^m, key and D_j.  One workgroup of kCtlT threads.
-__device__ int co_rpg_eval(const CohortView& v, const CoSlot& s, int from, int to) {
+__device__ int co_rpg_eval(const CohortView& v, int q, const CoSlot& s, int from, int to) {
   __shared__ uint32_t s_dm[kMaxW * kMaxKw];
   __shared__ int32_t s_lvl[kMaxW], s_sc[kMaxW], s_old[kMaxW];
   __shared__ int64_t s_key[kMaxW];
-  __shared__ uint32_t s_vc[kMaxW + 1];
   __shared__ int32_t s_stop, s_n, s_kth, s_minsc;
   const int nsel = s.nsel, M = s.M;
   const int64_t gn = s.gn, gd = s.gd;
-  const uint8_t* Hm = seg_base(v, s.seg) + s.c0 + s.C;
   for (int i = threadIdx.x; i < nsel * kMaxKw; i += kCtlT) s_dm[i] = kInf;
   for (int i = threadIdx.x; i < nsel; i += kCtlT) {
     s_old[i] = s.has_rpg[i];
     s_lvl[i] = s_old[i] ? s.sm[i] : INT_MAX;
     s_sc[i] = s.sel_sc[i];
   }
-  for (int i = threadIdx.x; i <= nsel; i += kCtlT) s_vc[i] = s.vc_off[i];
   if (threadIdx.x == 0) s_stop = -1;
   __syncthreads();
-  const uint32_t total = s_vc[nsel];
-  for (uint32_t p = threadIdx.x; p < total; p += kCtlT) {
-    const int rr = upper_index<uint32_t>(s_vc, 0, nsel + 1, p);
-    if (s_old[rr]) continue;
-    const uint8_t* row = Hm + (size_t)s.vc_nodes[p] * 16;
-    for (int j = 0; j < M; ++j) {
-      const uint32_t h = row[j];
-      if (h <= (uint32_t)to) atomicMin(&s_dm[rr * kMaxKw + j], h);
-    }
+  // D_j: the running minima that k_co_dmin keeps (every level written so far
+  // is <= to)
+  const uint32_t* gdm = v.dmin + (size_t)q * kMaxW * kMaxKw;
+  for (int i = threadIdx.x; i < nsel * kMaxKw; i += kCtlT) {
+    const uint32_t h = gdm[i];
+    if (!s_old[i / kMaxKw] && h <= (uint32_t)to) s_dm[i] = h;
   }
   __syncthreads();
   for (int rr = threadIdx.x; rr < nsel; rr += kCtlT) {
@@ -532,7 +526,7 @@ __global__ __launch_bounds__(kCtlT) void k_co_control(CohortView v, int level, u
   __syncthreads();
   if (s_go) {
     const int l = level - s.start;
-    const int stop = co_rpg_eval(v, s, s.checked + 1, l);
+    const int stop = co_rpg_eval(v, q, s, s.checked + 1, l);
     if (threadIdx.x == 0) {
       s.checked = l;
       if (stop >= 0) {
@@ -770,17 +764,51 @@ __global__ __launch_bounds__(kBlock) void k_co_cand_write(CoCandView cv, int32_t
   }
 }
 
-__global__ void k_co_cg_done(CohortView v, int q, const Status* gst, uint64_t seq) {
+__global__ __launch_bounds__(kBlock) void k_co_cg_done(CohortView v, int q, const Status* gst,
+                                                       uint64_t seq) {
   const int32_t ovf = gst->overflow & (1 | kOvfBig0);
   const int32_t nsel = gst->nsel;
-  if (!ovf) {
-    v.slots[q].nsel = nsel;
-    v.slots[q].vc_ready = 1;
+  // the D_j minima of the new V_C lists start at INF
+  uint32_t* dm = v.dmin + (size_t)q * kMaxW * kMaxKw;
+  for (int i = threadIdx.x; i < kMaxW * kMaxKw; i += kBlock) dm[i] = kInf;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (!ovf) {
+      v.slots[q].nsel = nsel;
+      v.slots[q].vc_ready = 1;
+    }
+    v.mirror->cg_ovf[q] = ovf;
+    v.mirror->cg_nsel[q] = nsel;
+    __threadfence_system();
+    *reinterpret_cast<volatile uint64_t*>(&v.mirror->cg_seq[q]) = seq;
   }
-  v.mirror->cg_ovf[q] = ovf;
-  v.mirror->cg_nsel[q] = nsel;
-  __threadfence_system();
-  *reinterpret_cast<volatile uint64_t*>(&v.mirror->cg_seq[q]) = seq;
+}
+
+// D_j = min over a CG's V_C nodes of its marginal level j (Definition 3),
+// kept as running minima: levels never change once written, so a rescan
+// only lowers them.  Grid-stride over the V_C entries of every slot whose
+// marginal run is checked at this level (or of slot `only`), skipping CGs
+// that already have their RPG.
+__global__ __launch_bounds__(kBlock) void k_co_dmin(CohortView v, int only) {
+  for (int q = 0; q < kCoSlots; ++q) {
+    if (only >= 0 && q != only) continue;
+    const CoSlot& s = v.slots[q];
+    if (!s.active || !s.vc_ready || s.M == 0 || s.nsel == 0) continue;
+    if (only < 0 && !s.m_run) continue;
+    const int nsel = s.nsel, M = s.M;
+    const uint32_t total = s.vc_off[nsel];
+    const uint8_t* Hm = seg_base(v, s.seg) + s.c0 + s.C;
+    uint32_t* dm = v.dmin + (size_t)q * kMaxW * kMaxKw;
+    for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < total; p += gridDim.x * kBlock) {
+      const int rr = upper_index<uint32_t>(s.vc_off, 0, nsel + 1, p);
+      if (s.has_rpg[rr]) continue;
+      const uint8_t* row = Hm + (size_t)s.vc_nodes[p] * 16;
+      for (int j = 0; j < M; ++j) {
+        const uint32_t h = row[j];
+        if (h != kInf && h < dm[rr * kMaxKw + j]) atomicMin(&dm[rr * kMaxKw + j], h);
+      }
+    }
+  }
 }
 
 // ------------------------------------------------- after the exploration ---
@@ -804,7 +832,7 @@ __global__ __launch_bounds__(kCtlT) void k_co_rpg_final(CohortView v, int q) {
   __syncthreads();
   if (s_go) {
     const int to = s.m_xreason == END_EXHAUSTED ? s.m_xend - 1 : s.m_xend;
-    const int stop = co_rpg_eval(v, s, s.checked + 1, to);
+    const int stop = co_rpg_eval(v, q, s, s.checked + 1, to);
     if (threadIdx.x == 0) {
       if (stop >= 0) { s.m_end = stop; s.m_reason = END_STOP; }
       else { s.m_end = s.m_xend; s.m_reason = s.m_xreason; }
@@ -1000,7 +1028,11 @@ void launch_co_cand(const CoCandView& cv, const CohortView& v, hipStream_t s) {
 
 void launch_co_cg_done(const CohortView& v, int q, const Status* gst, uint64_t seq,
                        hipStream_t s) {
-  k_co_cg_done<<<1, 1, 0, s>>>(v, q, gst, seq);
+  k_co_cg_done<<<1, kBlock, 0, s>>>(v, q, gst, seq);
+}
+
+void launch_co_dmin(const CohortView& v, int q, int grid, hipStream_t s) {
+  k_co_dmin<<<grid, kBlock, 0, s>>>(v, q);
 }
 
 void launch_co_rpg_final(const CohortView& v, int q, hipStream_t s) {

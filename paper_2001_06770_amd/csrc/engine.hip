@@ -78,7 +78,8 @@ struct Engine {
   Ctx* c = nullptr;
   hipStream_t stream = nullptr;
   CohortView v = {};
-  DevBuf H, R, slots, acc, tot, wpre, qpre, wtot, stage, cand, ccnt, coff, ccur, cst;
+  DevBuf H, R, slots, acc, tot, wpre, qpre, wtot, stage, cand, ccnt, coff, ccur, cst, dmin;
+  bool any_vc = false;   // some slot's marginal run is checked (V_C ready): minima each level
   CoMirror* h_mir = nullptr;
   CoMirror* d_mir = nullptr;
   uint64_t seq = 0, cg_no = 0;
@@ -131,6 +132,7 @@ int engine_alloc(Engine& E) {
   RAKS_TRY(dev_alloc(c, E.coff, (size_t)nb * 4));
   RAKS_TRY(dev_alloc(c, E.ccur, 16));
   RAKS_TRY(dev_alloc(c, E.cst, sizeof(RunStatus)));
+  RAKS_TRY(dev_alloc(c, E.dmin, (size_t)kCoSlots * kMaxW * kMaxKw * 4));
   if (!E.h_mir) {
     void* hp = nullptr;
     if (hipHostMalloc(&hp, sizeof(CoMirror), hipHostMallocDefault) != hipSuccess)
@@ -156,6 +158,7 @@ int engine_alloc(Engine& E) {
   v.wtot = P<uint32_t>(E.wtot);
   v.stage = P<CoEntry>(E.stage);
   v.mirror = E.d_mir;
+  v.dmin = P<uint32_t>(E.dmin);
   HIP_OK(hipMemsetAsync(E.ccur.p, 0, 16, E.stream));
   HIP_OK(hipMemsetAsync(E.wtot.p, 0, 16, E.stream));
   launch_co_init(v, E.stream);
@@ -174,7 +177,7 @@ int engine_create(Ctx* c, Engine** out) {
   const int rc = engine_alloc(*E);
   if (rc) {
     for (DevBuf* b : {&E->H, &E->R, &E->slots, &E->acc, &E->tot, &E->wpre, &E->qpre, &E->wtot, &E->stage,
-                      &E->cand, &E->ccnt, &E->coff, &E->ccur, &E->cst})
+                      &E->cand, &E->ccnt, &E->coff, &E->ccur, &E->cst, &E->dmin})
       dev_free(c, *b);
     if (E->h_mir) (void)hipHostFree(E->h_mir);
     (void)hipStreamDestroy(E->stream);
@@ -441,6 +444,7 @@ int enqueue_level(Engine& E, int level, uint64_t seq) {
     launch();
   };
   timed(1, [&] { launch_co_scan(E.v, g, level, s); });
+  if (E.any_vc) launch_co_dmin(E.v, -1, c->num_cu * 4, s);
   timed(2, [&] { launch_co_control(E.v, level, seq, s); });
   if (tm & 1u) {
     hipEvent_t a = timing_event(E), b = timing_event(E);
@@ -585,6 +589,7 @@ int poll_cg(Engine& E) {
     if (!q || q->handed || !q->x_done || !q->cg_ok) continue;
     // the final marginal decision, the counters, and the query's levels moved
     // to its lane; slot and columns are free for the next level
+    if (q->p.M > 0) launch_co_dmin(E.v, q->slot, E.c->num_cu * 4, E.stream);
     launch_co_rpg_final(E.v, q->slot, E.stream);
     CoFinishView fv;
     fv.seg = E.v.H + (size_t)q->seg * E.v.n_pad * 16;
@@ -748,6 +753,9 @@ int engine_loop(Engine& E) {
     take_releases(E);
     RAKS_TRY(admit(E));
     if (any_exploring(E)) {
+      E.any_vc = false;
+      for (int i = 0; i < kCoSlots; ++i)
+        E.any_vc |= E.slot[i] && !E.slot[i]->x_done && E.slot[i]->cg_sent && E.slot[i]->p.M > 0;
       const uint64_t sq = ++E.seq;
       RAKS_TRY(enqueue_level(E, E.level, sq));
       if (have_prev) {
@@ -827,7 +835,7 @@ void cohort_destroy(Ctx* c) {
   stop_workers(*E);
   (void)hipStreamSynchronize(E->stream);
   for (DevBuf* b : {&E->H, &E->R, &E->slots, &E->acc, &E->tot, &E->wpre, &E->qpre, &E->wtot, &E->stage,
-                    &E->cand, &E->ccnt, &E->coff, &E->ccur, &E->cst})
+                    &E->cand, &E->ccnt, &E->coff, &E->ccur, &E->cst, &E->dmin})
     dev_free(c, *b);
   for (hipEvent_t e : E->ev_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : E->tev_pool) (void)hipEventDestroy(e);

@@ -102,7 +102,7 @@ def main():
     for i in picked:
         q = qs[i]
         t1 = time.time()
-        res = o.query(act, q)
+        res = o.query(act, q, lean=True)
         entry = {"index": i, "central": list(q.central), "marginal": list(q.marginal),
                  "k": q.k, "w": q.w, "max_level": q.max_level}
         entry.update(summarize(res))
