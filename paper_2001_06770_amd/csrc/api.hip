@@ -95,6 +95,9 @@ DevGraphView graph_view(const Ctx* c, const AlphaView& v) {
   g.n = c->n;
   g.A = c->A;
   g.row_ptr = reinterpret_cast<const uint32_t*>(c->row_ptr.p);
+  g.row_ptr_o = reinterpret_cast<const uint32_t*>(c->row_ptr_o.p);
+  g.orig_id = reinterpret_cast<const int32_t*>(c->orig_id.p);
+  g.int_id = reinterpret_cast<const int32_t*>(c->int_id.p);
   g.col = reinterpret_cast<const int32_t*>(c->col.p);
   g.label = reinterpret_cast<const uint16_t*>(c->label.p);
   g.act = reinterpret_cast<const uint8_t*>(v.act.p);
@@ -343,11 +346,15 @@ int build_view(Ctx* c, Lane* L, AlphaView& v, double alpha) {
   level_table(c->mode, (int64_t)c->wmin, (int64_t)c->wmax, c->abar, alpha, lut.data());
   RAKS_TRY(dev_alloc(c, c->lut, span));
   HIP_OK(hipMemcpyAsync(c->lut.p, lut.data(), span, hipMemcpyHostToDevice, s));
-  if (c->mode == RAKS_ACT_EDGE)
+  if (c->mode == RAKS_ACT_EDGE) {
     launch_act_edge(g, P<uint32_t>(c->cweight), P<uint8_t>(c->lut), c->wmin, P<uint8_t>(v.act), s);
-  else
+  } else {
+    // node levels by original id (they give the per-arc levels), then by internal id
+    RAKS_TRY(dev_alloc(c, c->node_tmp, (size_t)c->n));
     launch_act_node(g, P<uint8_t>(c->nw), P<uint8_t>(c->lut), (uint32_t)c->wmin,
-                    P<uint8_t>(v.act_node), P<uint8_t>(v.act), s);
+                    P<uint8_t>(c->node_tmp), P<uint8_t>(v.act), s);
+    launch_to_internal_u8(g, P<uint8_t>(c->node_tmp), P<uint8_t>(v.act_node), s);
+  }
   launch_sort_rows(g, P<int32_t>(v.col_s), P<uint8_t>(v.act_s), P<uint32_t>(v.eid_s),
                    P<uint8_t>(v.row_amax), P<uint32_t>(v.bnd), c->nbnd, s);
   HIP_OK(hipGetLastError());
@@ -1010,6 +1017,7 @@ int stage_central(Lane* L, const QueryPlan& p, QueryRun& q) {
   RAKS_TRY(run_levels(L, r1, p.TPc, p.central, p.C, &q.s1));
   q.top1 = std::max(0, q.s1.levels - 1);   // central levels are at most this
   SelectView sv;
+  sv.int_id = P<int32_t>(L->ctx->int_id);
   sv.cand = P<uint64_t>(L->cand);
   sv.st = r1.st;
   sv.gst = st;
@@ -1408,7 +1416,8 @@ int raks_destroy(raks_ctx* c) {
   drop_views(c);
   free_view(c, c->base);
   DevBuf* bufs[] = {&c->row_ptr, &c->col, &c->label, &c->nw, &c->kw_nodes, &c->arc_src,
-                    &c->rev, &c->cweight, &c->wstat, &c->lut};
+                    &c->rev, &c->cweight, &c->wstat, &c->lut, &c->row_ptr_o, &c->orig_id,
+                    &c->int_id, &c->node_tmp};
   for (DevBuf* b : bufs) dev_free(c, *b);
   delete c;
   return RAKS_OK;
@@ -1458,17 +1467,50 @@ int raks_load_graph(raks_ctx* c, const raks_graph_desc* g) {
   c->alpha = g->alpha;
   std::vector<uint32_t> rp32(n + 1);
   for (int64_t v = 0; v <= n; ++v) rp32[v] = (uint32_t)g->row_ptr[v];
+  // internal numbering: nodes by degree, largest first, ties by original id
+  // (a counting sort), and the internal row starts
+  std::vector<int32_t> orig_id(n), int_id(n);
+  std::vector<uint32_t> rpi(n + 1);
+  {
+    int64_t maxd = 0;
+    for (int64_t v = 0; v < n; ++v) maxd = std::max(maxd, g->row_ptr[v + 1] - g->row_ptr[v]);
+    std::vector<int64_t> start((size_t)maxd + 1, 0);
+    for (int64_t v = 0; v < n; ++v) ++start[g->row_ptr[v + 1] - g->row_ptr[v]];
+    int64_t acc = 0;
+    for (int64_t d = maxd; d >= 0; --d) {
+      const int64_t k = start[d];
+      start[d] = acc;
+      acc += k;
+    }
+    for (int64_t v = 0; v < n; ++v) {
+      const int64_t u = start[g->row_ptr[v + 1] - g->row_ptr[v]]++;
+      orig_id[u] = (int32_t)v;
+      int_id[v] = (int32_t)u;
+    }
+    rpi[0] = 0;
+    for (int64_t u = 0; u < n; ++u)
+      rpi[u + 1] = rpi[u] + (uint32_t)(g->row_ptr[orig_id[u] + 1] - g->row_ptr[orig_id[u]]);
+  }
   RAKS_TRY(dev_alloc(c, c->row_ptr, (n + 1) * 4));
+  RAKS_TRY(dev_alloc(c, c->row_ptr_o, (n + 1) * 4));
+  RAKS_TRY(dev_alloc(c, c->orig_id, n * 4));
+  RAKS_TRY(dev_alloc(c, c->int_id, n * 4));
   RAKS_TRY(dev_alloc(c, c->col, std::max<int64_t>(A, 1) * 4));
   RAKS_TRY(dev_alloc(c, c->label, std::max<int64_t>(A, 1) * 2));
   drop_views(c);
   RAKS_TRY(dev_alloc(c, c->kw_nodes, std::max<int64_t>(nkw, 1) * 4));
-  HIP_OK(hipMemcpyAsync(c->row_ptr.p, rp32.data(), (n + 1) * 4, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(c->row_ptr_o.p, rp32.data(), (n + 1) * 4, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(c->row_ptr.p, rpi.data(), (n + 1) * 4, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(c->orig_id.p, orig_id.data(), n * 4, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(c->int_id.p, int_id.data(), n * 4, hipMemcpyHostToDevice, s));
   if (A > 0) {
     HIP_OK(hipMemcpyAsync(c->col.p, g->col, A * 4, hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(c->label.p, g->label, A * 2, hipMemcpyHostToDevice, s));
   }
-  if (nkw > 0) HIP_OK(hipMemcpyAsync(c->kw_nodes.p, g->kw_nodes, nkw * 4, hipMemcpyHostToDevice, s));
+  if (nkw > 0) {
+    HIP_OK(hipMemcpyAsync(c->kw_nodes.p, g->kw_nodes, nkw * 4, hipMemcpyHostToDevice, s));
+    launch_map_ids(P<int32_t>(c->int_id), P<int32_t>(c->kw_nodes), (uint64_t)nkw, s);
+  }
   if (g->act_mode == RAKS_ACT_NODE) {
     RAKS_TRY(dev_alloc(c, c->nw, n));
     HIP_OK(hipMemcpyAsync(c->nw.p, g->node_weight, n, hipMemcpyHostToDevice, s));

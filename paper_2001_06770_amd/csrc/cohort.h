@@ -126,6 +126,7 @@ struct CoCandView {
   uint32_t* cursor;              // [2]: earlier-level candidates placed / counted
   uint64_t* cand;                // keys: earlier levels first, then the last level in node order
   RunStatus* st;                 // receives ncand_total / ncand_level for the selection
+  const int32_t* orig_id;        // internal id -> original id (the keys' node ids)
 };
 
 // End of a query's exploration: the work counters of both runs from its

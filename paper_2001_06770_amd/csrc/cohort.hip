@@ -754,7 +754,7 @@ __global__ __launch_bounds__(kBlock) void k_co_cand_write(CoCandView cv, int32_t
       }
       keep = complete && mx <= cv.end;
       last = keep && mx == cv.end;
-      key = ((uint64_t)mx << 48) | ((uint64_t)sum << 32) | (uint32_t)v;
+      key = ((uint64_t)mx << 48) | ((uint64_t)sum << 32) | (uint32_t)cv.orig_id[v];
     }
     uint32_t tot;
     const uint32_t ex = block_exclusive_scan<uint32_t, kBlock>(last ? 1u : 0u, s_red, &tot);

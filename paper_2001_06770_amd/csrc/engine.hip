@@ -501,8 +501,10 @@ int enqueue_cg(Engine& E, CoQuery* q) {
   cv.cursor = P<uint32_t>(E.ccur);
   cv.cand = P<uint64_t>(E.cand);
   cv.st = P<RunStatus>(E.cst);
+  cv.orig_id = P<int32_t>(c->orig_id);
   launch_co_cand(cv, E.v, s);
   SelectView sv;
+  sv.int_id = P<int32_t>(c->int_id);
   sv.cand = P<uint64_t>(E.cand);
   sv.st = P<RunStatus>(E.cst);
   sv.gst = st;

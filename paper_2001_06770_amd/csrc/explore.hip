@@ -216,7 +216,7 @@ __device__ inline NodeInfo inspect_node(const RunView& r, const DevGraphView& g,
   o.active = !blocked && (o.mask_new | o.mask_old) != 0 && d > 0;
   o.deg = o.active ? d : 0;
   o.cand = (r.kind == RUN_CENTRAL) && st.complete && st.mx == (uint32_t)level;
-  o.key = ((uint64_t)st.mx << 48) | ((uint64_t)st.sum << 32) | (uint32_t)v;
+  o.key = ((uint64_t)st.mx << 48) | ((uint64_t)st.sum << 32) | (uint32_t)g.orig_id[v];
   o.lo = o.hi = o.start = o.work = 0;
   if (o.active) {
     // arcs of level <= x: none below 0, the whole row from its largest level
@@ -668,12 +668,11 @@ __global__ __launch_bounds__(kBlock) void k_expand(RunView r, DevGraphView g, in
 // -------------------------------------------------------------- top-w ---
 // Top-w central graphs by (S^c, sum of central levels, node id).  All CGs of
 // earlier levels are kept (they are fewer than w); the remaining slots go to
-// the last level's CGs with the smallest sums, ties to smaller node ids (the
-// candidate list of a level is in node order).
+// the last level's CGs with the smallest sums, ties to smaller node ids.  The
+// keys hold original node ids; the selected nodes are stored by internal id.
 __global__ __launch_bounds__(kCtl) void k_select(SelectView v) {
   __shared__ uint64_t s_sel[kMaxW];
   __shared__ uint32_t s_hist[4096];
-  __shared__ uint32_t s_scan[kCtl / kWave + 1];
   __shared__ uint32_t s_cnt, s_thr, s_take, s_nsel;
   const RunStatus* st = v.st;
   const uint32_t total = st->ncand_total, last = st->ncand_level;
@@ -714,31 +713,42 @@ __global__ __launch_bounds__(kCtl) void k_select(SelectView v) {
       s_nsel = w;
     }
     __syncthreads();
-    const uint32_t thr = s_thr, take = s_take;
-    // every thread walks one contiguous segment of the level's list; one scan
-    // of the per-segment counts of sums equal to the threshold gives each
-    // segment's rank among them, so the first `take` in list order are kept
-    const uint32_t seg = (last + kCtl - 1) / kCtl;
-    const uint32_t a = prev + min(last, threadIdx.x * seg);
-    const uint32_t b = prev + min(last, (threadIdx.x + 1) * seg);
-    uint32_t eq = 0;
-#pragma unroll 8
-    for (uint32_t i = a; i < b; ++i) {
+    const uint32_t thr = s_thr;
+    // ties at the threshold sum go to the smallest node ids: unless every tie
+    // is kept, a byte-wise radix select finds the take-th smallest id T among
+    // them (ids are unique, so exactly `take` ties have an id <= T)
+    uint32_t T = 0xFFFFFFFFu;
+    if (s_hist[thr] != s_take) {
+      uint32_t prefix = 0, mask = 0, rem = s_take;
+      for (int sh = 24; sh >= 0; sh -= 8) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < 256; i += kCtl) s_hist[i] = 0;
+        __syncthreads();
+        for (uint32_t i = prev + threadIdx.x; i < total; i += kCtl) {
+          const uint64_t key = v.cand[i];
+          const uint32_t id = (uint32_t)key;
+          if (((uint32_t)(key >> 32) & 0xFFFF) == thr && (id & mask) == prefix)
+            atomicAdd(&s_hist[(id >> sh) & 255u], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          uint32_t cum = 0;
+          for (uint32_t d = 0; d < 256; ++d) {
+            if (cum + s_hist[d] >= rem) { s_thr = prefix | (d << sh); s_take = rem - cum; break; }
+            cum += s_hist[d];
+          }
+        }
+        __syncthreads();
+        prefix = s_thr;
+        rem = s_take;
+        mask |= 255u << sh;
+      }
+      T = prefix;
+    }
+    for (uint32_t i = prev + threadIdx.x; i < total; i += kCtl) {
       const uint64_t key = v.cand[i];
       const uint32_t s = (uint32_t)(key >> 32) & 0xFFFF;
-      if (s < thr) s_sel[atomicAdd(&s_cnt, 1u)] = key;
-      eq += s == thr;
-    }
-    uint32_t tot;
-    const uint32_t ex = block_exclusive_scan<uint32_t, kCtl>(eq, s_scan, &tot);
-    uint32_t rank = ex;
-#pragma unroll 4
-    for (uint32_t i = a; i < b && rank < take; ++i) {
-      const uint64_t key = v.cand[i];
-      if (((uint32_t)(key >> 32) & 0xFFFF) == thr) {
-        s_sel[atomicAdd(&s_cnt, 1u)] = key;
-        ++rank;
-      }
+      if (s < thr || (s == thr && (uint32_t)key <= T)) s_sel[atomicAdd(&s_cnt, 1u)] = key;
     }
   }
   __syncthreads();
@@ -747,7 +757,7 @@ __global__ __launch_bounds__(kCtl) void k_select(SelectView v) {
     const uint64_t key = s_sel[i];
     uint32_t rank = 0;
     for (uint32_t j = 0; j < nsel; ++j) rank += s_sel[j] < key;
-    v.sel_node[rank] = (int32_t)(key & 0xFFFFFFFFu);
+    v.sel_node[rank] = v.int_id[key & 0xFFFFFFFFu];
     v.sel_sc[rank] = (int32_t)(key >> 48);
     v.sel_sumh[rank] = (int32_t)((key >> 32) & 0xFFFF);
   }

@@ -119,21 +119,26 @@ __global__ __launch_bounds__(kBlock) void k_act_gather(const uint8_t* act_node,
 // (counting sort per row, one wavefront per row), plus the row's largest
 // level and its entries of the level-major level table.  At level l a
 // frontier's arcs with level <= l form a row prefix.
-__global__ __launch_bounds__(kBlock) void k_sort_rows(const uint32_t* row_ptr, const int32_t* col,
-                                                      const uint8_t* act, int32_t n,
-                                                      int32_t* col_s, uint8_t* act_s,
+__global__ __launch_bounds__(kBlock) void k_sort_rows(const uint32_t* row_ptr_o,
+                                                      const uint32_t* row_ptr,
+                                                      const int32_t* orig_id, const int32_t* int_id,
+                                                      const int32_t* col, const uint8_t* act,
+                                                      int32_t n, int32_t* col_s, uint8_t* act_s,
                                                       uint32_t* eid_s, uint8_t* row_amax,
                                                       uint32_t* bnd, int32_t nbnd) {
   __shared__ uint32_t s_hist[kBlock / kWave][256];
   uint32_t* hist = s_hist[wave_id()];
   const int lane = lane_id();
   const int waves = gridDim.x * (kBlock / kWave);
-  for (int32_t v = blockIdx.x * (kBlock / kWave) + wave_id(); v < n; v += waves) {
-    const uint32_t rs = row_ptr[v], re = row_ptr[v + 1];
+  for (int32_t u = blockIdx.x * (kBlock / kWave) + wave_id(); u < n; u += waves) {
+    // internal row u holds original row v's arcs
+    const int32_t v = orig_id[u];
+    const uint32_t rs_o = row_ptr_o[v], re_o = row_ptr_o[v + 1];
+    const uint32_t rs = row_ptr[u];
     for (int b = lane; b < 256; b += kWave) hist[b] = 0;
     __builtin_amdgcn_wave_barrier();
     uint32_t amax = 0;
-    for (uint32_t e = rs + lane; e < re; e += kWave) {
+    for (uint32_t e = rs_o + lane; e < re_o; e += kWave) {
       const uint32_t a = act[e];
       atomicAdd(&hist[a], 1u);
       amax = a > amax ? a : amax;
@@ -154,25 +159,38 @@ __global__ __launch_bounds__(kBlock) void k_sort_rows(const uint32_t* row_ptr, c
     hist[4 * lane + 3] = ex + c0 + c1 + c2;
     __builtin_amdgcn_wave_barrier();
     // arcs with level <= l = start of level l + 1
-    if (lane < nbnd) bnd[(size_t)lane * n + v] = hist[lane + 1];
+    if (lane < nbnd) bnd[(size_t)lane * n + u] = hist[lane + 1];
     __builtin_amdgcn_wave_barrier();
-    for (uint32_t e = rs + lane; e < re; e += kWave) {
+    for (uint32_t e = rs_o + lane; e < re_o; e += kWave) {
       const uint32_t a = act[e];
       const uint32_t pos = rs + atomicAdd(&hist[a], 1u);
-      col_s[pos] = col[e];
+      col_s[pos] = int_id[col[e]];
       act_s[pos] = (uint8_t)a;
       eid_s[pos] = e;
     }
-    if (lane == 0) row_amax[v] = (uint8_t)amax;
+    if (lane == 0) row_amax[u] = (uint8_t)amax;
     __builtin_amdgcn_wave_barrier();
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_to_internal_u8(const int32_t* orig_id, int32_t n,
+                                                           const uint8_t* in, uint8_t* out) {
+  for (int32_t u = blockIdx.x * kBlock + threadIdx.x; u < n; u += gridDim.x * kBlock)
+    out[u] = in[orig_id[u]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_map_ids(const int32_t* int_id, int32_t* ids,
+                                                    uint64_t count) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < count;
+       i += (uint64_t)gridDim.x * kBlock)
+    ids[i] = int_id[ids[i]];
 }
 
 void launch_sort_rows(const DevGraphView& g, int32_t* col_s, uint8_t* act_s, uint32_t* eid_s,
                       uint8_t* row_amax, uint32_t* bnd, int32_t nbnd, hipStream_t s) {
   const unsigned grid = (unsigned)std::min<int64_t>(16384, ((int64_t)g.n + 3) / 4);
-  k_sort_rows<<<grid, kBlock, 0, s>>>(g.row_ptr, g.col, g.act, g.n, col_s, act_s, eid_s, row_amax,
-                                      bnd, nbnd);
+  k_sort_rows<<<grid, kBlock, 0, s>>>(g.row_ptr_o, g.row_ptr, g.orig_id, g.int_id, g.col, g.act,
+                                      g.n, col_s, act_s, eid_s, row_amax, bnd, nbnd);
 }
 
 __global__ void k_status_reset_minmax(Status* st) {
@@ -193,7 +211,7 @@ void launch_check_and_count(const DevGraphView& g, uint32_t* c_tmp, int32_t* arc
                             Status* st, hipStream_t s) {
   k_status_reset_minmax<<<1, 1, 0, s>>>(st);
   if (g.A > 0)
-    k_check_and_count<<<grid_for(g.A), kBlock, 0, s>>>(g.row_ptr, g.col, g.label, g.n, g.A, c_tmp,
+    k_check_and_count<<<grid_for(g.A), kBlock, 0, s>>>(g.row_ptr_o, g.col, g.label, g.n, g.A, c_tmp,
                                                         arc_src, rev, st);
 }
 
@@ -206,6 +224,14 @@ void launch_node_weight_range(const DevGraphView& g, const uint8_t* nw, Status* 
                               hipStream_t s) {
   k_status_reset_minmax<<<1, 1, 0, s>>>(st);
   k_node_weight_range<<<grid_for(g.n), kBlock, 0, s>>>(nw, g.n, st);
+}
+
+void launch_to_internal_u8(const DevGraphView& g, const uint8_t* in, uint8_t* out, hipStream_t s) {
+  k_to_internal_u8<<<grid_for(g.n), kBlock, 0, s>>>(g.orig_id, g.n, in, out);
+}
+
+void launch_map_ids(const int32_t* int_id, int32_t* ids, uint64_t count, hipStream_t s) {
+  if (count) k_map_ids<<<grid_for(count), kBlock, 0, s>>>(int_id, ids, count);
 }
 
 void launch_act_node(const DevGraphView& g, const uint8_t* nw, const uint8_t* lut, uint32_t wmin,

@@ -5,24 +5,32 @@
 
 namespace raks {
 
+// Two numberings of the nodes.  The caller's ("original") ids and CSR
+// positions are kept for everything that leaves the library and for the
+// load-time checks; the search runs on internal ids that order the nodes by
+// degree (largest first), so the hitting levels and reached masks of the
+// nodes that most arcs point to share a few cache lines.
 struct DevGraphView {
   int32_t n;
   uint32_t A;
-  const uint32_t* row_ptr;  // [n+1]
-  const int32_t* col;       // [A]
-  const uint16_t* label;    // [A]
-  const uint8_t* act;       // [A] activation level per arc
-  const uint8_t* act_node;  // [n] NODE mode, else nullptr
+  const uint32_t* row_ptr;  // [n+1] internal rows (the traversal copy's row starts)
+  const uint32_t* row_ptr_o;// [n+1] original rows
+  const int32_t* orig_id;   // [n] internal id -> original id
+  const int32_t* int_id;    // [n] original id -> internal id
+  const int32_t* col;       // [A] original CSR: destination (original id)
+  const uint16_t* label;    // [A] original CSR
+  const uint8_t* act;       // [A] activation level per arc, original CSR order
+  const uint8_t* act_node;  // [n] NODE mode, by internal id, else nullptr
   int32_t mode;             // 0 EDGE, 1 NODE
-  // traversal copy: every row re-ordered by activation level (ascending)
-  const int32_t* col_s;     // [A]
+  // traversal copy, internal rows: each row's arcs ordered by activation level
+  const int32_t* col_s;     // [A] destination (internal id)
   const uint8_t* act_s;     // [A]
-  const uint32_t* eid_s;    // [A] CSR position of the arc
-  const int32_t* arc_src;   // [A] source node of each arc (CSR order)
-  const uint32_t* rev;      // [A] CSR position of each arc's reverse arc
-  const uint8_t* row_amax;  // [n_pad] largest activation level of the row (0 if empty;
-                            // 0 past n, up to a multiple of kScanNodes)
-  const uint32_t* bnd;      // [nbnd][n] arcs of the row with level <= l, l < nbnd
+  const uint32_t* eid_s;    // [A] original CSR position of the arc
+  const int32_t* arc_src;   // [A] source node of each arc (original id, original CSR order)
+  const uint32_t* rev;      // [A] original CSR position of each arc's reverse arc
+  const uint8_t* row_amax;  // [n_pad] largest activation level of the row, internal ids (0 if
+                            // empty; 0 past n, up to a multiple of kScanNodes)
+  const uint32_t* bnd;      // [nbnd][n] arcs of the internal row with level <= l, l < nbnd
                             // (level-major: a level's counts of all nodes are contiguous)
   int32_t nbnd;             // levels covered by bnd (1..16)
 };
@@ -66,7 +74,7 @@ struct RunView {
   uint32_t* q_mask;      // keywords reached at level l | keywords reached before << 16
   uint32_t* tile_first;  // [A / kExpandTile + 2] queue entry holding each expansion tile's
                          // first arc (| kTileAtEntry when the tile starts with the entry)
-  uint64_t* cand;        // central run: identified central nodes (S<<48 | sum<<32 | node)
+  uint64_t* cand;        // central run: identified central nodes (S<<48 | sum<<32 | original id)
   int32_t max_level;
   int32_t w, k, gamma_num, gamma_den;
   int32_t score_mode;        // 0: Eq. 6, 1: S^c * S^m
@@ -90,11 +98,12 @@ struct SeedList {
 };
 
 struct SelectView {
+  const int32_t* int_id;    // original id (in the keys) -> internal id
   const uint64_t* cand;
   RunStatus* st;
   Status* gst;
   int32_t w;
-  int32_t* sel_node;   // [w]
+  int32_t* sel_node;   // [w] internal ids
   int32_t* sel_sc;     // [w]
   int32_t* sel_sumh;   // [w]
 };
@@ -235,6 +244,10 @@ void launch_act_edge(const DevGraphView& g, const uint32_t* c_tmp, const uint8_t
                      uint64_t cmin, uint8_t* act, hipStream_t s);
 void launch_sort_rows(const DevGraphView& g, int32_t* col_s, uint8_t* act_s, uint32_t* eid_s,
                       uint8_t* row_amax, uint32_t* bnd, int32_t nbnd, hipStream_t s);
+// out[u] = in[orig_id[u]] for every internal id u (per-node arrays to internal order)
+void launch_to_internal_u8(const DevGraphView& g, const uint8_t* in, uint8_t* out, hipStream_t s);
+// ids[i] = int_id[ids[i]] (original node ids to internal ones, in place)
+void launch_map_ids(const int32_t* int_id, int32_t* ids, uint64_t count, hipStream_t s);
 // node weight range into st->cmin / st->cmax (NODE mode, once per graph)
 void launch_node_weight_range(const DevGraphView& g, const uint8_t* nw, Status* st,
                               hipStream_t s);

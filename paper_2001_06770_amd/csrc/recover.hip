@@ -294,8 +294,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeView v) {
       const InstCap ic = v.caps[inst];
       const uint32_t cnt = min(v.cnt[inst * 2 + pass], pass == 0 ? ic.ncap : ic.acap);
       if (pass == 0) {
+        // recovered nodes are internal ids; results list original ids
         const int32_t* src = v.nl + ic.noff;
-        for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) A[n + i] = (uint32_t)src[i];
+        for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) A[n + i] = (uint32_t)g.orig_id[src[i]];
       } else {
         const uint32_t* src = v.al + ic.aoff;
         for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) A[n + i] = src[i];
@@ -312,19 +313,20 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeView v) {
       for (uint32_t i = threadIdx.x; i < m; i += kBlock) dst[i] = uniq[i];
       if (threadIdx.x == 0) v.cg_cnt[r * 2 + pass] = m;
       if (pass == 0) {
-        // V_C in node order
+        // V_C in node order, stored as internal ids
         int32_t* vc = v.vc_tmp + v.cg_noff[r];
         uint32_t written = 0;
         for (uint32_t t0 = 0; t0 < m; t0 += kBlock) {
           const uint32_t i = t0 + threadIdx.x;
           uint32_t keep = 0;
+          int64_t x = 0;
           if (i < m) {
-            const int64_t x = uniq[i];
+            x = g.int_id[uniq[i]];
             for (int c = 0; c < v.Tc; ++c) keep |= v.Hc[x * v.TPc + c] == 0;
           }
           uint32_t tot;
           const uint32_t ex = block_exclusive_scan<uint32_t, kBlock>(keep, lds.scan, &tot);
-          if (keep) vc[written + ex] = (int32_t)uniq[i];
+          if (keep) vc[written + ex] = (int32_t)x;
           written += tot;
         }
         if (threadIdx.x == 0) v.vc_cnt[r] = written;
@@ -344,7 +346,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeView v) {
         s_off = off;
         ResultHdr& hd = v.hdr[t];
         if (pass == 0) {
-          hd.central = v.sel_node[r];
+          hd.central = v.g.orig_id[v.sel_node[r]];
           hd.score_c = v.sel_sc[r];
           hd.score_m = v.sm[r];
           hd.cg_rank = r;
@@ -421,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_big_mark(FinalizeView v, int t, int 
       const uint32_t cnt = min(v.cnt[inst * 2], ic.ncap);
       const int32_t* src = v.nl + ic.noff;
       for (uint32_t i = tid; i < cnt; i += stride) {
-        const uint32_t x = (uint32_t)src[i];
+        const uint32_t x = (uint32_t)v.g.orig_id[src[i]];   // internal -> original id
         if (x < limit) atomicOr(&bm[x >> 5], 1u << (x & 31u));
       }
     }
@@ -434,7 +436,7 @@ __device__ inline uint32_t big_bits(const FinalizeView& v, int pass, uint32_t wo
   uint32_t keep = 0;
   for (uint32_t b = word; b; b &= b - 1) {
     const int bit = __ffs(b) - 1;
-    const int64_t x = (int64_t)wi * 32 + bit;
+    const int64_t x = v.g.int_id[wi * 32 + (uint32_t)bit];   // the bitmap is over original ids
     bool vc = false;
     for (int c = 0; c < v.Tc; ++c) vc |= v.Hc[x * v.TPc + c] == 0;
     keep |= (vc ? 1u : 0u) << bit;
@@ -491,7 +493,7 @@ __global__ __launch_bounds__(kBlock) void k_big_scan(FinalizeView v, int t, int 
   slot[0] = off;
   ResultHdr& hd = v.hdr[t];
   if (pass == 0) {
-    hd.central = v.sel_node[r];
+    hd.central = v.g.orig_id[v.sel_node[r]];
     hd.score_c = v.sel_sc[r];
     hd.score_m = v.sm[r];
     hd.cg_rank = r;
@@ -538,7 +540,7 @@ __global__ __launch_bounds__(kBlock) void k_big_write(FinalizeView v, int t, int
       if (!v.marginal) {
         if (pass == 0) v.cg_nodes[pos] = id;
         else if (pass == 1) v.cg_arcs[pos] = id;
-        else v.vc_tmp[pos] = (int32_t)id;
+        else v.vc_tmp[pos] = g.int_id[id];
       } else if (pass == 0) {
         v.out_nodes[pos] = (int32_t)id;
       } else {

@@ -161,6 +161,8 @@ struct Ctx {
   int32_t mode = 0;
   double abar = 0, alpha = 0;
   DevBuf row_ptr, col, label, nw, kw_nodes, arc_src;
+  // internal (degree-ordered) node numbering: original row starts, both id maps
+  DevBuf row_ptr_o, orig_id, int_id, node_tmp;
   DevBuf rev;            // CSR position of every arc's reverse arc
   DevBuf cweight;        // EDGE: label count c of every arc, kept for other alphas
   DevBuf wstat;          // Status holding the c (or node weight) range of the graph
