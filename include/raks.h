@@ -216,10 +216,46 @@ typedef struct {
     int32_t status;          /* RAKS_STATUS_* bits */
 } raks_results;
 
+/* Caller-owned output of raks_query_noalloc.  The caller sets the arrays and
+ * their capacities; the call fills the rest.  r[i].nodes and r[i].arcs point
+ * into `nodes` and `arcs`, where the results' lists lie back to back. */
+typedef struct {
+    raks_result* r;          /* [cap_results] */
+    int32_t cap_results;     /* at least the query's k */
+    int32_t* nodes;          /* [cap_nodes] */
+    int64_t cap_nodes;
+    raks_arc* arcs;          /* [cap_arcs] */
+    int64_t cap_arcs;
+    int32_t n;               /* out: number of results (<= k) */
+    int32_t status;          /* out: RAKS_STATUS_* bits */
+    int64_t n_nodes;         /* out: node entries of all results (also on a too-small RAKS_ENOMEM) */
+    int64_t n_arcs;          /* out: arc entries of all results (likewise) */
+    raks_query_stats stats;  /* out */
+} raks_results_buf;
+
 /* Runs one query (both runs of Section 4.1 on the GPU: exploration,
  * identification, top-w selection, recovery, marginal run, ranking) and
  * returns its results.  *out is library-owned until raks_results_free. */
 int raks_query(raks_ctx* ctx, const raks_query_desc* q, raks_results** out);
+
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, e.g. tight serving loops or harnesses that forbid it): the same
+ * query and results as raks_query, with no device or pinned-host allocation
+ * in the call.  It runs on a lane of its own that raks_create sets up; all of
+ * its device state lives in one static device array of 256 MiB per GPU that
+ * the library holds until the process ends.  That array is shared by every
+ * context on the GPU and keeps the last call's contents (the call initialises
+ * what it reads), so calls that overlap on one GPU race: issue them one at a
+ * time per GPU.  The results are written to the caller's arrays in `out`.
+ * Errors: RAKS_EINVAL for NULL arguments, negative capacities, a NULL array
+ * with a positive capacity, cap_results < k or an invalid query;
+ * RAKS_ESTATE while serving runs, without a graph, or when the levels of the
+ * query's alpha have not been built (a raks_query with that alpha builds
+ * them); RAKS_ENOMEM when the query's device state would exceed the 256 MiB
+ * (graphs of up to about 3M nodes fit), or when the results do not fit the
+ * caller's arrays (then out->n_nodes / n_arcs give the sizes needed and out->n
+ * is 0).  Event timing (raks_set_timing) does not cover this lane. */
+int raks_query_noalloc(raks_ctx* ctx, const raks_query_desc* q, raks_results_buf* out);
 
 /* Runs n queries and returns outs[i] = the results of qs[i], identical to
  * those of raks_query(qs[i]), each owned independently.  On error no output

@@ -84,6 +84,14 @@ class Results(ctypes.Structure):
                 ("status", ctypes.c_int32)]
 
 
+class ResultsBuf(ctypes.Structure):
+    _fields_ = [("r", ctypes.POINTER(Result)), ("cap_results", ctypes.c_int32),
+                ("nodes", ctypes.POINTER(ctypes.c_int32)), ("cap_nodes", ctypes.c_int64),
+                ("arcs", ctypes.POINTER(Arc)), ("cap_arcs", ctypes.c_int64),
+                ("n", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("n_nodes", ctypes.c_int64), ("n_arcs", ctypes.c_int64), ("stats", QueryStats)]
+
+
 class KernelTiming(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
@@ -112,6 +120,8 @@ def lib():
         L.raks_get_activations.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
         L.raks_query.argtypes = [ctypes.c_void_p, ctypes.POINTER(QueryDesc),
                                  ctypes.POINTER(ctypes.POINTER(Results))]
+        L.raks_query_noalloc.argtypes = [ctypes.c_void_p, ctypes.POINTER(QueryDesc),
+                                         ctypes.POINTER(ResultsBuf)]
         L.raks_query_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(QueryDesc), ctypes.c_int32,
                                        ctypes.POINTER(ctypes.POINTER(Results))]
         L.raks_results_free.argtypes = [ctypes.POINTER(Results)]
@@ -140,7 +150,7 @@ EXPORTED = ("raks_create", "raks_destroy", "raks_load_graph", "raks_set_alpha",
             "raks_get_activations", "raks_query", "raks_query_batch", "raks_results_free",
             "raks_serve_start", "raks_submit", "raks_poll", "raks_wait", "raks_serve_stop",
             "raks_set_timing", "raks_get_timing", "raks_last_error", "raks_version",
-            "raks_set_batch_mode", "raks_level_table", "raks_set_tuning")
+            "raks_set_batch_mode", "raks_level_table", "raks_set_tuning", "raks_query_noalloc")
 RAKS_EAGAIN = -5
 
 
@@ -286,6 +296,31 @@ class Context:
             return _results_to_dict(out.contents, lean)
         finally:
             lib().raks_results_free(out)
+
+    def query_noalloc(self, q, cap_nodes: int = 1 << 20, cap_arcs: int = 1 << 20,
+                      lean: bool = False) -> dict:
+        """raks_query_noalloc: the query with no device allocation in the call;
+        the result lists go into host arrays of the given capacities."""
+        keep = []
+        d = self._desc(q, keep)
+        cap_r = max(int(q.k), 1)
+        res_arr = (Result * cap_r)()
+        nodes = np.empty(max(cap_nodes, 1), np.int32)
+        arcs = np.empty((max(cap_arcs, 1), 3), np.int32)
+        buf = ResultsBuf()
+        buf.r = ctypes.cast(res_arr, ctypes.POINTER(Result))
+        buf.cap_results = cap_r
+        buf.nodes = nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        buf.cap_nodes = int(cap_nodes)
+        buf.arcs = ctypes.cast(arcs.ctypes.data, ctypes.POINTER(Arc))
+        buf.cap_arcs = int(cap_arcs)
+        rc = lib().raks_query_noalloc(self._h, ctypes.byref(d), ctypes.byref(buf))
+        if rc != 0:
+            err = RaksError(rc, lib().raks_last_error().decode())
+            err.need = (int(buf.n_nodes), int(buf.n_arcs))
+            raise err
+        view = Results(buf.n, buf.r, buf.stats, buf.status)
+        return _results_to_dict(view, lean)
 
     def query_batch(self, qs, lean: bool = False) -> list:
         """Runs the queries together (cohorts, or lanes in RAKS_BATCH_LANES mode)."""

@@ -52,15 +52,30 @@ double now_ms() {
 
 // Device buffers grow on demand and are kept.  The context's allocator and
 // budget are shared by all lanes, so allocation is serialised.
+thread_local Arena* g_arena = nullptr;
+
 int dev_alloc(Ctx* c, DevBuf& b, size_t bytes) {
   if (b.bytes >= bytes && b.p) return RAKS_OK;
+  if (g_arena) {
+    Arena& a = *g_arena;
+    bytes = (std::max<size_t>(bytes, 256) + 255) & ~size_t(255);
+    if (bytes > a.cap - a.used)
+      return fail(RAKS_ENOMEM, "allocation-free query: its device state exceeds the " +
+                                   std::to_string(a.cap >> 20) + " MiB scratch (" +
+                                   std::to_string(a.used + bytes) + " bytes needed so far)");
+    b.p = a.base + a.used;
+    b.bytes = bytes;
+    b.borrowed = true;
+    a.used += bytes;
+    return RAKS_OK;
+  }
   std::lock_guard<std::mutex> lk(c->mem_mu);
-  if (b.p) {
+  if (b.p && !b.borrowed) {
     if (c->free_fn) c->free_fn(b.p, b.bytes, c->alloc_user);
     else (void)hipFree(b.p);
     c->in_use -= b.bytes;
-    b = DevBuf();
   }
+  b = DevBuf();
   if (bytes == 0) bytes = 256;
   bytes = (bytes + 255) & ~size_t(255);
   if (c->budget && c->in_use + bytes > c->budget)
@@ -80,7 +95,10 @@ int dev_alloc(Ctx* c, DevBuf& b, size_t bytes) {
 }
 
 void dev_free(Ctx* c, DevBuf& b) {
-  if (!b.p) return;
+  if (!b.p || b.borrowed) {
+    b = DevBuf();
+    return;
+  }
   std::lock_guard<std::mutex> lk(c->mem_mu);
   if (c->free_fn) c->free_fn(b.p, b.bytes, c->alloc_user);
   else (void)hipFree(b.p);
@@ -118,22 +136,28 @@ DevGraphView graph_view(const Lane* L) { return graph_view(L->ctx, *L->view); }
 
 // -------------------------------------------------------------- lanes ---
 
+std::vector<DevBuf*> lane_buffers(Lane* L) {
+  std::vector<DevBuf*> v = {
+      &L->Hc, &L->Hm, &L->Hq, &L->R, &L->tot, &L->sb, &L->q_off, &L->q_rs, &L->q_lo,
+      &L->q_mask, &L->tile_first, &L->cand, &L->s_item, &L->s_cand, &L->sel_node, &L->sel_sc,
+      &L->sel_sumh, &L->has_rpg, &L->sm, &L->key, &L->dmin, &L->ranked, &L->vc_cnt,
+      &L->vc_tmp, &L->vc_off, &L->vc_nodes, &L->hpool, &L->nl, &L->al, &L->items, &L->sort_a,
+      &L->sort_b, &L->cg_nodes, &L->cg_arcs, &L->cg_cnt, &L->hdr, &L->out_nodes, &L->out_arcs,
+      &L->bigf, &L->big_bm, &L->big_chunk, &L->big_slot};
+  for (RecPhase& P : L->ph)
+    for (DevBuf* b : {&P.layout, &P.cnt, &P.iflag, &P.lcnt}) v.push_back(b);
+  return v;
+}
+
 void lane_destroy(Ctx* c, Lane* L) {
   if (!L) return;
   if (L->stream) (void)hipStreamSynchronize(L->stream);
-  DevBuf* bufs[] = {&L->Hc, &L->Hm, &L->Hq, &L->R, &L->tot, &L->sb, &L->q_off, &L->q_rs,
-                    &L->q_lo, &L->q_mask, &L->tile_first, &L->cand, &L->s_item, &L->s_cand, &L->sel_node, &L->sel_sc, &L->sel_sumh,
-                    &L->has_rpg, &L->sm, &L->key, &L->dmin, &L->ranked, &L->vc_cnt, &L->vc_tmp,
-                    &L->vc_off, &L->vc_nodes, &L->hpool, &L->nl, &L->al, &L->items, &L->sort_a,
-                    &L->sort_b, &L->cg_nodes, &L->cg_arcs, &L->cg_cnt, &L->hdr, &L->out_nodes,
-                    &L->out_arcs, &L->status, &L->bigf, &L->big_bm, &L->big_chunk, &L->big_slot};
+  for (DevBuf* b : lane_buffers(L)) dev_free(c, *b);
+  dev_free(c, L->status);
   for (RecPhase& P : L->ph) {
-    DevBuf* pb[] = {&P.layout, &P.cnt, &P.iflag, &P.lcnt};
-    for (DevBuf* b : pb) dev_free(c, *b);
     if (P.stage) (void)hipHostFree(P.stage);
     P.stage = nullptr;
   }
-  for (DevBuf* b : bufs) dev_free(c, *b);
   for (hipEvent_t e : L->ev_pool) (void)hipEventDestroy(e);
   L->ev_pool.clear();
   if (L->q_start) (void)hipEventDestroy(L->q_start);
@@ -207,6 +231,8 @@ hipEvent_t next_event(Lane* L) {
   return L->ev_pool[L->ev_used++];
 }
 
+uint32_t timing_mask(const Lane* L) { return L->no_alloc ? 0u : L->ctx->timing.load(); }
+
 // Brackets the launches of its scope with events on the lane's stream while
 // timing is enabled.
 struct Timed {
@@ -215,7 +241,7 @@ struct Timed {
   hipEvent_t a = nullptr;
   Timed(Lane* L_, int kind_, int level_ = -1, int run_ = -1)
       : L(L_), kind(kind_), level(level_), run(run_) {
-    if ((L->ctx->timing.load() >> kind) & 1u) {
+    if ((timing_mask(L) >> kind) & 1u) {
       a = next_event(L);
       if (a) (void)hipEventRecord(a, L->stream);
     }
@@ -414,6 +440,14 @@ int acquire_view(Lane* L, double alpha) {
   L->view = v.get();
   c->views.push_back(std::move(v));
   return RAKS_OK;
+}
+
+bool view_ready(Ctx* c, double alpha) {
+  if (alpha == 0.0 || alpha == c->alpha) return true;
+  std::lock_guard<std::mutex> lk(c->view_mu);
+  for (auto& v : c->views)
+    if (v->alpha == alpha) return true;
+  return false;
 }
 
 void release_view(Lane* L) {
@@ -626,7 +660,7 @@ int run_levels(Lane* L, RunView& r, int TP, const std::vector<int32_t>& kws, int
       want[slot] = ++L->ctl_seq;
       launch_front_enqueue(r, TP, level, &L->d_run[slot], want[slot], s);
     }
-    if (c->timing.load() & 1u) {
+    if (timing_mask(L) & 1u) {
       // expansion timing: the launch itself stamps the two events
       hipEvent_t a = next_event(L), b = next_event(L);
       launch_expand(r, TP, g, level, grid, s, a, b);
@@ -643,7 +677,7 @@ int run_levels(Lane* L, RunView& r, int TP, const std::vector<int32_t>& kws, int
     if (level + 1 <= r.max_level) RAKS_TRY(enqueue(level + 1, slot ^ 1));
     RAKS_TRY(wait_status(L, slot, want[slot]));
     const RunStatus rs = L->h_run[slot];
-    if (c->timing.load()) {
+    if (timing_mask(L)) {
       for (auto& pe : L->pending) {
         if (pe.kind != 0 || pe.level != level || pe.run != r.kind) continue;
         if (rs.end_level == INT32_MAX) {
@@ -680,15 +714,19 @@ uint32_t dense_words(const Ctx* c) { return (uint32_t)(((uint64_t)c->n + 31) / 3
 
 // Initial capacities for a phase of n_res results with T instances each.
 void phase_reset(const Ctx* c, RecPhase& P, int n_res, int T) {
+  phase_reset(P, n_res, T, c->rec_nc0, c->rec_ac0, c->rec_lcap0);
+}
+
+void phase_reset(RecPhase& P, int n_res, int T, uint32_t nc0, uint32_t ac0, uint32_t lc0) {
   const int n_inst = n_res * T;
   if (!P.grown && P.n_res == n_res && P.T == T && P.lcap) return;
   P.n_inst = n_inst;
   P.n_res = n_res;
   P.T = T;
-  P.ncap.assign(n_inst, c->rec_nc0);
-  P.acap.assign(n_inst, c->rec_ac0);
+  P.ncap.assign(n_inst, nc0);
+  P.acap.assign(n_inst, ac0);
   P.dense.assign(n_inst, 0);
-  P.lcap = c->rec_lcap0;
+  P.lcap = lc0;
   P.grown = false;
   P.dirty = true;
 }
@@ -1089,6 +1127,31 @@ int stage_output(Lane* L, const QueryPlan& p, const QueryRun& q) {
 // rest of the output only when it is larger.  *ovf receives the overflow
 // bits (1 CG recovery, 2 RPG recovery, 4 output arena); results are built
 // only when it is 0.
+// Work counters, end reasons, device time and status bits of a finished query.
+void fill_stats(Lane* L, const QueryPlan& p, const Status& hs, raks_query_stats* st,
+                int32_t* status) {
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, L->q_start, L->q_end);
+  const int nsel = hs.nsel;
+  for (int k = 0; k < 2; ++k) {
+    const RunStatus& rs = hs.run[k];
+    const bool ran = (k == 0) || (p.M > 0 && nsel > 0);
+    st->levels[k] = ran ? rs.levels : 0;
+    st->end_reason[k] = ran ? rs.end_reason : END_NONE;
+    st->frontier[k] = ran ? (int64_t)rs.frontier_sum : 0;
+    st->e_arc[k] = ran ? (int64_t)rs.e_arc : 0;
+    st->e_alg[k] = ran ? (int64_t)rs.e_alg : 0;
+    st->gate_pass[k] = ran ? (int64_t)rs.gate_pass : 0;
+    st->h_writes[k] = ran ? (int64_t)rs.h_writes : 0;
+  }
+  st->n_cg = (int32_t)hs.run[0].ncand_total;
+  st->device_ms = ms;
+  int bits = 0;
+  if (hs.run[0].end_reason == END_LEVEL_BOUND) bits |= RAKS_STATUS_CG_LEVEL_BOUND;
+  if (p.M > 0 && nsel > 0 && hs.run[1].end_reason == END_LEVEL_BOUND) bits |= RAKS_STATUS_RPG_LEVEL_BOUND;
+  *status = bits;
+}
+
 int collect(Lane* L, const QueryPlan& p, raks_results** out, int* ovf) {
   Ctx* c = L->ctx;
   hipStream_t s = L->stream;
@@ -1113,7 +1176,7 @@ int collect(Lane* L, const QueryPlan& p, raks_results** out, int* ovf) {
   const Status hs = *L->h_status;
   *ovf = hs.overflow;
   if (hs.overflow) {
-    if (c->timing.load()) harvest_timing(L);
+    if (timing_mask(L)) harvest_timing(L);
     return RAKS_OK;
   }
   const int nres = hs.nres, nsel = hs.nsel;
@@ -1175,26 +1238,8 @@ int collect(Lane* L, const QueryPlan& p, raks_results** out, int* ovf) {
       return fail(RAKS_EDEVICE, std::string("result copy: ") + hipGetErrorString(e));
     }
   }
-  float ms = 0;
-  (void)hipEventElapsedTime(&ms, L->q_start, L->q_end);
-  if (c->timing.load()) harvest_timing(L);
-  for (int k = 0; k < 2; ++k) {
-    const RunStatus& rs = hs.run[k];
-    const bool ran = (k == 0) || (p.M > 0 && nsel > 0);
-    res->stats.levels[k] = ran ? rs.levels : 0;
-    res->stats.end_reason[k] = ran ? rs.end_reason : END_NONE;
-    res->stats.frontier[k] = ran ? (int64_t)rs.frontier_sum : 0;
-    res->stats.e_arc[k] = ran ? (int64_t)rs.e_arc : 0;
-    res->stats.e_alg[k] = ran ? (int64_t)rs.e_alg : 0;
-    res->stats.gate_pass[k] = ran ? (int64_t)rs.gate_pass : 0;
-    res->stats.h_writes[k] = ran ? (int64_t)rs.h_writes : 0;
-  }
-  res->stats.n_cg = (int32_t)hs.run[0].ncand_total;
-  res->stats.device_ms = ms;
-  int status = 0;
-  if (hs.run[0].end_reason == END_LEVEL_BOUND) status |= RAKS_STATUS_CG_LEVEL_BOUND;
-  if (p.M > 0 && nsel > 0 && hs.run[1].end_reason == END_LEVEL_BOUND) status |= RAKS_STATUS_RPG_LEVEL_BOUND;
-  res->status = status;
+  if (timing_mask(L)) harvest_timing(L);
+  fill_stats(L, p, hs, &res->stats, &res->status);
   *out = res;
   return RAKS_OK;
 }
@@ -1203,13 +1248,31 @@ int collect(Lane* L, const QueryPlan& p, raks_results** out, int* ovf) {
 // at the end.  When a recovery capacity ran out, only that phase is repeated
 // (the CG phase together with everything after it, since V_C feeds the
 // marginal run), with the overflowing instances grown.
-int query_plan_on_lane(Lane* L, const QueryPlan& p, raks_results** out, double t0) {
+int query_plan_on_lane(Lane* L, const QueryPlan& p, raks_results** out, raks_results_buf* buf,
+                       double t0) {
   Ctx* c = L->ctx;
+  auto gather = [&](int* ovf) { return buf ? collect_into(L, p, buf, ovf) : collect(L, p, out, ovf); };
   RAKS_TRY(ensure_node_buffers(L));
   RAKS_TRY(dev_alloc(c, L->Hc, (size_t)L->n_pad * p.TPc));
   if (p.M > 0) RAKS_TRY(dev_alloc(c, L->Hm, (size_t)L->n_pad * p.TPm));
-  phase_reset(c, L->ph[0], p.w, p.C);
-  phase_reset(c, L->ph[1], p.n_build, p.M);
+  if (L->no_alloc) {
+    // the context's initial recovery capacities, halved until both phases'
+    // first layouts take at most a quarter of the scratch (they grow on
+    // demand like any lane's)
+    uint32_t nc = c->rec_nc0, ac = c->rec_ac0, lc = c->rec_lcap0;
+    const uint64_t inst = (uint64_t)p.w * p.C + (uint64_t)p.n_build * std::max(p.M, 1);
+    const uint64_t share = c->na_scratch_bytes / 4;
+    while ((nc > 64 || ac > 64) && inst * (32ull * nc + 24ull * ac) > share) {
+      nc = std::max(64u, nc / 2);
+      ac = std::max(64u, ac / 2);
+    }
+    while (lc > 1024 && (uint64_t)(p.L + 1) * lc * sizeof(RecItem) > share / 2) lc /= 2;
+    phase_reset(L->ph[0], p.w, p.C, nc, ac, lc);
+    phase_reset(L->ph[1], p.n_build, p.M, nc, ac, lc);
+  } else {
+    phase_reset(c, L->ph[0], p.w, p.C);
+    phase_reset(c, L->ph[1], p.n_build, p.M);
+  }
   QueryRun qr;
   RAKS_TRY(ensure_recovery(L, p));   // before any kernel of this query is queued
   RAKS_TRY(stage_central(L, p, qr));
@@ -1217,7 +1280,7 @@ int query_plan_on_lane(Lane* L, const QueryPlan& p, raks_results** out, double t
   RAKS_TRY(stage_marginal(L, p, qr));
   RAKS_TRY(stage_output(L, p, qr));
   int ovf = 0;
-  RAKS_TRY(collect(L, p, out, &ovf));
+  RAKS_TRY(gather(&ovf));
   for (int attempt = 1; ovf; ++attempt) {
     if (attempt >= kMaxAttempts)
       return fail(RAKS_ENOMEM, "recovered subgraphs exceed the recovery capacity");
@@ -1229,7 +1292,7 @@ int query_plan_on_lane(Lane* L, const QueryPlan& p, raks_results** out, double t
       RAKS_TRY(big_finalize(L, 1, p, p.n_build, P<uint8_t>(L->Hc), p.TPc));
       if (p.rerank) launch_rerank(P<ResultHdr>(L->hdr), P<Status>(L->status), p.k, L->stream);
       HIP_OK(hipEventRecord(L->q_end, L->stream));
-      RAKS_TRY(collect(L, p, out, &ovf));
+      RAKS_TRY(gather(&ovf));
       continue;
     }
     if (ovf & 1) RAKS_TRY(grow_phase(L, 0, L->h_status->nsel, qr.top1));
@@ -1242,9 +1305,9 @@ int query_plan_on_lane(Lane* L, const QueryPlan& p, raks_results** out, double t
       RAKS_TRY(stage_marginal(L, p, qr));
     }
     RAKS_TRY(stage_output(L, p, qr));
-    RAKS_TRY(collect(L, p, out, &ovf));
+    RAKS_TRY(gather(&ovf));
   }
-  (*out)->stats.host_ms = now_ms() - t0;
+  (buf ? &buf->stats : &(*out)->stats)->host_ms = now_ms() - t0;
   return RAKS_OK;
 }
 
@@ -1257,7 +1320,23 @@ int query_on_lane(Lane* L, const raks_query_desc* q, raks_results** out) {
   QueryPlan p;
   RAKS_TRY(validate_query(c, q, p));
   RAKS_TRY(acquire_view(L, p.alpha));
-  const int rc = query_plan_on_lane(L, p, out, t0);
+  const int rc = query_plan_on_lane(L, p, out, nullptr, t0);
+  release_view(L);
+  return rc;
+}
+
+int query_on_lane_into(Lane* L, const raks_query_desc* q, raks_results_buf* out) {
+  Ctx* c = L->ctx;
+  if (!c->loaded) return fail(RAKS_ESTATE, "no graph loaded");
+  const double t0 = now_ms();
+  QueryPlan p;
+  RAKS_TRY(validate_query(c, q, p));
+  if (out->cap_results < p.k) return fail(RAKS_EINVAL, "cap_results is smaller than k");
+  if (!view_ready(c, p.alpha))
+    return fail(RAKS_ESTATE, "the levels of this query's alpha are not built (a query with "
+                             "that alpha through raks_query builds them)");
+  RAKS_TRY(acquire_view(L, p.alpha));
+  const int rc = query_plan_on_lane(L, p, nullptr, out, t0);
   release_view(L);
   return rc;
 }
@@ -1396,7 +1475,8 @@ int raks_create(raks_ctx** out, const raks_ctx_opts* opts) {
   if (o.rec_arcs) c->rec_ac0 = o.rec_arcs;
   if (o.rec_chunks) c->rec_lcap0 = o.rec_chunks;
   if (o.big_list) c->big_list = o.big_list;
-  const int rc = ensure_lanes(c, std::max(1, (int)o.lanes));
+  int rc = ensure_lanes(c, std::max(1, (int)o.lanes));
+  if (rc == RAKS_OK) rc = noalloc_setup(c);
   if (rc) {
     const std::string msg = g_err;
     raks_destroy(c);
@@ -1413,6 +1493,8 @@ int raks_destroy(raks_ctx* c) {
   cohort_destroy(c);
   for (auto& L : c->lanes) lane_destroy(c, L.get());
   c->lanes.clear();
+  if (c->na_lane) lane_destroy(c, c->na_lane.get());
+  c->na_lane.reset();
   drop_views(c);
   free_view(c, c->base);
   DevBuf* bufs[] = {&c->row_ptr, &c->col, &c->label, &c->nw, &c->kw_nodes, &c->arc_src,

@@ -30,6 +30,7 @@ constexpr int kMaxViews = 4;       // cached activation views for per-query alph
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool borrowed = false;   // a slice of the allocation-free scratch: never freed
 };
 
 template <typename T>
@@ -81,6 +82,7 @@ struct Lane {
   hipStream_t stream = nullptr;
   const AlphaView* view = nullptr;   // activation levels of the current query
   bool own_stream = false;
+  bool no_alloc = false;   // the allocation-free lane: no event timing, buffers from scratch
 
   int32_t n_pad = 0, nblocks = 0, cpw = 1;
   DevBuf Hc, Hm, R, tot, sb, q_off, q_rs, q_lo, q_mask, tile_first, cand, s_item, s_cand;
@@ -176,6 +178,9 @@ struct Ctx {
   std::vector<int64_t> kw_ptr;
 
   std::vector<std::unique_ptr<Lane>> lanes;
+  std::unique_ptr<Lane> na_lane;   // the lane of raks_query_noalloc (made at raks_create)
+  void* na_scratch = nullptr;      // that lane's device scratch (the device's static array)
+  size_t na_scratch_bytes = 0;
   // batches and serving: 0 = cohort engine (many queries in one level loop),
   // 1 = independent single-query runs on the lanes
   int32_t batch_mode = 0;

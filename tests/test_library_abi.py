@@ -62,6 +62,7 @@ LAYOUT_STRUCTS = {
     "raks_query_desc": "QueryDesc", "raks_arc": "Arc", "raks_result": "Result",
     "raks_query_stats": "QueryStats", "raks_results": "Results",
     "raks_kernel_timing": "KernelTiming", "raks_tuning": "Tuning",
+    "raks_results_buf": "ResultsBuf",
 }
 
 
