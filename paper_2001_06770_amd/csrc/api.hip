@@ -145,7 +145,8 @@ std::vector<DevBuf*> lane_buffers(Lane* L) {
       &L->sort_b, &L->cg_nodes, &L->cg_arcs, &L->cg_cnt, &L->hdr, &L->out_nodes, &L->out_arcs,
       &L->bigf, &L->big_bm, &L->big_chunk, &L->big_slot};
   for (RecPhase& P : L->ph)
-    for (DevBuf* b : {&P.layout, &P.cnt, &P.iflag, &P.lcnt}) v.push_back(b);
+    for (DevBuf* b : {&P.layout, &P.cnt, &P.iflag, &P.lcnt, &P.touch, &P.tcnt}) v.push_back(b);
+  v.push_back(&L->lab);
   return v;
 }
 
@@ -703,6 +704,9 @@ int run_levels(Lane* L, RunView& r, int TP, const std::vector<int32_t>& kws, int
 // ------------------------------------------------------------ recovery ---
 
 constexpr int kMaxAttempts = 24;
+// a phase whose instances counted more nodes than this in all (or whose node
+// tables filled up) is repeated in the labelled mode
+constexpr uint64_t kLabelNodes = 1u << 16;
 
 uint32_t pow2_at_least(uint64_t x) {
   uint32_t h = 64;
@@ -727,6 +731,8 @@ void phase_reset(RecPhase& P, int n_res, int T, uint32_t nc0, uint32_t ac0, uint
   P.acap.assign(n_inst, ac0);
   P.dense.assign(n_inst, 0);
   P.lcap = lc0;
+  P.labelled = false;
+  P.tcap = 0;
   P.grown = false;
   P.dirty = true;
 }
@@ -740,14 +746,15 @@ void phase_layout(const Ctx* c, RecPhase& P, const RecPhase* cg_phase) {
   uint64_t h = 0, nn = 0, aa = 0;
   for (int i = 0; i < P.n_inst; ++i) {
     InstCap& ic = P.caps[i];
-    ic.dense = P.dense[i];
-    ic.hcap = ic.dense ? 0u : pow2_at_least(2ull * P.ncap[i]);
+    // the labelled mode keeps no per-instance node sets
+    ic.dense = P.labelled ? 0 : P.dense[i];
+    ic.hcap = (ic.dense || P.labelled) ? 0u : pow2_at_least(2ull * P.ncap[i]);
     ic.ncap = P.ncap[i];
     ic.acap = P.acap[i];
     ic.hoff = h;
     ic.noff = nn;
     ic.aoff = aa;
-    h += ((ic.dense ? (uint64_t)dw : (uint64_t)ic.hcap) + 63) & ~uint64_t(63);
+    if (!P.labelled) h += ((ic.dense ? (uint64_t)dw : (uint64_t)ic.hcap) + 63) & ~uint64_t(63);
     nn += ic.ncap;
     aa += ic.acap;
   }
@@ -789,6 +796,10 @@ int phase_upload(Lane* L, RecPhase& P, int max_level) {
   RAKS_TRY(dev_alloc(c, P.cnt, (size_t)std::max(P.n_inst, 1) * 8));
   RAKS_TRY(dev_alloc(c, P.iflag, (size_t)std::max(P.n_inst, 1) * 4));
   RAKS_TRY(dev_alloc(c, P.lcnt, (size_t)(max_level + 1) * 4));
+  if (P.labelled) {
+    RAKS_TRY(dev_alloc(c, P.touch, (size_t)std::max<uint32_t>(P.tcap, 1) * 8));
+    RAKS_TRY(dev_alloc(c, P.tcnt, 4));
+  }
   if (!P.dirty) return RAKS_OK;
   const size_t nr = (size_t)P.n_res + 1;
   P.lay_cg_noff = ((size_t)P.n_inst * sizeof(InstCap) + 63) & ~size_t(63);
@@ -847,6 +858,15 @@ int ensure_recovery(Lane* L, const QueryPlan& p) {
   RAKS_TRY(dev_alloc(c, L->bigf, (size_t)std::max({P0.n_res, P1.n_res, 1}) * 4));
   RAKS_TRY(dev_alloc(c, L->out_nodes, std::max<uint64_t>(P1.out_n, 1) * 4));
   RAKS_TRY(dev_alloc(c, L->out_arcs, std::max<uint64_t>(P1.out_a, 1) * 12));
+  // labels of the labelled mode: [T * G][n] words for the larger phase
+  uint64_t lw = 0;
+  for (const RecPhase* P : {&P0, &P1})
+    if (P->labelled) lw = std::max<uint64_t>(lw, (uint64_t)P->T * ((P->n_res + 63) / 64) * c->n);
+  if (lw) {
+    const void* before = L->lab.p;
+    RAKS_TRY(dev_alloc(c, L->lab, lw * 8));
+    if (L->lab.p != before) L->lab_dirty = true;
+  }
   return RAKS_OK;
 }
 
@@ -867,16 +887,23 @@ int grow_phase(Lane* L, int ph, int n_valid, int max_layer) {
     HIP_OK(hipMemcpyAsync(fl.data(), P.iflag.p, (size_t)live * 4, hipMemcpyDeviceToHost, s));
   }
   HIP_OK(hipMemcpyAsync(lc.data(), P.lcnt.p, (size_t)layers * 4, hipMemcpyDeviceToHost, s));
+  uint32_t tc = 0;
+  if (P.labelled) HIP_OK(hipMemcpyAsync(&tc, P.tcnt.p, 4, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   uint32_t lmax = 0;
   for (int h = 1; h < layers; ++h) lmax = std::max(lmax, lc[h]);
   const bool chunks_fit = lmax <= P.lcap;
   const uint32_t dw = dense_words(c);
+  uint64_t counted = 0;
+  bool lost = false;
   for (int i = 0; i < live; ++i) {
     const uint32_t cn = cnt[2 * i], ca = cnt[2 * i + 1];
+    counted += cn;
+    lost |= fl[i] != 0;
     if (cn <= P.ncap[i] && ca <= P.acap[i] && !fl[i]) continue;
-    // a bitmap instance that lost no work chunk counted exactly
-    const bool exact = P.dense[i] && !fl[i] && chunks_fit;
+    // a bitmap instance that lost no work chunk counted exactly, and so did a
+    // labelled search that lost neither chunks nor labelled nodes
+    const bool exact = P.labelled ? (chunks_fit && tc <= P.tcap) : (P.dense[i] && !fl[i] && chunks_fit);
     const uint64_t wn = exact ? cn + cn / 8 + 64 : 2ull * std::max(P.ncap[i], cn);
     const uint64_t wa = exact ? ca + ca / 8 + 64 : 2ull * std::max(P.acap[i], ca);
     const uint64_t nn = std::min<uint64_t>((uint64_t)c->n, std::max<uint64_t>(wn, P.ncap[i]));
@@ -885,6 +912,21 @@ int grow_phase(Lane* L, int ph, int n_valid, int max_layer) {
     P.ncap[i] = (uint32_t)nn;
     P.acap[i] = (uint32_t)na;
     if (fl[i] || pow2_at_least(2ull * nn) >= dw) P.dense[i] = 1;
+  }
+  const uint64_t lab_entries = (uint64_t)P.T * ((P.n_res + 63) / 64) * (uint64_t)c->n;
+  if (P.labelled) {
+    if (tc > P.tcap) {
+      // labelled nodes were lost, and their labels were not cleared
+      P.tcap = (uint32_t)std::min<uint64_t>({lab_entries, 2ull * tc, 1ull << 31});
+      L->lab_dirty = true;
+    }
+  } else if (lost || counted > kLabelNodes) {
+    // large instances: one search per keyword column from now on; a node
+    // labelled in a column is in at least one instance's node list
+    P.labelled = true;
+    uint64_t sum = 0;
+    for (int i = 0; i < P.n_inst; ++i) sum += P.ncap[i];
+    P.tcap = (uint32_t)std::min<uint64_t>({lab_entries, std::max<uint64_t>(sum, 1024), 1ull << 31});
   }
   // a layer holds at most every node's chunks once per instance
   const uint64_t bound = (uint64_t)std::max(live, 1) *
@@ -925,6 +967,16 @@ RecoverView recover_view(Lane* L, int ph, const uint8_t* H, int TP, const int32_
   v.max_layer = max_layer;
   v.ovf_bit = ph == 0 ? 1 : 2;
   v.gst = P<Status>(L->status);
+  if (Ph.labelled) {
+    v.labelled = 1;
+    v.G = (Ph.n_res + 63) / 64;
+    v.wipe = L->lab_dirty ? 1 : 0;
+    L->lab_dirty = false;   // the launch clears it first
+    v.lab = P<uint64_t>(L->lab);
+    v.touch = P<uint64_t>(Ph.touch);
+    v.tcnt = P<uint32_t>(Ph.tcnt);
+    v.tcap = Ph.tcap;
+  }
   return v;
 }
 

@@ -168,6 +168,14 @@ struct RecoverView {
   int32_t max_layer;
   int32_t ovf_bit;           // bit set in gst->overflow when a capacity runs out
   Status* gst;
+  // labelled mode: one search per keyword column serves up to 64 results
+  int32_t labelled;
+  int32_t G;                 // label words per node and column (results / 64, rounded up)
+  int32_t wipe;              // clear all of `lab` first (it may hold stale bits)
+  uint64_t* lab;             // [T * G][n] result bits per node; zero outside a phase
+  uint64_t* touch;           // [tcap] (column group << 32) | node, per labelled node
+  uint32_t* tcnt;            // entries of `touch` requested (counted past tcap)
+  uint32_t tcap;
 };
 
 // Union, sort and unique per result.

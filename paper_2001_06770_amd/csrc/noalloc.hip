@@ -167,6 +167,7 @@ extern "C" int raks_query_noalloc(raks_ctx* c, const raks_query_desc* q, raks_re
   // from its start and initialised by the query's own kernels, and the
   // recovery capacities restart from the context's initial values
   for (DevBuf* b : lane_buffers(L)) *b = DevBuf();
+  L->lab_dirty = true;
   for (RecPhase& P : L->ph) {
     P.grown = true;
     P.dirty = true;

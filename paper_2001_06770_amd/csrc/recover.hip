@@ -36,43 +36,12 @@ __device__ inline bool ht_insert(uint32_t* ht, uint32_t hc, uint32_t key, int* f
   return false;
 }
 
-// Lanes with `act` set have recovered node n (hitting level hn in instance
-// inst's column): record each node once per instance and queue its arcs on
-// layer hn.  Called by all lanes of a wavefront together (the counters are
-// bumped once per wavefront, not once per lane: every wave of a large
-// instance would otherwise queue on the same two addresses).
-__device__ inline void rec_discover(const RecoverView& v, bool act, uint32_t inst,
-                                    const InstCap& ic, int32_t n, uint32_t hn) {
+// Lanes with `fresh` set queue the in-arcs of node n (hitting level hn) that
+// can be recovered arcs as work chunks of layer hn, tagged `inst`.  Called by
+// all lanes of a wavefront together.
+__device__ inline void rec_queue(const RecoverView& v, bool fresh, uint32_t inst, int32_t n,
+                                 uint32_t hn) {
   const int lane = lane_id();
-  const uint64_t below = (1ull << lane) - 1;
-  bool fresh = false;
-  if (act) {
-    if (ic.dense) {
-      uint32_t* w = v.hpool + ic.hoff + ((uint32_t)n >> 5);
-      const uint32_t bit = 1u << ((uint32_t)n & 31u);
-      fresh = (atomicOr(w, bit) & bit) == 0;
-    } else {
-      int full = 0;
-      fresh = ht_insert(v.hpool + ic.hoff, ic.hcap, (uint32_t)n, &full);
-      if (full) {
-        v.iflag[inst] = 1;
-        atomicOr(&v.gst->overflow, v.ovf_bit);
-      }
-    }
-  }
-  // node list slots
-  const uint64_t fb = __ballot(fresh);
-  if (fb == 0) return;
-  const int lead = __ffsll((unsigned long long)fb) - 1;
-  uint32_t base = 0;
-  if (lane == lead) base = atomicAdd(&v.cnt[inst * 2], (uint32_t)__popcll(fb));
-  base = __shfl(base, lead, kWave);
-  if (fresh) {
-    const uint32_t slot = base + (uint32_t)__popcll(fb & below);
-    if (slot < ic.ncap) v.nl[ic.noff + slot] = n;
-    else atomicOr(&v.gst->overflow, v.ovf_bit);
-  }
-  // work chunks, grouped by layer
   uint32_t k = 0, rs = 0, deg = 0;
   if (fresh && hn >= 1 && (int)hn <= v.max_layer) {
     // in-arcs m -> n that can meet h_n = 1 + max(a, h_m) have a <= h_n - 1:
@@ -112,6 +81,45 @@ __device__ inline void rec_discover(const RecoverView& v, bool act, uint32_t ins
     }
     pend &= ~grp;
   }
+}
+
+// Lanes with `act` set have recovered node n (hitting level hn in instance
+// inst's column): record each node once per instance and queue its arcs on
+// layer hn.  Called by all lanes of a wavefront together (the counters are
+// bumped once per wavefront, not once per lane: every wave of a large
+// instance would otherwise queue on the same two addresses).
+__device__ inline void rec_discover(const RecoverView& v, bool act, uint32_t inst,
+                                    const InstCap& ic, int32_t n, uint32_t hn) {
+  const int lane = lane_id();
+  const uint64_t below = (1ull << lane) - 1;
+  bool fresh = false;
+  if (act) {
+    if (ic.dense) {
+      uint32_t* w = v.hpool + ic.hoff + ((uint32_t)n >> 5);
+      const uint32_t bit = 1u << ((uint32_t)n & 31u);
+      fresh = (atomicOr(w, bit) & bit) == 0;
+    } else {
+      int full = 0;
+      fresh = ht_insert(v.hpool + ic.hoff, ic.hcap, (uint32_t)n, &full);
+      if (full) {
+        v.iflag[inst] = 1;
+        atomicOr(&v.gst->overflow, v.ovf_bit);
+      }
+    }
+  }
+  // node list slots
+  const uint64_t fb = __ballot(fresh);
+  if (fb == 0) return;
+  const int lead = __ffsll((unsigned long long)fb) - 1;
+  uint32_t base = 0;
+  if (lane == lead) base = atomicAdd(&v.cnt[inst * 2], (uint32_t)__popcll(fb));
+  base = __shfl(base, lead, kWave);
+  if (fresh) {
+    const uint32_t slot = base + (uint32_t)__popcll(fb & below);
+    if (slot < ic.ncap) v.nl[ic.noff + slot] = n;
+    else atomicOr(&v.gst->overflow, v.ovf_bit);
+  }
+  rec_queue(v, fresh, inst, n, hn);
 }
 
 // Clears the node sets and counters of the live instances: row y of the grid
@@ -208,6 +216,184 @@ __global__ __launch_bounds__(kBlock) void k_rec_layer(RecoverView v, int h) {
         else atomicOr(&v.gst->overflow, v.ovf_bit);
       }
       rec_discover(v, take, item.inst, ic, n, hn);
+    }
+  }
+}
+
+// ------------------------------------------------------ labelled mode
+//
+// The instances of one keyword column differ only in their start nodes, and a
+// search from a set of start nodes reaches the union of what the searches
+// from each of them reach, over the same recovered arcs.  So one search per
+// column (and group of 64 results) stands for all of the column's instances:
+// every reached node carries a label with one bit per result whose search
+// reaches it, and a recovered arc n -> q passes q's label on to n.  A node of
+// layer h gets bits only from nodes of higher layers, so its label is final
+// when layer h runs: its recovered in-arcs are then written to the arc list of
+// every result in the label.  The node lists are written from the final
+// labels once the last layer has run, which also clears them.  Each
+// instance's lists hold the same sets as in the per-instance search; the work
+// is that of the column's union instead of the sum of its instances.
+
+__device__ inline uint64_t* lab_row(const RecoverView& v, uint32_t jg) {
+  return v.lab + (size_t)jg * (uint32_t)v.g.n;
+}
+
+// Lanes with `fresh` set gave node n its first label bits in column group jg:
+// record (jg, n) for the node pass and queue n's in-arcs on layer hn.
+__device__ inline void lr_fresh(const RecoverView& v, bool fresh, uint32_t jg, int32_t n,
+                                uint32_t hn) {
+  const int lane = lane_id();
+  const uint64_t fb = __ballot(fresh);
+  if (fb == 0) return;
+  const int lead = __ffsll((unsigned long long)fb) - 1;
+  uint32_t base = 0;
+  if (lane == lead) base = atomicAdd(v.tcnt, (uint32_t)__popcll(fb));
+  base = __shfl(base, lead, kWave);
+  if (fresh) {
+    const uint32_t slot = base + (uint32_t)__popcll(fb & ((1ull << lane) - 1));
+    if (slot < v.tcap) v.touch[slot] = ((uint64_t)jg << 32) | (uint32_t)n;
+    else atomicOr(&v.gst->overflow, v.ovf_bit);
+  }
+  rec_queue(v, fresh, jg, n, hn);
+}
+
+__global__ __launch_bounds__(kBlock) void k_lr_clear(RecoverView v, size_t wipe_words) {
+  const uint32_t tid = blockIdx.x * kBlock + threadIdx.x, stride = gridDim.x * kBlock;
+  for (uint32_t i = tid; i < (uint32_t)v.n_inst * 2u; i += stride) v.cnt[i] = 0;
+  for (uint32_t i = tid; i < (uint32_t)v.n_inst; i += stride) v.iflag[i] = 0;
+  for (uint32_t i = tid; i <= (uint32_t)v.max_layer; i += stride) v.lcnt[i] = 0;
+  if (tid == 0) *v.tcnt = 0;
+  for (size_t i = tid; i < wipe_words; i += stride) v.lab[i] = 0;
+}
+
+// Start nodes as in k_rec_seed, labelled with their result's bit.
+template <int TP>
+__global__ __launch_bounds__(kBlock) void k_lr_seed(RecoverView v) {
+  const uint32_t inst = blockIdx.x;
+  const int res = inst / v.T, col = inst % v.T;
+  if (res >= *v.n_valid) return;
+  const uint32_t jg = (uint32_t)(col * v.G + res / 64);
+  const unsigned long long bit = 1ull << (res % 64);
+  unsigned long long* lab = reinterpret_cast<unsigned long long*>(lab_row(v, jg));
+  if (!v.marginal) {
+    if (wave_id() == 0) {
+      const int32_t c = v.sel_node[res];
+      const bool fresh = lane_id() == 0 && atomicOr(&lab[c], bit) == 0;
+      lr_fresh(v, fresh, jg, c, v.H[(int64_t)c * TP + col]);
+    }
+  } else {
+    const int r = v.ranked[res];
+    const uint8_t d = v.dmin[r * kMaxKw + col];
+    const uint32_t p0 = v.vc_off[r], p1 = v.vc_off[r + 1];
+    for (uint32_t p = p0 + (threadIdx.x & ~(uint32_t)(kWave - 1)); p < p1; p += kBlock) {
+      const uint32_t q = p + lane_id();
+      const int32_t x = q < p1 ? v.vc_nodes[q] : 0;
+      const bool act = q < p1 && v.H[(int64_t)x * TP + col] == d;
+      const bool fresh = act && atomicOr(&lab[x], bit) == 0;
+      lr_fresh(v, fresh, jg, x, d);
+    }
+  }
+}
+
+template <int TP>
+__global__ __launch_bounds__(kBlock) void k_lr_layer(RecoverView v, int h) {
+  if (v.lcnt[h] > v.lcap) return;   // as in k_rec_layer: the phase is repeated
+  const uint32_t n_items = v.lcnt[h];
+  const uint32_t waves = gridDim.x * (kBlock / kWave);
+  const int lane = lane_id();
+  const uint64_t below = (1ull << lane) - 1;
+  const RecItem* list = v.items + (size_t)h * v.lcap;
+  const DevGraphView& g = v.g;
+  for (uint32_t it = blockIdx.x * (kBlock / kWave) + wave_id(); it < n_items; it += waves) {
+    const RecItem item = list[it];
+    const uint32_t jg = item.inst;
+    const int col = (int)jg / v.G, grp = (int)jg % v.G;
+    const int32_t q = item.q;
+    unsigned long long* lab = reinterpret_cast<unsigned long long*>(lab_row(v, jg));
+    const uint64_t lq = lab[q];   // final: q is on this layer
+    const uint32_t aq = g.mode ? g.act_node[q] : 0u;
+    for (uint32_t k0 = 0; k0 < item.len; k0 += kWave) {
+      const uint32_t k = k0 + lane;
+      bool take = false;
+      int32_t n = 0;
+      uint32_t hn = 0, fwd = 0;
+      if (k < item.len) {
+        const uint32_t e = item.start + k;
+        const uint32_t a = g.mode ? aq : g.act_s[e];
+        if (a < (uint32_t)h) {
+          n = g.col_s[e];
+          hn = v.H[(int64_t)n * TP + col];
+          take = hn < (uint32_t)h && (a + 1 == (uint32_t)h || hn + 1 == (uint32_t)h);
+          if (take) fwd = g.rev[g.eid_s[e]];
+        }
+      }
+      const uint64_t tb = __ballot(take);
+      if (tb == 0) continue;
+      const int lead = __ffsll((unsigned long long)tb) - 1;
+      const uint32_t cnt = (uint32_t)__popcll(tb), mine = (uint32_t)__popcll(tb & below);
+      // the arc goes to every result whose search reached q
+      for (uint64_t bits = lq; bits; bits &= bits - 1) {
+        const int b = __ffsll((unsigned long long)bits) - 1;
+        const uint32_t inst = (uint32_t)(grp * 64 + b) * (uint32_t)v.T + (uint32_t)col;
+        const InstCap ic = v.caps[inst];
+        uint32_t base = 0;
+        if (lane == lead) base = atomicAdd(&v.cnt[inst * 2 + 1], cnt);
+        base = __shfl(base, lead, kWave);
+        if (take) {
+          if (base + mine < ic.acap) v.al[ic.aoff + base + mine] = fwd;
+          else atomicOr(&v.gst->overflow, v.ovf_bit);
+        }
+      }
+      const bool fresh = take && atomicOr(&lab[n], (unsigned long long)lq) == 0;
+      lr_fresh(v, fresh, jg, n, hn);
+    }
+  }
+}
+
+// Node lists from the final labels; the labels are cleared on the way.
+__global__ __launch_bounds__(kBlock) void k_lr_nodes(RecoverView v) {
+  const uint32_t total = min(*v.tcnt, v.tcap);
+  const uint32_t waves = gridDim.x * (kBlock / kWave);
+  const int lane = lane_id();
+  const uint64_t below = (1ull << lane) - 1;
+  for (uint32_t w0 = (blockIdx.x * (kBlock / kWave) + wave_id()) * kWave; w0 < total;
+       w0 += waves * kWave) {
+    const uint32_t i = w0 + lane;
+    uint32_t jg = 0;
+    int32_t n = 0;
+    uint64_t my = 0;
+    if (i < total) {
+      const uint64_t e = v.touch[i];
+      jg = (uint32_t)(e >> 32);
+      n = (int32_t)(uint32_t)e;
+      uint64_t* lab = lab_row(v, jg);
+      my = lab[n];
+      lab[n] = 0;
+    }
+    // one counter update per (wavefront, instance)
+    for (;;) {
+      const uint64_t act = __ballot(my != 0);
+      if (act == 0) break;
+      const int lead = __ffsll((unsigned long long)act) - 1;
+      const uint32_t ljg = __shfl(jg, lead, kWave);
+      const uint32_t lo = __shfl((uint32_t)my, lead, kWave);
+      const uint32_t hi = __shfl((uint32_t)(my >> 32), lead, kWave);
+      const int b = lo ? __ffs(lo) - 1 : 32 + __ffs(hi) - 1;
+      const bool sel = jg == ljg && ((my >> b) & 1ull);
+      const uint64_t sm = __ballot(sel);
+      const uint32_t inst = (uint32_t)((int)(ljg % (uint32_t)v.G) * 64 + b) * (uint32_t)v.T +
+                            ljg / (uint32_t)v.G;
+      const InstCap ic = v.caps[inst];
+      uint32_t base = 0;
+      if (lane == lead) base = atomicAdd(&v.cnt[inst * 2], (uint32_t)__popcll(sm));
+      base = __shfl(base, lead, kWave);
+      if (sel) {
+        const uint32_t slot = base + (uint32_t)__popcll(sm & below);
+        if (slot < ic.ncap) v.nl[ic.noff + slot] = n;
+        else atomicOr(&v.gst->overflow, v.ovf_bit);
+        my &= ~(1ull << b);
+      }
     }
   }
 }
@@ -580,6 +766,28 @@ __global__ __launch_bounds__(kBlock) void k_pack_vc(const uint32_t* vc_cnt, cons
 
 void launch_recover(const RecoverView& v, hipStream_t s) {
   if (v.n_inst <= 0) return;
+  if (v.labelled) {
+    const size_t wipe = v.wipe ? (size_t)v.T * v.G * (uint32_t)v.g.n : 0;
+    const unsigned gc = wipe ? 4096u : 64u;
+    k_lr_clear<<<gc, kBlock, 0, s>>>(v, wipe);
+    const unsigned grid = 1024;
+    switch (v.TP) {
+      case 4:
+        k_lr_seed<4><<<v.n_inst, kBlock, 0, s>>>(v);
+        for (int h = v.max_layer; h >= 1; --h) k_lr_layer<4><<<grid, kBlock, 0, s>>>(v, h);
+        break;
+      case 8:
+        k_lr_seed<8><<<v.n_inst, kBlock, 0, s>>>(v);
+        for (int h = v.max_layer; h >= 1; --h) k_lr_layer<8><<<grid, kBlock, 0, s>>>(v, h);
+        break;
+      default:
+        k_lr_seed<16><<<v.n_inst, kBlock, 0, s>>>(v);
+        for (int h = v.max_layer; h >= 1; --h) k_lr_layer<16><<<grid, kBlock, 0, s>>>(v, h);
+        break;
+    }
+    k_lr_nodes<<<grid, kBlock, 0, s>>>(v);
+    return;
+  }
   // enough blocks per instance for a dense node set; tables of sparse ones
   // are small
   const unsigned gx = (unsigned)std::min<size_t>(64, ((size_t)v.dwords + kBlock - 1) / kBlock + 1);

@@ -72,6 +72,11 @@ struct RecPhase {
   void* stage = nullptr;                          // pinned staging of the layout
   size_t stage_bytes = 0;
   DevBuf cnt, iflag, lcnt;                        // device counters of the phase
+  // labelled mode (one search per keyword column for all results): chosen
+  // after a first attempt found large or overflowing instances
+  bool labelled = false;
+  uint32_t tcap = 0;                              // capacity of the labelled-node list
+  DevBuf touch, tcnt;
 };
 
 // Everything one query needs besides the graph.  A lane runs one query at a
@@ -95,6 +100,8 @@ struct Lane {
   DevBuf Hq;                          // cohort path: the query's hitting levels, [n_pad][16]
   DevBuf bigf, big_bm, big_chunk, big_slot;   // bitmap path of large results
   RecPhase ph[2];                     // [0] CG recovery, [1] RPG recovery + output
+  DevBuf lab;                         // labels of the labelled mode, [T * G][n] words
+  bool lab_dirty = true;              // lab may hold non-zero words
   Status* h_status = nullptr;   // pinned
   RunStatus* h_run = nullptr;   // pinned [2]: per-level status, double-buffered
   uint64_t ctl_seq = 0;         // control launches so far (stamps of h_run)
