@@ -9,8 +9,11 @@ the node list (int32 little-endian) and of the arc list ((src, dst, label)
 int32 triples), so the GPU tests can check full-size outputs without running
 the reference at those sizes during the test.
 
-usage: python tests/golden/make_golden.py large [n_queries] [--shard K/N PART_FILE]
+usage: python tests/golden/make_golden.py large [n_queries] [--node] [--shard K/N PART_FILE]
        python tests/golden/make_golden.py merge large PART_FILE...
+
+--node uses NODE activation (levels from the node weights) and writes
+tests/golden/<workload>_node_queries.json.
 
 With --shard, only every N-th sampled query starting at K is run and the
 entries go to PART_FILE; merge combines the parts of all N shards into
@@ -79,6 +82,7 @@ def main():
         return
     name = sys.argv[1]
     count = int(sys.argv[2]) if len(sys.argv) > 2 and not sys.argv[2].startswith("--") else 8
+    node = "--node" in sys.argv
     shard, part = None, None
     if "--shard" in sys.argv:
         i = sys.argv.index("--shard")
@@ -89,7 +93,10 @@ def main():
     print(f"graph {name}: {g.n_nodes} nodes {g.n_arcs} arcs abar {g.abar} "
           f"({time.time() - t0:.0f} s)", flush=True)
     o = oracle.Oracle(g, check=False)
-    act = o.activation(g.abar, 0.5)
+    if node:
+        act = o.activation(g.abar, 0.5, oracle.MODE_NODE)[0]
+    else:
+        act = o.activation(g.abar, 0.5)
     act_sha = hashlib.sha256(np.ascontiguousarray(act, np.uint8).tobytes()).hexdigest()
     print(f"activation levels ({time.time() - t0:.0f} s)", flush=True)
     qs = synth.make_queries(g, name)
@@ -99,6 +106,8 @@ def main():
         picked = picked[shard[0]::shard[1]]
     out = {"workload": name, "alpha": 0.5, "abar_x100": g.abar_x100, "n_arcs": g.n_arcs,
            "act_sha256": act_sha, "queries": []}
+    if node:
+        out["mode"] = "node"
     for i in picked:
         q = qs[i]
         t1 = time.time()
@@ -115,7 +124,7 @@ def main():
             json.dump(out, f)
         print(f"wrote {part}")
     else:
-        print(f"wrote {write(name, out)} ({time.time() - t0:.0f} s total)")
+        print(f"wrote {write(name + ('_node' if node else ''), out)} ({time.time() - t0:.0f} s total)")
 
 
 if __name__ == "__main__":

@@ -5,7 +5,7 @@ against expected values the reference implementation wrote
 core, too long to run beside the GPU).  Checked bit-exactly: the SHA-256 of
 all activation levels, and per sampled query the status, the counters of both
 runs and every result (central node, scores, key, sizes, SHA-256 of the node
-and arc lists).  The batch workload's sample runs as one batch over 4 lanes."""
+and arc lists)."""
 from __future__ import annotations
 
 import hashlib
@@ -51,6 +51,10 @@ def expected(entry):
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("name", ["large", "batch", "serve"])
 def test_full_size_golden(name):
+    """large: every sampled query alone and as one cohort batch; batch: all
+    256 queries of the workload as one cohort batch; serve: 32 queries alone,
+    then served in a mix (submitted in two waves, the second while the first
+    runs), each equal to the reference and to its alone run."""
     import paper_2001_06770_amd as raks
     gold = golden(name)
     print(f"[golden] generating {name}", flush=True)
@@ -65,13 +69,54 @@ def test_full_size_golden(name):
             del act
         qs = [synth.Query(tuple(e["central"]), tuple(e["marginal"]), e["k"], e["w"],
                           e["max_level"]) for e in gold["queries"]]
+        exp = [expected(e) for e in gold["queries"]]
         print(f"[golden] {name}: {len(qs)} queries", flush=True)
-        if name == "batch":
+        if name != "batch":
+            alone = [digest(c.query(q, lean=True)) for q in qs]
+            for e, q, r in zip(gold["queries"], qs, alone):
+                assert r == expected(e), (name, "alone", e["index"], q)
+        if name in ("large", "batch"):
+            print(f"[golden] {name}: cohort batch", flush=True)
             got = c.query_batch(qs, lean=True)
-        else:
-            got = [c.query(q, lean=True) for q in qs]
-        for e, q, r in zip(gold["queries"], qs, got):
-            assert digest(r) == expected(e), (name, e["index"], q)
+            for e, q, r in zip(gold["queries"], qs, got):
+                assert digest(r) == expected(e), (name, "batch", e["index"], q)
+        if name == "serve":
+            print(f"[golden] {name}: served mix", flush=True)
+            c.serve_start()
+            try:
+                half = len(qs) // 2
+                tickets = [c.submit(q) for q in qs[:half]]
+                first = c.wait(tickets[0], lean=True)
+                tickets += [c.submit(q) for q in qs[half:]]
+                served = [first] + [c.wait(t, lean=True) for t in tickets[1:]]
+            finally:
+                c.serve_stop()
+            for e, q, r, a in zip(gold["queries"], qs, served, alone):
+                d = digest(r)
+                assert d == expected(e), (name, "served", e["index"], q)
+                assert d == a, (name, "served != alone", e["index"], q)
+        del exp
     finally:
         c.close()
         synth.make_graph.cache_clear()
+
+
+@pytest.mark.timeout(600)
+def test_medium_node_golden():
+    """NODE activation at size: the medium workload's 32 queries, alone and as
+    one cohort batch, against the reference's values."""
+    import paper_2001_06770_amd as raks
+    gold = golden("medium_node")
+    g = synth.make_graph("medium")
+    assert g.n_arcs == gold["n_arcs"] and gold["mode"] == "node"
+    with raks.Context(0) as c:
+        c.load_graph(g, alpha=gold["alpha"], mode=raks.RAKS_ACT_NODE)
+        act = c.activations()
+        assert hashlib.sha256(act.tobytes()).hexdigest() == gold["act_sha256"]
+        qs = [synth.Query(tuple(e["central"]), tuple(e["marginal"]), e["k"], e["w"],
+                          e["max_level"]) for e in gold["queries"]]
+        print(f"[golden] medium NODE: {len(qs)} queries", flush=True)
+        for e, q in zip(gold["queries"], qs):
+            assert digest(c.query(q, lean=True)) == expected(e), ("alone", e["index"], q)
+        for e, q, r in zip(gold["queries"], qs, c.query_batch(qs, lean=True)):
+            assert digest(r) == expected(e), ("batch", e["index"], q)

@@ -197,7 +197,7 @@ def medium():
     return g, o, act
 
 
-@pytest.mark.parametrize("qi", range(6))
+@pytest.mark.parametrize("qi", range(32))
 def test_medium_parity(ctx, medium, qi):
     g, o, act = medium
     if qi == 0:
