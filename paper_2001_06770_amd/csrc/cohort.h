@@ -130,15 +130,17 @@ struct CoCandView {
 };
 
 // End of a query's exploration: the work counters of both runs from its
-// final hitting levels, its columns copied out to its lane (rows of 16 bytes:
-// its levels first, then INF) and reset to INF in the cohort matrix.
+// final hitting levels, its columns copied out to its lane (rows of TPq = 4, 8
+// or 16 bytes, the smallest that holds its |C| + |M| levels: its levels first,
+// then INF) and reset to INF in the cohort matrix.
 struct CoFinishView {
   uint8_t* seg;                  // the query's segment [n_pad][16]
   int32_t c0, C, M, m_block;
   int32_t n_pad;
+  int32_t TPq;                   // row bytes of the copy
   const CoSlot* slot;            // end levels
   Status* gst;                   // the lane's status: run[0], run[1] counters
-  uint8_t* Hq;                   // the lane's copy [n_pad][16]
+  uint8_t* Hq;                   // the lane's copy [n_pad][TPq]
 };
 
 void launch_co_init(const CohortView& v, hipStream_t s);

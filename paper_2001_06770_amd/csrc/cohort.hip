@@ -946,7 +946,9 @@ __global__ __launch_bounds__(kBlock) void k_co_finish(CoFinishView fv, DevGraphV
     uint4 o, k;
     __builtin_memcpy(&o, out, 16);
     __builtin_memcpy(&k, keep, 16);
-    reinterpret_cast<uint4*>(fv.Hq)[v] = o;
+    if (fv.TPq == 4) reinterpret_cast<uint32_t*>(fv.Hq)[v] = o.x;
+    else if (fv.TPq == 8) reinterpret_cast<uint2*>(fv.Hq)[v] = make_uint2(o.x, o.y);
+    else reinterpret_cast<uint4*>(fv.Hq)[v] = o;
     *rowp = k;
   }
   uint64_t tot[10];

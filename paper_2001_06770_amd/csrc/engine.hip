@@ -600,6 +600,7 @@ int poll_cg(Engine& E) {
     fv.M = q->p.M;
     fv.m_block = q->p.M >= 2 ? 1 : 0;
     fv.n_pad = E.v.n_pad;
+    fv.TPq = tp_for(q->p.C + q->p.M);
     fv.slot = E.v.slots + q->slot;
     fv.gst = P<Status>(q->L->status);
     fv.Hq = P<uint8_t>(q->L->Hq);
@@ -653,11 +654,12 @@ int post_output(Engine& E, CoQuery* q, raks_results** out) {
   const QueryPlan& p = q->p;
   const uint8_t* Hc = P<uint8_t>(L->Hq);
   const uint8_t* Hm = Hc + p.C;
+  const int TPq = tp_for(p.C + p.M);   // row bytes of the lane's copy
   HIP_OK(hipStreamWaitEvent(s, q->ready, 0));
   launch_rank(rank_view(L, p), s);
   auto stage_out = [&]() -> int {
-    if (p.M > 0) launch_recover(recover_view(L, 1, Hm, 16, &st->nres, q->m_bound), s);
-    launch_finalize(finalize_view(L, 1, &st->nres, p.C, Hc, 16), s);
+    if (p.M > 0) launch_recover(recover_view(L, 1, Hm, TPq, &st->nres, q->m_bound), s);
+    launch_finalize(finalize_view(L, 1, &st->nres, p.C, Hc, TPq), s);
     if (p.rerank) launch_rerank(P<ResultHdr>(L->hdr), st, p.k, s);
     HIP_OK(hipGetLastError());
     HIP_OK(hipEventRecord(L->q_end, s));
@@ -671,7 +673,7 @@ int post_output(Engine& E, CoQuery* q, raks_results** out) {
     if (ovf & (4 | 1 | kOvfBig0))
       return fail(RAKS_EDEVICE, "unexpected overflow after the CG stage (internal error)");
     if (!(ovf & 2)) {
-      RAKS_TRY(big_finalize(L, 1, p, p.n_build, Hc, 16));
+      RAKS_TRY(big_finalize(L, 1, p, p.n_build, Hc, TPq));
       if (p.rerank) launch_rerank(P<ResultHdr>(L->hdr), st, p.k, s);
       HIP_OK(hipEventRecord(L->q_end, s));
       RAKS_TRY(collect(L, p, out, &ovf));

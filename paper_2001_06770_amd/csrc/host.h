@@ -58,6 +58,7 @@ struct QueryPlan {
   std::vector<int32_t> central, marginal;
 };
 
+int tp_for(int T);   // row bytes (4, 8 or 16) of a hitting-level matrix for T keywords
 int validate_query(Ctx* c, const raks_query_desc* q, QueryPlan& p);
 
 // activation levels (Eqs. 1-3) of every value in [lo, hi], built on the host

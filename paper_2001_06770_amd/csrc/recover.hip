@@ -24,9 +24,16 @@ namespace raks {
 
 constexpr uint32_t kLdsSort = 4096;   // lists up to this size are sorted in LDS
 
+// Linear probing over at most kMaxProbe slots.  Within its capacity a table is
+// at most half full, so a run that long means it has filled up: the node is
+// reported lost (the instance switches to a bitmap on the next attempt)
+// instead of every later insert walking the whole table with atomics.
+constexpr uint32_t kMaxProbe = 64;
+
 __device__ inline bool ht_insert(uint32_t* ht, uint32_t hc, uint32_t key, int* full) {
   uint32_t h = (key * 2654435761u) & (hc - 1);
-  for (uint32_t probe = 0; probe < hc; ++probe) {
+  const uint32_t probes = hc < kMaxProbe ? hc : kMaxProbe;
+  for (uint32_t probe = 0; probe < probes; ++probe) {
     const uint32_t old = atomicCAS(&ht[h], kEmpty, key);
     if (old == kEmpty) return true;
     if (old == key) return false;
@@ -296,6 +303,15 @@ __global__ __launch_bounds__(kBlock) void k_lr_seed(RecoverView v) {
   }
 }
 
+// One wavefront per work chunk (at most kRecChunk = 4 x 64 arcs of q's row).
+// All of a chunk's recovered arcs go to the arc lists of the same results
+// (those in q's final label), so the chunk's arcs are found first and each of
+// those results gets one reservation for all of them, made by one lane per
+// result at the same time.  A node's label is read before it is or-ed: bits
+// are only added during a layer, so a label that already holds all of q's
+// bits needs no atomic (and its node is not fresh).
+static_assert(kRecChunk == 4 * kWave, "a recovery chunk is four wavefront rounds");
+
 template <int TP>
 __global__ __launch_bounds__(kBlock) void k_lr_layer(RecoverView v, int h) {
   if (v.lcnt[h] > v.lcap) return;   // as in k_rec_layer: the phase is repeated
@@ -313,40 +329,64 @@ __global__ __launch_bounds__(kBlock) void k_lr_layer(RecoverView v, int h) {
     unsigned long long* lab = reinterpret_cast<unsigned long long*>(lab_row(v, jg));
     const uint64_t lq = lab[q];   // final: q is on this layer
     const uint32_t aq = g.mode ? g.act_node[q] : 0u;
-    for (uint32_t k0 = 0; k0 < item.len; k0 += kWave) {
-      const uint32_t k = k0 + lane;
-      bool take = false;
-      int32_t n = 0;
-      uint32_t hn = 0, fwd = 0;
+    bool take[4];
+    int32_t nn[4];
+    uint32_t hh[4], fwd[4], pos[4];
+    uint32_t tot = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t k = (uint32_t)r * kWave + lane;
+      take[r] = false;
+      nn[r] = 0;
+      hh[r] = 0;
+      fwd[r] = 0;
       if (k < item.len) {
         const uint32_t e = item.start + k;
         const uint32_t a = g.mode ? aq : g.act_s[e];
         if (a < (uint32_t)h) {
-          n = g.col_s[e];
-          hn = v.H[(int64_t)n * TP + col];
-          take = hn < (uint32_t)h && (a + 1 == (uint32_t)h || hn + 1 == (uint32_t)h);
-          if (take) fwd = g.rev[g.eid_s[e]];
+          nn[r] = g.col_s[e];
+          hh[r] = v.H[(int64_t)nn[r] * TP + col];
+          // h = 1 + max(a, h_n)
+          take[r] = hh[r] < (uint32_t)h && (a + 1 == (uint32_t)h || hh[r] + 1 == (uint32_t)h);
+          if (take[r]) fwd[r] = g.rev[g.eid_s[e]];
         }
       }
-      const uint64_t tb = __ballot(take);
-      if (tb == 0) continue;
-      const int lead = __ffsll((unsigned long long)tb) - 1;
-      const uint32_t cnt = (uint32_t)__popcll(tb), mine = (uint32_t)__popcll(tb & below);
-      // the arc goes to every result whose search reached q
-      for (uint64_t bits = lq; bits; bits &= bits - 1) {
-        const int b = __ffsll((unsigned long long)bits) - 1;
-        const uint32_t inst = (uint32_t)(grp * 64 + b) * (uint32_t)v.T + (uint32_t)col;
-        const InstCap ic = v.caps[inst];
-        uint32_t base = 0;
-        if (lane == lead) base = atomicAdd(&v.cnt[inst * 2 + 1], cnt);
-        base = __shfl(base, lead, kWave);
-        if (take) {
-          if (base + mine < ic.acap) v.al[ic.aoff + base + mine] = fwd;
-          else atomicOr(&v.gst->overflow, v.ovf_bit);
-        }
+      const uint64_t tb = __ballot(take[r]);
+      pos[r] = tot + (uint32_t)__popcll(tb & below);
+      tot += (uint32_t)__popcll(tb);
+    }
+    if (tot == 0) continue;
+    // lane j reserves room in the arc list of the result of q's j-th label bit
+    const int nres = __popcll(lq);
+    uint32_t base = 0, acap = 0;
+    uint64_t aoff = 0;
+    if (lane < nres) {
+      uint64_t m = lq;
+      for (int j = 0; j < lane; ++j) m &= m - 1;
+      const int b = __ffsll((unsigned long long)m) - 1;
+      const uint32_t inst = (uint32_t)(grp * 64 + b) * (uint32_t)v.T + (uint32_t)col;
+      const InstCap ic = v.caps[inst];
+      acap = ic.acap;
+      aoff = ic.aoff;
+      base = atomicAdd(&v.cnt[inst * 2 + 1], tot);
+      if (base + tot > acap) atomicOr(&v.gst->overflow, v.ovf_bit);
+    }
+    for (int j = 0; j < nres; ++j) {
+      const uint32_t bj = __shfl(base, j, kWave), cj = __shfl(acap, j, kWave);
+      const uint64_t oj = ((uint64_t)__shfl((uint32_t)(aoff >> 32), j, kWave) << 32) |
+                          __shfl((uint32_t)aoff, j, kWave);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (take[r] && bj + pos[r] < cj) v.al[oj + bj + pos[r]] = fwd[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      bool fresh = false;
+      if (take[r]) {
+        const uint64_t cur = __atomic_load_n(&lab[nn[r]], __ATOMIC_RELAXED);
+        if ((cur & lq) != lq) fresh = atomicOr(&lab[nn[r]], (unsigned long long)lq) == 0;
       }
-      const bool fresh = take && atomicOr(&lab[n], (unsigned long long)lq) == 0;
-      lr_fresh(v, fresh, jg, n, hn);
+      lr_fresh(v, fresh, jg, nn[r], hh[r]);
     }
   }
 }

@@ -97,7 +97,7 @@ struct Lane {
   DevBuf hpool, nl, al, items, sort_a, sort_b;
   DevBuf cg_nodes, cg_arcs, cg_cnt;   // CG lists, kept for the marginal phase
   DevBuf hdr, out_nodes, out_arcs, status;
-  DevBuf Hq;                          // cohort path: the query's hitting levels, [n_pad][16]
+  DevBuf Hq;                          // cohort path: the query's hitting levels, [n_pad][TPq]
   DevBuf bigf, big_bm, big_chunk, big_slot;   // bitmap path of large results
   RecPhase ph[2];                     // [0] CG recovery, [1] RPG recovery + output
   DevBuf lab;                         // labels of the labelled mode, [T * G][n] words
