@@ -18,6 +18,7 @@
 //               results; then it resets the query's columns to INF and
 //               returns slot, columns and lane.
 // Results are those of the single-query path, query by query.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -167,12 +168,27 @@ int engine_alloc(Engine& E) {
   return RAKS_OK;
 }
 
+// The level loop's stream.  A process has few hardware queues (4 by
+// default), and streams beyond that share them; packets of one queue run in
+// order, so a level's control step queued behind another query's recovery
+// layer on a shared queue would wait for all of it.  A stream made with a CU
+// mask gets a hardware queue of its own; the mask holds every CU.
+int make_level_stream(const Ctx* c, hipStream_t* s) {
+  std::vector<uint32_t> mask(((size_t)std::max(c->num_cu, 1) + 31) / 32, 0u);
+  for (int i = 0; i < c->num_cu; ++i) mask[(size_t)i / 32] |= 1u << (i % 32);
+  if (hipExtStreamCreateWithCUMask(s, (uint32_t)c->num_cu, mask.data()) == hipSuccess)
+    return RAKS_OK;
+  (void)hipGetLastError();
+  if (hipStreamCreateWithFlags(s, hipStreamNonBlocking) == hipSuccess) return RAKS_OK;
+  return fail(RAKS_EDEVICE, "stream creation failed");
+}
+
 int engine_create(Ctx* c, Engine** out) {
   Engine* E = new Engine();
   E->c = c;
-  if (hipStreamCreateWithFlags(&E->stream, hipStreamNonBlocking) != hipSuccess) {
+  if (make_level_stream(c, &E->stream) != RAKS_OK) {
     delete E;
-    return fail(RAKS_EDEVICE, "stream creation failed");
+    return RAKS_EDEVICE;
   }
   const int rc = engine_alloc(*E);
   if (rc) {

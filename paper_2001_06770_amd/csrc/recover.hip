@@ -303,91 +303,199 @@ __global__ __launch_bounds__(kBlock) void k_lr_seed(RecoverView v) {
   }
 }
 
-// One wavefront per work chunk (at most kRecChunk = 4 x 64 arcs of q's row).
-// All of a chunk's recovered arcs go to the arc lists of the same results
-// (those in q's final label), so the chunk's arcs are found first and each of
-// those results gets one reservation for all of them, made by one lane per
-// result at the same time.  A node's label is read before it is or-ed: bits
-// are only added during a layer, so a label that already holds all of q's
-// bits needs no atomic (and its node is not fresh).
+// A labelled layer in batches of kLrBatch work chunks per workgroup, one
+// wavefront per chunk (at most kRecChunk = 4 x 64 arcs of q's row), so that a
+// batch makes one global reservation per arc list, per layer queue and for
+// the node log instead of one per chunk: these counters are few, and every
+// wavefront of the GPU adds to them (atomics on device memory are performed
+// at the memory side, so one address takes them one at a time).
+//   A  each wavefront examines its chunks: recovered arcs (h = 1 + max(a, h_n)),
+//      labels or-ed into their nodes (a label that already holds all of q's
+//      bits needs no atomic, and its node is not fresh: bits are only added
+//      during a layer), and the batch's local offsets from LDS counters;
+//   B  one global reservation per touched arc list, per layer with queued
+//      chunks and for the node log;
+//   C  the writes.
+// All of a chunk's recovered arcs go to the arc lists of the results in q's
+// final label.
+constexpr int kLrGI = 2;                                 // chunks per wavefront per batch
+constexpr int kLrBatch = kLrGI * (kBlock / kWave);      // chunks per workgroup per batch
+constexpr int kLrMaxInst = kMaxW * kMaxKw;               // instances of a phase
+constexpr int kLrMaxLayer = 256;
 static_assert(kRecChunk == 4 * kWave, "a recovery chunk is four wavefront rounds");
 
 template <int TP>
 __global__ __launch_bounds__(kBlock) void k_lr_layer(RecoverView v, int h) {
   if (v.lcnt[h] > v.lcap) return;   // as in k_rec_layer: the phase is repeated
+  __shared__ uint32_t s_cnt[kLrMaxInst];     // batch's arcs per instance, then its global base
+  __shared__ uint16_t s_list[kLrBatch * 64]; // instances touched by the batch
+  __shared__ uint32_t s_lay[kLrMaxLayer];    // chunks queued per layer, then the global base
+  __shared__ uint32_t s_nt, s_touch, s_tbase;
   const uint32_t n_items = v.lcnt[h];
-  const uint32_t waves = gridDim.x * (kBlock / kWave);
-  const int lane = lane_id();
+  const int lane = lane_id(), wv = wave_id();
   const uint64_t below = (1ull << lane) - 1;
   const RecItem* list = v.items + (size_t)h * v.lcap;
   const DevGraphView& g = v.g;
-  for (uint32_t it = blockIdx.x * (kBlock / kWave) + wave_id(); it < n_items; it += waves) {
-    const RecItem item = list[it];
-    const uint32_t jg = item.inst;
-    const int col = (int)jg / v.G, grp = (int)jg % v.G;
-    const int32_t q = item.q;
-    unsigned long long* lab = reinterpret_cast<unsigned long long*>(lab_row(v, jg));
-    const uint64_t lq = lab[q];   // final: q is on this layer
-    const uint32_t aq = g.mode ? g.act_node[q] : 0u;
-    bool take[4];
-    int32_t nn[4];
-    uint32_t hh[4], fwd[4], pos[4];
-    uint32_t tot = 0;
+  for (int i = threadIdx.x; i < v.n_inst; i += kBlock) s_cnt[i] = 0;
+  for (int i = threadIdx.x; i <= v.max_layer; i += kBlock) s_lay[i] = 0;
+  if (threadIdx.x == 0) { s_nt = 0; s_touch = 0; }
+  __syncthreads();
+  for (uint32_t b0 = blockIdx.x * (uint32_t)kLrBatch; b0 < n_items; b0 += gridDim.x * (uint32_t)kLrBatch) {
+    // ---- A
+    uint32_t fwd[kLrGI][4];
+    int32_t nn[kLrGI][4];
+    uint32_t hh[kLrGI][4], toff[kLrGI][4], qoff[kLrGI][4];
+    uint32_t take = 0, fresh = 0;             // bit 4 g + r
+    uint32_t pos[kLrGI][4];
+    uint64_t lqs[kLrGI];
+    uint32_t jgs[kLrGI], tots[kLrGI];         // per chunk (the same in every lane)
+    uint32_t lbase[kLrGI];                    // lane j: local offset in its j-th result's list
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const uint32_t k = (uint32_t)r * kWave + lane;
-      take[r] = false;
-      nn[r] = 0;
-      hh[r] = 0;
-      fwd[r] = 0;
-      if (k < item.len) {
-        const uint32_t e = item.start + k;
-        const uint32_t a = g.mode ? aq : g.act_s[e];
-        if (a < (uint32_t)h) {
-          nn[r] = g.col_s[e];
-          hh[r] = v.H[(int64_t)nn[r] * TP + col];
-          // h = 1 + max(a, h_n)
-          take[r] = hh[r] < (uint32_t)h && (a + 1 == (uint32_t)h || hh[r] + 1 == (uint32_t)h);
-          if (take[r]) fwd[r] = g.rev[g.eid_s[e]];
+    for (int gi = 0; gi < kLrGI; ++gi) {
+      const uint32_t it = b0 + (uint32_t)(wv * kLrGI + gi);
+      lqs[gi] = 0;
+      jgs[gi] = 0;
+      lbase[gi] = 0;
+      RecItem item = {0, 0, 0, 0};
+      if (it < n_items) item = list[it];
+      const uint32_t jg = item.inst;
+      const int col = (int)jg / v.G, grp = (int)jg % v.G;
+      unsigned long long* lab = reinterpret_cast<unsigned long long*>(lab_row(v, jg));
+      const uint64_t lq = it < n_items ? lab[item.q] : 0ull;   // final: q is on this layer
+      const uint32_t aq = (g.mode && it < n_items) ? g.act_node[item.q] : 0u;
+      lqs[gi] = lq;
+      jgs[gi] = jg;
+      uint32_t tot = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t k = (uint32_t)r * kWave + lane;
+        bool tk = false;
+        nn[gi][r] = 0;
+        hh[gi][r] = 0;
+        fwd[gi][r] = 0;
+        if (k < item.len) {
+          const uint32_t e = item.start + k;
+          const uint32_t a = g.mode ? aq : g.act_s[e];
+          if (a < (uint32_t)h) {
+            nn[gi][r] = g.col_s[e];
+            hh[gi][r] = v.H[(int64_t)nn[gi][r] * TP + col];
+            // h = 1 + max(a, h_n)
+            tk = hh[gi][r] < (uint32_t)h && (a + 1 == (uint32_t)h || hh[gi][r] + 1 == (uint32_t)h);
+            if (tk) fwd[gi][r] = g.rev[g.eid_s[e]];
+          }
+        }
+        const uint64_t tb = __ballot(tk);
+        pos[gi][r] = tot + (uint32_t)__popcll(tb & below);
+        tot += (uint32_t)__popcll(tb);
+        if (tk) take |= 1u << (4 * gi + r);
+        bool fr = false;
+        if (tk) {
+          const uint64_t cur = __atomic_load_n(&lab[nn[gi][r]], __ATOMIC_RELAXED);
+          if ((cur & lq) != lq) fr = atomicOr(&lab[nn[gi][r]], (unsigned long long)lq) == 0;
+        }
+        // local offsets of a fresh node: its node-log entry and its queued chunks
+        toff[gi][r] = 0;
+        qoff[gi][r] = 0;
+        const uint64_t fb = __ballot(fr);
+        if (fb) {
+          const int lead = __ffsll((unsigned long long)fb) - 1;
+          uint32_t t0 = 0;
+          if (lane == lead) t0 = atomicAdd(&s_touch, (uint32_t)__popcll(fb));
+          t0 = __shfl(t0, lead, kWave);
+          if (fr) {
+            fresh |= 1u << (4 * gi + r);
+            toff[gi][r] = t0 + (uint32_t)__popcll(fb & below);
+            const uint32_t hn = hh[gi][r];
+            if (hn >= 1 && (int)hn <= v.max_layer) {
+              const int32_t n = nn[gi][r];
+              const uint32_t deg = g.mode ? ((uint32_t)g.act_node[n] < hn ? g.row_ptr[n + 1] - g.row_ptr[n] : 0u)
+                                          : count_le(g, n, (int)hn - 1);
+              const uint32_t kc = (deg + kRecChunk - 1) / kRecChunk;
+              if (kc) qoff[gi][r] = atomicAdd(&s_lay[hn], kc);
+            }
+          }
         }
       }
-      const uint64_t tb = __ballot(take[r]);
-      pos[r] = tot + (uint32_t)__popcll(tb & below);
-      tot += (uint32_t)__popcll(tb);
-    }
-    if (tot == 0) continue;
-    // lane j reserves room in the arc list of the result of q's j-th label bit
-    const int nres = __popcll(lq);
-    uint32_t base = 0, acap = 0;
-    uint64_t aoff = 0;
-    if (lane < nres) {
-      uint64_t m = lq;
-      for (int j = 0; j < lane; ++j) m &= m - 1;
-      const int b = __ffsll((unsigned long long)m) - 1;
-      const uint32_t inst = (uint32_t)(grp * 64 + b) * (uint32_t)v.T + (uint32_t)col;
-      const InstCap ic = v.caps[inst];
-      acap = ic.acap;
-      aoff = ic.aoff;
-      base = atomicAdd(&v.cnt[inst * 2 + 1], tot);
-      if (base + tot > acap) atomicOr(&v.gst->overflow, v.ovf_bit);
-    }
-    for (int j = 0; j < nres; ++j) {
-      const uint32_t bj = __shfl(base, j, kWave), cj = __shfl(acap, j, kWave);
-      const uint64_t oj = ((uint64_t)__shfl((uint32_t)(aoff >> 32), j, kWave) << 32) |
-                          __shfl((uint32_t)aoff, j, kWave);
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (take[r] && bj + pos[r] < cj) v.al[oj + bj + pos[r]] = fwd[r];
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      bool fresh = false;
-      if (take[r]) {
-        const uint64_t cur = __atomic_load_n(&lab[nn[r]], __ATOMIC_RELAXED);
-        if ((cur & lq) != lq) fresh = atomicOr(&lab[nn[r]], (unsigned long long)lq) == 0;
+      tots[gi] = tot;
+      // lane j: room for this chunk's arcs in the list of q's j-th label bit
+      if (tot && lane < __popcll(lq)) {
+        uint64_t m = lq;
+        for (int j = 0; j < lane; ++j) m &= m - 1;
+        const int b = __ffsll((unsigned long long)m) - 1;
+        const uint32_t inst = (uint32_t)(grp * 64 + b) * (uint32_t)v.T + (uint32_t)col;
+        lbase[gi] = atomicAdd(&s_cnt[inst], tot);
+        if (lbase[gi] == 0) s_list[atomicAdd(&s_nt, 1u)] = (uint16_t)inst;
       }
-      lr_fresh(v, fresh, jg, nn[r], hh[r]);
     }
+    __syncthreads();
+    // ---- B
+    for (uint32_t t = threadIdx.x; t < s_nt; t += kBlock) {
+      const uint32_t inst = s_list[t];
+      const uint32_t c = s_cnt[inst];
+      const uint32_t base = atomicAdd(&v.cnt[inst * 2 + 1], c);
+      if (base + c > v.caps[inst].acap) atomicOr(&v.gst->overflow, v.ovf_bit);
+      s_cnt[inst] = base;
+    }
+    for (int t = threadIdx.x; t <= v.max_layer; t += kBlock)
+      if (s_lay[t]) s_lay[t] = atomicAdd(&v.lcnt[t], s_lay[t]);
+    if (threadIdx.x == 0 && s_touch) s_tbase = atomicAdd(v.tcnt, s_touch);
+    __syncthreads();
+    // ---- C
+#pragma unroll
+    for (int gi = 0; gi < kLrGI; ++gi) {
+      const uint64_t lq = lqs[gi];
+      const uint32_t jg = jgs[gi];
+      const int col = (int)jg / v.G, grp = (int)jg % v.G;
+      if (tots[gi]) {
+        uint64_t m = lq;
+        for (int j = 0; m; ++j, m &= m - 1) {
+          const int b = __ffsll((unsigned long long)m) - 1;
+          const uint32_t inst = (uint32_t)(grp * 64 + b) * (uint32_t)v.T + (uint32_t)col;
+          const InstCap ic = v.caps[inst];
+          const uint32_t base = s_cnt[inst] + __shfl(lbase[gi], j, kWave);
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (((take >> (4 * gi + r)) & 1u) && base + pos[gi][r] < ic.acap)
+              v.al[ic.aoff + base + pos[gi][r]] = fwd[gi][r];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (!((fresh >> (4 * gi + r)) & 1u)) continue;
+        const int32_t n = nn[gi][r];
+        const uint32_t hn = hh[gi][r];
+        const uint32_t slot = s_tbase + toff[gi][r];
+        if (slot < v.tcap) v.touch[slot] = ((uint64_t)jg << 32) | (uint32_t)n;
+        else atomicOr(&v.gst->overflow, v.ovf_bit);
+        if (hn >= 1 && (int)hn <= v.max_layer) {
+          const uint32_t rs = g.row_ptr[n];
+          const uint32_t deg = g.mode ? ((uint32_t)g.act_node[n] < hn ? g.row_ptr[n + 1] - rs : 0u)
+                                      : count_le(g, n, (int)hn - 1);
+          const uint32_t kc = (deg + kRecChunk - 1) / kRecChunk;
+          const uint32_t first = s_lay[hn] + qoff[gi][r];
+          if (kc && first + kc > v.lcap) {
+            atomicOr(&v.gst->overflow, v.ovf_bit);
+          } else {
+            RecItem* dst = v.items + (size_t)hn * v.lcap + first;
+            for (uint32_t c = 0; c < kc; ++c) {
+              RecItem ri;
+              ri.inst = jg;
+              ri.q = n;
+              ri.start = rs + c * kRecChunk;
+              ri.len = min(kRecChunk, deg - c * kRecChunk);
+              dst[c] = ri;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // reset the batch's counters
+    for (uint32_t t = threadIdx.x; t < s_nt; t += kBlock) s_cnt[s_list[t]] = 0;
+    for (int t = threadIdx.x; t <= v.max_layer; t += kBlock) s_lay[t] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) { s_nt = 0; s_touch = 0; }
+    __syncthreads();
   }
 }
 
