@@ -159,9 +159,34 @@ def _check(rc):
         raise RaksError(rc, lib().raks_last_error().decode())
 
 
-def _results_to_dict(res: Results, lean: bool = False) -> dict:
+class _Owned:
+    """Library-owned results (``raks_results*``), freed with
+    ``raks_results_free`` when the last array viewing them is gone."""
+
+    def __init__(self, ptr):
+        self._ptr = ptr
+
+    def __del__(self):
+        try:
+            lib().raks_results_free(self._ptr)
+        except Exception:  # interpreter shutdown
+            pass
+
+
+class _View:
+    """A read-only numpy view of library memory that keeps its owner alive."""
+
+    def __init__(self, owner, addr: int, shape, typestr: str = "<i4"):
+        self._owner = owner
+        self.__array_interface__ = {"data": (addr, True), "shape": shape,
+                                    "typestr": typestr, "version": 3}
+
+
+def _results_to_dict(res: Results, lean: bool = False, owner=None) -> dict:
     """Results as a dict; nodes and arcs as tuples, or as numpy arrays when
-    ``lean`` (no per-element Python objects)."""
+    ``lean`` (no per-element Python objects).  With an ``owner`` (lean only)
+    the arrays are views of the library's result lists, which stay allocated
+    until the arrays are gone; otherwise they are copies."""
     st = res.stats
     stats = []
     for k in range(2):
@@ -176,12 +201,18 @@ def _results_to_dict(res: Results, lean: bool = False) -> dict:
            "queue_ms": float(st.queue_ms)}
     for i in range(res.n):
         r = res.r[i]
-        nodes = np.empty(r.n_nodes, np.int32)
-        if r.n_nodes:
-            ctypes.memmove(nodes.ctypes.data, r.nodes, 4 * r.n_nodes)
-        arcs = np.empty((r.n_arcs, 3), np.int32)
-        if r.n_arcs:
-            ctypes.memmove(arcs.ctypes.data, r.arcs, 12 * r.n_arcs)
+        if owner is not None and lean and r.n_nodes and r.n_arcs:
+            nodes = np.asarray(_View(owner, ctypes.cast(r.nodes, ctypes.c_void_p).value,
+                                     (r.n_nodes,)))
+            arcs = np.asarray(_View(owner, ctypes.cast(r.arcs, ctypes.c_void_p).value,
+                                    (r.n_arcs, 3)))
+        else:
+            nodes = np.empty(r.n_nodes, np.int32)
+            if r.n_nodes:
+                ctypes.memmove(nodes.ctypes.data, r.nodes, 4 * r.n_nodes)
+            arcs = np.empty((r.n_arcs, 3), np.int32)
+            if r.n_arcs:
+                ctypes.memmove(arcs.ctypes.data, r.arcs, 12 * r.n_arcs)
         if not lean:
             nodes = tuple(nodes.tolist())
             arcs = tuple(map(tuple, arcs.tolist()))
@@ -190,6 +221,19 @@ def _results_to_dict(res: Results, lean: bool = False) -> dict:
                                "weight_sum": int(r.weight_sum),
                                "nodes": nodes, "arcs": arcs})
     return out
+
+
+def _to_dict_owned(ptr, lean: bool) -> dict:
+    """Takes ownership of library results: lean dicts view them (freed when
+    the views are gone), others copy them (freed at once)."""
+    if lean:
+        ptr = ctypes.cast(ptr, ctypes.POINTER(Results))   # its own copy of the address
+        owner = _Owned(ptr)
+        return _results_to_dict(ptr.contents, True, owner)
+    try:
+        return _results_to_dict(ptr.contents, False)
+    finally:
+        lib().raks_results_free(ptr)
 
 
 class Context:
@@ -292,10 +336,7 @@ class Context:
         d = self._desc(q, keep)
         out = ctypes.POINTER(Results)()
         _check(lib().raks_query(self._h, ctypes.byref(d), ctypes.byref(out)))
-        try:
-            return _results_to_dict(out.contents, lean)
-        finally:
-            lib().raks_results_free(out)
+        return _to_dict_owned(out, lean)
 
     def query_noalloc(self, q, cap_nodes: int = 1 << 20, cap_arcs: int = 1 << 20,
                       lean: bool = False) -> dict:
@@ -332,10 +373,13 @@ class Context:
         res = []
         try:
             for i in range(n):
-                res.append(_results_to_dict(outs[i].contents, lean))
+                ptr = ctypes.cast(outs[i], ctypes.POINTER(Results))
+                outs[i] = None   # owned by ptr from here on
+                res.append(_to_dict_owned(ptr, lean))
         finally:
             for i in range(n):
-                lib().raks_results_free(outs[i])
+                if outs[i]:
+                    lib().raks_results_free(outs[i])
         return res
 
     # ---- serving
@@ -357,10 +401,7 @@ class Context:
         if rc == RAKS_EAGAIN:
             return None
         _check(rc)
-        try:
-            return _results_to_dict(out.contents, lean)
-        finally:
-            lib().raks_results_free(out)
+        return _to_dict_owned(out, lean)
 
     def poll(self, ticket: int, lean: bool = False):
         """Results of a finished query, or None while it runs."""

@@ -26,6 +26,7 @@
 #include <string>
 #include <thread>
 #include <vector>
+#include <tuple>
 
 #include "host.h"
 #include "runtime.h"
@@ -168,6 +169,9 @@ void lane_destroy(Ctx* c, Lane* L) {
   if (L->h_hdr) (void)hipHostFree(L->h_hdr);
   if (L->h_nodes) (void)hipHostFree(L->h_nodes);
   if (L->h_arcs) (void)hipHostFree(L->h_arcs);
+  if (L->xfer) (void)hipHostFree(L->xfer);
+  L->xfer = nullptr;
+  L->xfer_bytes = 0;
   if (L->own_stream && L->stream) (void)hipStreamDestroy(L->stream);
   L->stream = nullptr;
 }
@@ -1204,6 +1208,34 @@ void fill_stats(Lane* L, const QueryPlan& p, const Status& hs, raks_query_stats*
   *status = bits;
 }
 
+// Host copies of the pieces (dst, src, bytes) by several threads: the result
+// arrays are fresh allocations, so the copy also takes their first-touch page
+// faults, which the kernel serves in parallel.
+void parallel_copy(const std::vector<std::tuple<void*, const void*, size_t>>& pieces) {
+  size_t total = 0;
+  for (const auto& x : pieces) total += std::get<2>(x);
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const unsigned nt = (unsigned)std::min<size_t>({(size_t)8, (size_t)hw, total / (4u << 20) + 1});
+  auto part = [&](unsigned t) {
+    // thread t copies bytes [t * total / nt, (t + 1) * total / nt) of the concatenation
+    const size_t lo = total * t / nt, hi = total * (t + 1) / nt;
+    size_t at = 0;
+    for (const auto& x : pieces) {
+      const size_t b = std::get<2>(x);
+      const size_t s0 = std::max(lo, at), s1 = std::min(hi, at + b);
+      if (s0 < s1)
+        memcpy(static_cast<char*>(std::get<0>(x)) + (s0 - at),
+               static_cast<const char*>(std::get<1>(x)) + (s0 - at), s1 - s0);
+      at += b;
+      if (at >= hi) break;
+    }
+  };
+  std::vector<std::thread> th;
+  for (unsigned t = 1; t < nt; ++t) th.emplace_back(part, t);
+  part(0);
+  for (auto& x : th) x.join();
+}
+
 int collect(Lane* L, const QueryPlan& p, raks_results** out, int* ovf) {
   Ctx* c = L->ctx;
   hipStream_t s = L->stream;
@@ -1244,6 +1276,37 @@ int collect(Lane* L, const QueryPlan& p, raks_results** out, int* ovf) {
     raks_results_free(res);
     return fail(RAKS_ENOMEM, "host allocation failed");
   }
+  // lists beyond the pinned buffers: one copy of the whole output into the
+  // lane's pinned staging (a copy into pageable memory goes through small
+  // staging buffers of the runtime), then host copies into the result arrays
+  const size_t big_bytes = (dev_nodes ? (size_t)tn * 4 : 0) + (dev_arcs ? (size_t)ta * 12 : 0);
+  char* stage = nullptr;
+  if (big_bytes) {
+    if (L->xfer_bytes < big_bytes) {
+      if (L->xfer) (void)hipHostFree(L->xfer);
+      L->xfer = nullptr;
+      L->xfer_bytes = 0;
+      const size_t want = big_bytes + big_bytes / 4;
+      if (hipHostMalloc(&L->xfer, want, hipHostMallocDefault) == hipSuccess) L->xfer_bytes = want;
+      else (void)hipGetLastError();
+    }
+    if (L->xfer) {
+      stage = static_cast<char*>(L->xfer);
+      hipError_t e = hipSuccess;
+      if (dev_nodes) e = hipMemcpyAsync(stage, L->out_nodes.p, (size_t)tn * 4, hipMemcpyDeviceToHost, s);
+      if (dev_arcs && e == hipSuccess)
+        e = hipMemcpyAsync(stage + (dev_nodes ? (size_t)tn * 4 : 0), L->out_arcs.p, (size_t)ta * 12,
+                           hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) {
+        raks_results_free(res);
+        return fail(RAKS_EDEVICE, std::string("result copy: ") + hipGetErrorString(e));
+      }
+    }
+  }
+  const int32_t* st_nodes = reinterpret_cast<const int32_t*>(stage);
+  const int32_t* st_arcs = reinterpret_cast<const int32_t*>(stage + (dev_nodes ? (size_t)tn * 4 : 0));
+  std::vector<std::tuple<void*, const void*, size_t>> pieces;
   for (int t = 0; t < nres; ++t) {
     raks_result& o = res->r[t];
     const ResultHdr& h = L->h_hdr[t];
@@ -1264,14 +1327,18 @@ int collect(Lane* L, const QueryPlan& p, raks_results** out, int* ovf) {
     }
     hipError_t e = hipSuccess;
     if (h.n_nodes) {
-      if (dev_nodes)
+      if (dev_nodes && stage)
+        pieces.emplace_back(nd, st_nodes + h.node_off, sizeof(int32_t) * h.n_nodes);
+      else if (dev_nodes)
         e = hipMemcpyAsync(nd, P<int32_t>(L->out_nodes) + h.node_off, sizeof(int32_t) * h.n_nodes,
                            hipMemcpyDeviceToHost, s);
       else
         memcpy(nd, L->h_nodes + h.node_off, sizeof(int32_t) * h.n_nodes);
     }
     if (h.n_arcs && e == hipSuccess) {
-      if (dev_arcs)
+      if (dev_arcs && stage)
+        pieces.emplace_back(ar, st_arcs + 3 * (size_t)h.arc_off, sizeof(raks_arc) * h.n_arcs);
+      else if (dev_arcs)
         e = hipMemcpyAsync(ar, P<int32_t>(L->out_arcs) + 3 * (size_t)h.arc_off,
                            sizeof(raks_arc) * h.n_arcs, hipMemcpyDeviceToHost, s);
       else
@@ -1283,7 +1350,8 @@ int collect(Lane* L, const QueryPlan& p, raks_results** out, int* ovf) {
       return fail(RAKS_EDEVICE, std::string("result copy: ") + hipGetErrorString(e));
     }
   }
-  if (dev_nodes || dev_arcs) {
+  if (!pieces.empty()) parallel_copy(pieces);
+  if ((dev_nodes || dev_arcs) && !stage) {
     const hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
       raks_results_free(res);

@@ -109,6 +109,8 @@ struct Lane {
   ResultHdr* h_hdr = nullptr;   // pinned [kMaxW]
   int32_t* h_nodes = nullptr;   // pinned [kSpecNodes]
   int32_t* h_arcs = nullptr;    // pinned [3 * kSpecArcs]
+  void* xfer = nullptr;         // pinned staging of outputs beyond the buffers above (grown)
+  size_t xfer_bytes = 0;
   // device addresses of the pinned buffers above (results are written there
   // by a kernel)
   Status* d_status = nullptr;
