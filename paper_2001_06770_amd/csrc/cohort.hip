@@ -653,22 +653,34 @@ __global__ __launch_bounds__(kBlock) void k_co_expand(CohortView v, DevGraphView
     for (int k = 0; k < IPT; ++k)
       s_own[threadIdx.x * IPT + k] = (uint16_t)(pre > loc[k] ? pre : loc[k]);
     __syncthreads();
-#pragma unroll 2
+    // all of the thread's arcs at once: their levels and targets, then the
+    // targets' reached masks, then the writes, so that a wavefront has IPT
+    // independent gathers in flight instead of one dependent chain per arc
+    int32_t nbv[IPT];
+    unsigned long long wantv[IPT], rv[IPT];
+#pragma unroll
     for (int k = 0; k < IPT; ++k) {
       const uint32_t i = k * kBlock + threadIdx.x;
-      if (w0 + i >= w1) break;
-      const int j = s_own[i];
-      const uint32_t e = s_base[j] + i;
-      const uint32_t a = g.act_s[e];
-      const unsigned long long want = (s_nm[j] & s_ge[a]) | (s_om[j] & s_eq[a]);
-      if (!want) continue;
-      const int32_t nb2 = g.col_s[e];
-      // columns that have not reached nb2 (as of the start of the level)
-      unsigned long long mm = ~v.R[nb2] & want;
+      wantv[k] = 0;
+      nbv[k] = 0;
+      if (w0 + i < w1) {
+        const int j = s_own[i];
+        const uint32_t e = s_base[j] + i;
+        const uint32_t a = g.act_s[e];
+        nbv[k] = g.col_s[e];
+        wantv[k] = (s_nm[j] & s_ge[a]) | (s_om[j] & s_eq[a]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) rv[k] = wantv[k] ? v.R[nbv[k]] : ~0ull;
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      // columns that have not reached the target (as of the start of the level)
+      unsigned long long mm = ~rv[k] & wantv[k];
       while (mm) {
         const int c = __ffsll(mm) - 1;
         mm &= mm - 1;
-        seg_base(v, c >> 4)[(size_t)nb2 * 16 + (c & 15)] = s_lv1[c];
+        seg_base(v, c >> 4)[(size_t)nbv[k] * 16 + (c & 15)] = s_lv1[c];
       }
     }
     __syncthreads();
@@ -912,25 +924,23 @@ __device__ inline void run_counts(const uint8_t* h, int T, int L, bool blk, cons
 }
 
 // One pass over the query's rows: counters, copy-out and reset.  Runs on the
-// cohort stream between levels, so whole rows are rewritten safely.
+// query's lane stream while the next levels run: the level kernels may write
+// other columns of the same rows, so the reset stores only the query's own
+// bytes (and only those that are not INF already).
 __global__ __launch_bounds__(kBlock) void k_co_finish(CoFinishView fv, DevGraphView g) {
   __shared__ uint64_t s_multi[(kBlock / kWave + 1) * 10];
   const CoSlot s = *fv.slot;
   const int Lc = s.c_end, Lm = s.m_end;
   const int T = fv.C + fv.M;
-  const uint32_t qmask = ((1u << T) - 1u) << fv.c0;
   uint64_t acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < fv.n_pad;
        v += (int64_t)gridDim.x * kBlock) {
     uint4* rowp = reinterpret_cast<uint4*>(fv.seg) + v;
     const uint4 row = *rowp;
-    uint8_t b[16], out[16], keep[16];
+    uint8_t b[16], out[16];
     __builtin_memcpy(b, &row, 16);
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      out[j] = kInf;
-      keep[j] = ((qmask >> j) & 1u) ? kInf : b[j];
-    }
+    for (int j = 0; j < 16; ++j) out[j] = kInf;
     for (int j = 0; j < T; ++j) out[j] = b[fv.c0 + j];
     if (v < g.n && ((row.x & row.y & row.z & row.w) != 0xFFFFFFFFu)) {
       const uint32_t rs = g.row_ptr[v], d = g.row_ptr[v + 1] - rs, amax = g.row_amax[v];
@@ -943,13 +953,14 @@ __global__ __launch_bounds__(kBlock) void k_co_finish(CoFinishView fv, DevGraphV
         acc[5] += c.fr; acc[6] += c.ea; acc[7] += c.eg; acc[8] += c.gp; acc[9] += c.hw;
       }
     }
-    uint4 o, k;
+    uint4 o;
     __builtin_memcpy(&o, out, 16);
-    __builtin_memcpy(&k, keep, 16);
     if (fv.TPq == 4) reinterpret_cast<uint32_t*>(fv.Hq)[v] = o.x;
     else if (fv.TPq == 8) reinterpret_cast<uint2*>(fv.Hq)[v] = make_uint2(o.x, o.y);
     else reinterpret_cast<uint4*>(fv.Hq)[v] = o;
-    *rowp = k;
+    uint8_t* rb = reinterpret_cast<uint8_t*>(rowp);
+    for (int j = 0; j < T; ++j)
+      if (out[j] != kInf) rb[fv.c0 + j] = kInf;
   }
   uint64_t tot[10];
   block_exclusive_scan_multi<10, kBlock>(acc, tot, s_multi);

@@ -58,7 +58,8 @@ struct CoQuery {
   bool big0 = false;
   int c_end = 0, m_bound = 0, cg_attempts = 0;
   uint64_t cg_seq = 0;
-  hipEvent_t ready = nullptr;
+  hipEvent_t ready = nullptr;     // lane stream: counters, copy-out and reset done
+  hipEvent_t fin = nullptr;       // cohort stream: the final marginal decision is written
   double t_submit = 0, t_admit = 0;
   // outcome
   raks_results* res = nullptr;
@@ -605,10 +606,17 @@ int poll_cg(Engine& E) {
   for (int i = 0; i < kCoSlots; ++i) {
     CoQuery* q = E.slot[i];
     if (!q || q->handed || !q->x_done || !q->cg_ok) continue;
-    // the final marginal decision, the counters, and the query's levels moved
-    // to its lane; slot and columns are free for the next level
+    // the final marginal decision on the cohort stream; the counters, the
+    // copy of the query's levels to its lane and the reset of its columns on
+    // the lane's stream, beside the next levels (they touch only its columns,
+    // which no level kernel reads or writes any more); slot and columns are
+    // free once that is done
     if (q->p.M > 0) launch_co_dmin(E.v, q->slot, E.c->num_cu * 4, E.stream);
     launch_co_rpg_final(E.v, q->slot, E.stream);
+    q->fin = take_event(E);
+    if (!q->fin) return fail(RAKS_EDEVICE, "event creation failed");
+    HIP_OK(hipEventRecord(q->fin, E.stream));
+    HIP_OK(hipStreamWaitEvent(q->L->stream, q->fin, 0));
     CoFinishView fv;
     fv.seg = E.v.H + (size_t)q->seg * E.v.n_pad * 16;
     fv.c0 = q->c0;
@@ -620,14 +628,11 @@ int poll_cg(Engine& E) {
     fv.slot = E.v.slots + q->slot;
     fv.gst = P<Status>(q->L->status);
     fv.Hq = P<uint8_t>(q->L->Hq);
-    launch_co_finish(fv, graph_view(E.c, E.c->base), E.stream);
+    launch_co_finish(fv, graph_view(E.c, E.c->base), q->L->stream);
     HIP_OK(hipGetLastError());
     q->ready = take_event(E);
     if (!q->ready) return fail(RAKS_EDEVICE, "event creation failed");
-    HIP_OK(hipEventRecord(q->ready, E.stream));
-    E.used[q->seg] &= (uint16_t)~(((1u << q->T) - 1u) << q->c0);
-    E.slot[i] = nullptr;
-    q->slot = -1;
+    HIP_OK(hipEventRecord(q->ready, q->L->stream));
     q->handed = true;
     {
       std::lock_guard<std::mutex> lk(E.mu);
@@ -636,6 +641,18 @@ int poll_cg(Engine& E) {
     E.cv.notify_all();
   }
   return RAKS_OK;
+}
+
+// Slots and columns of handed-off queries whose lane has finished with them.
+void reap_finished(Engine& E) {
+  for (int i = 0; i < kCoSlots; ++i) {
+    CoQuery* q = E.slot[i];
+    if (!q || !q->handed || !q->ready) continue;
+    if (hipEventQuery(q->ready) != hipSuccess) continue;
+    E.used[q->seg] &= (uint16_t)~(((1u << q->T) - 1u) << q->c0);
+    E.slot[i] = nullptr;
+    q->slot = -1;
+  }
 }
 
 bool cg_outstanding(const Engine& E) {
@@ -656,6 +673,7 @@ void take_releases(Engine& E) {
       E.slot[q->slot] = nullptr;
     }
     if (q->ready) E.ev_pool.push_back(q->ready);
+    if (q->fin) E.ev_pool.push_back(q->fin);
     if (q->lane >= 0) E.free_lanes.push_back(q->lane);
     delete q;
   }
@@ -771,6 +789,7 @@ int engine_loop(Engine& E) {
   uint64_t prev_seq = 0;
   for (;;) {
     take_releases(E);
+    reap_finished(E);
     RAKS_TRY(admit(E));
     if (any_exploring(E)) {
       E.any_vc = false;
