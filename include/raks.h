@@ -298,6 +298,9 @@ typedef struct {
     int32_t expand_wg_per_cu;
     int32_t admit_below;
     int32_t expand_tile;    /* examined arcs per expansion tile: 512, 1024 or 2048 (0 = 1024) */
+    int32_t cohort_cols;    /* columns of the cohort: 16, 32 or 64 (0 = 64); a narrower cohort
+                             * holds fewer queries at once and keeps its per-node reached masks
+                             * in 2 or 4 bytes instead of 8 */
 } raks_tuning;
 int raks_set_tuning(raks_ctx* ctx, const raks_tuning* t);
 

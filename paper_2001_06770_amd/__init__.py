@@ -34,7 +34,7 @@ class CtxOpts(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("expand_wg_per_cu", ctypes.c_int32), ("admit_below", ctypes.c_int32),
-                ("expand_tile", ctypes.c_int32)]
+                ("expand_tile", ctypes.c_int32), ("cohort_cols", ctypes.c_int32)]
 
 
 class ServeOpts(ctypes.Structure):
@@ -274,9 +274,10 @@ class Context:
         if batch_mode != RAKS_BATCH_COHORT:
             self.set_batch_mode(batch_mode)
 
-    def set_tuning(self, expand_wg_per_cu: int = 0, admit_below: int = 32, expand_tile: int = 0):
+    def set_tuning(self, expand_wg_per_cu: int = 0, admit_below: int = 32, expand_tile: int = 0,
+                   cohort_cols: int = 0):
         """Cohort path parameters (see raks_set_tuning)."""
-        t = Tuning(int(expand_wg_per_cu), int(admit_below), int(expand_tile))
+        t = Tuning(int(expand_wg_per_cu), int(admit_below), int(expand_tile), int(cohort_cols))
         _check(lib().raks_set_tuning(self._h, ctypes.byref(t)))
 
     def set_batch_mode(self, mode: int):

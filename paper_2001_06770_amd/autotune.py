@@ -7,11 +7,13 @@ path's parameters and keeps the fastest:
   many of the cohort's queries are still exploring (0: level-aligned waves,
   32: whenever a query fits);
 * ``expand_tile`` -- examined arcs per expansion tile (512, 1024, 2048);
-* ``expand_wg_per_cu`` -- workgroups per compute unit of the expansion.
+* ``expand_wg_per_cu`` -- workgroups per compute unit of the expansion;
+* ``cohort_cols`` -- columns of the cohort (16, 32, 64): fewer queries at once,
+  with smaller per-node reached masks for the expansion's gathers.
 
-The objective is the device time of the level kernels (frontier scan, control
-step, expansion) over the batch, from the library's event timers; the
-batch's wall time is recorded beside it.  The search is coordinate descent in
+The objective is the batch's wall time (the best of two runs); the device
+time of the level kernels (frontier scan, control step, expansion) from the
+library's event timers is recorded beside it.  The search is coordinate descent in
 the order above, starting from the library's defaults.  The result is a JSON
 file (``tuning/<workload>.json`` in this package) that ``bench.py`` applies.
 
@@ -30,9 +32,9 @@ ROOT = os.path.dirname(HERE)
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-SPACE = {"admit_below": (0, 4, 32), "expand_tile": (512, 1024, 2048),
+SPACE = {"cohort_cols": (16, 32, 64), "admit_below": (0, 4, 32), "expand_tile": (512, 1024, 2048),
          "expand_wg_per_cu": (4, 8, 16)}
-DEFAULT = {"admit_below": 32, "expand_tile": 1024, "expand_wg_per_cu": 8}
+DEFAULT = {"cohort_cols": 64, "admit_below": 32, "expand_tile": 1024, "expand_wg_per_cu": 8}
 
 
 def tuning_path(workload: str) -> str:
@@ -48,15 +50,21 @@ def load(workload: str):
         return json.load(f)["choice"]
 
 
-def measure(ctx, qs, setting, raks):
+def measure(ctx, qs, setting, raks, reps=2):
+    """Best wall time of the batch over `reps` runs, and the level kernels'
+    device time of that run."""
     ctx.set_tuning(**setting)
-    ctx.set_timing(True)
-    t0 = time.perf_counter()
-    ctx.query_batch(qs, lean=True)
-    wall = time.perf_counter() - t0
-    ms = sum(ctx.timing(k)["ms"] for k in (raks.TIMER_EXPAND, 1, 2))
-    ctx.set_timing(False)
-    return ms, wall
+    best = None
+    for _ in range(reps):
+        ctx.set_timing(True)
+        t0 = time.perf_counter()
+        ctx.query_batch(qs, lean=True)
+        wall = time.perf_counter() - t0
+        ms = sum(ctx.timing(k)["ms"] for k in (raks.TIMER_EXPAND, 1, 2))
+        ctx.set_timing(False)
+        if best is None or wall < best[1]:
+            best = (ms, wall)
+    return best
 
 
 def main():
@@ -83,9 +91,10 @@ def main():
     ctx.load_graph(g, alpha=0.5)
     ctx.query_batch(qs, lean=True)   # warm-up: lanes, buffers, code objects
     cur = dict(DEFAULT)
-    best_ms, _ = measure(ctx, qs, cur, raks)
-    trials = [{"setting": dict(cur), "level_kernel_ms": best_ms}]
-    print(f"# default {cur}: {best_ms:.1f} ms", file=sys.stderr, flush=True)
+    best_ms, best_wall = measure(ctx, qs, cur, raks)
+    trials = [{"setting": dict(cur), "level_kernel_ms": best_ms, "wall_s": best_wall}]
+    print(f"# default {cur}: {best_wall:.3f} s wall ({best_ms:.1f} ms level kernels)",
+          file=sys.stderr, flush=True)
     for key, values in SPACE.items():
         for val in values:
             if val == cur[key]:
@@ -93,13 +102,14 @@ def main():
             cand = dict(cur, **{key: val})
             ms, wall = measure(ctx, qs, cand, raks)
             trials.append({"setting": cand, "level_kernel_ms": ms, "wall_s": wall})
-            print(f"# {cand}: {ms:.1f} ms ({wall:.2f} s wall)", file=sys.stderr, flush=True)
-            if ms < best_ms:
-                best_ms, cur = ms, cand
+            print(f"# {cand}: {wall:.3f} s wall ({ms:.1f} ms level kernels)", file=sys.stderr,
+                  flush=True)
+            if wall < best_wall:
+                best_ms, best_wall, cur = ms, wall, cand
     ctx.close()
     out = {"workload": args.workload, "queries": qdesc,
-           "objective": "device ms of the level kernels (scan, control, expansion) per batch",
-           "choice": cur, "level_kernel_ms": best_ms, "trials": trials}
+           "objective": "wall time of the batch (best of 2 runs)",
+           "choice": cur, "wall_s": best_wall, "level_kernel_ms": best_ms, "trials": trials}
     with open(args.out, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out["choice"]))

@@ -1909,12 +1909,14 @@ int raks_set_tuning(raks_ctx* c, const raks_tuning* t) {
   if (!c || !t) return fail(RAKS_EINVAL, "NULL argument");
   if (t->expand_wg_per_cu < 0 || t->expand_wg_per_cu > 64 || t->admit_below < 0 ||
       (t->expand_tile != 0 && t->expand_tile != 512 && t->expand_tile != 1024 &&
-       t->expand_tile != 2048))
+       t->expand_tile != 2048) ||
+      (t->cohort_cols != 0 && t->cohort_cols != 16 && t->cohort_cols != 32 && t->cohort_cols != 64))
     return fail(RAKS_EINVAL, "tuning values out of range");
   if (c->serve.running) return fail(RAKS_ESTATE, "serving is running");
   c->co_wpc = t->expand_wg_per_cu ? t->expand_wg_per_cu : 8;
   c->co_admit_below = t->admit_below;
   c->co_tile = t->expand_tile ? t->expand_tile : 1024;
+  c->co_cols = t->cohort_cols ? t->cohort_cols : 64;
   return RAKS_OK;
 }
 

@@ -104,7 +104,9 @@ struct CohortView {
   int32_t nblocks, cpw;          // scan workgroups and 1024-node chunks per workgroup
   uint8_t* H;                    // [kCoSegs][n_pad][16]
   unsigned long long* R;         // [n_pad] reached mask: bit c set iff column c expands and
-                                 // its hitting level is finite at the start of the level
+                                 // its hitting level is finite at the start of the level;
+                                 // entries of rbytes bytes (the cohort's width / 8)
+  int32_t rbytes;                // 2, 4 or 8: the cohort uses the first rbytes / 2 segments
   CoSlot* slots;                 // [kCoSlots]
   CoAcc* acc;
   uint2* tot;                    // [nblocks] per scan workgroup: entries, examined arcs

@@ -37,6 +37,21 @@ __device__ inline uint8_t* seg_base(const CohortView& v, int seg) {
   return v.H + (size_t)seg * v.n_pad * 16;
 }
 
+// A node's reached mask in the cohort's width: a narrower cohort keeps its
+// masks in 2 or 4 bytes per node, so that the expansion's random gathers touch
+// a smaller array (it fits the 256 MB Infinity Cache on larger graphs).
+__device__ inline uint64_t r_get(const CohortView& v, int64_t i) {
+  if (v.rbytes == 2) return reinterpret_cast<const uint16_t*>(v.R)[i];
+  if (v.rbytes == 4) return reinterpret_cast<const uint32_t*>(v.R)[i];
+  return v.R[i];
+}
+
+__device__ inline void r_put(const CohortView& v, int64_t i, uint64_t x) {
+  if (v.rbytes == 2) reinterpret_cast<uint16_t*>(v.R)[i] = (uint16_t)x;
+  else if (v.rbytes == 4) reinterpret_cast<uint32_t*>(v.R)[i] = (uint32_t)x;
+  else v.R[i] = x;
+}
+
 // Bit 7 of each byte of x (only those bits set) -> 4-bit mask.
 __device__ inline uint32_t msb4(uint32_t x) { return ((x >> 7) * 0x10204080u) >> 28; }
 
@@ -289,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void k_co_scan(CohortView v, DevGraphView g
       if (vv < v.n) {
         // the reached mask of the running columns, as the expansion reads it
         const unsigned long long rnew = rfin & cfg.run;
-        if (v.R[vv] != rnew) v.R[vv] = rnew;
+        if (r_get(v, vv) != rnew) r_put(v, vv, rnew);
       }
       CoEntry e = {};
       uint32_t work = 0;
@@ -672,7 +687,7 @@ __global__ __launch_bounds__(kBlock) void k_co_expand(CohortView v, DevGraphView
       }
     }
 #pragma unroll
-    for (int k = 0; k < IPT; ++k) rv[k] = wantv[k] ? v.R[nbv[k]] : ~0ull;
+    for (int k = 0; k < IPT; ++k) rv[k] = wantv[k] ? r_get(v, nbv[k]) : ~0ull;
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
       // columns that have not reached the target (as of the start of the level)

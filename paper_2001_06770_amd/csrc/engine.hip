@@ -152,6 +152,7 @@ int engine_alloc(Engine& E) {
   v.cpw = cpw;
   v.H = P<uint8_t>(E.H);
   v.R = P<unsigned long long>(E.R);
+  v.rbytes = 8;
   v.slots = P<CoSlot>(E.slots);
   v.acc = P<CoAcc>(E.acc);
   v.tot = P<uint2>(E.tot);
@@ -269,10 +270,10 @@ int take_lane(Engine& E) {
   return id;
 }
 
-// First free run of T columns within one segment.
+// First free run of T columns within one segment of the cohort's width.
 bool find_cols(Engine& E, int T, int* seg, int* c0) {
   const uint32_t m = (1u << T) - 1u;
-  for (int s = 0; s < kCoSegs; ++s)
+  for (int s = 0; s < E.v.rbytes / 2; ++s)
     for (int x = 0; x + T <= 16; ++x)
       if (!((E.used[s] >> x) & m)) {
         *seg = s;
@@ -841,6 +842,18 @@ int engine_loop(Engine& E) {
   return RAKS_OK;
 }
 
+// The cohort's width (columns) from the context's tuning; set while the
+// cohort is empty, with the reached masks cleared for the new entry size.
+int set_width(Engine& E) {
+  const int rb = E.c->co_cols / 8;
+  if (E.v.rbytes == rb) return RAKS_OK;
+  E.v.rbytes = rb;
+  launch_co_init(E.v, E.stream);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamSynchronize(E.stream));
+  return RAKS_OK;
+}
+
 Engine* get_engine(Ctx* c, int* rc) {
   *rc = RAKS_OK;
   Engine* E = static_cast<Engine*>(c->engine);
@@ -889,6 +902,7 @@ int cohort_query_batch(Ctx* c, const raks_query_desc* qs, int32_t n, raks_result
   int rc = RAKS_OK;
   Engine* E = get_engine(c, &rc);
   if (!E) return rc;
+  RAKS_TRY(set_width(*E));
   std::vector<int> rcs((size_t)std::max(n, 0), RAKS_OK);
   std::vector<std::string> errs((size_t)std::max(n, 0));
   E->on_done = [&](CoQuery* q) {
@@ -947,6 +961,7 @@ int cohort_query_batch(Ctx* c, const raks_query_desc* qs, int32_t n, raks_result
 int cohort_serve_start(Ctx* c, int32_t queue_cap) {
   int rc = RAKS_OK;
   Engine* E = get_engine(c, &rc);
+  if (E) RAKS_TRY(set_width(*E));
   if (!E) return rc;
   ServeState& S = c->serve;
   S.queue_cap = queue_cap;

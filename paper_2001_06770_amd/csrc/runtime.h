@@ -196,7 +196,7 @@ struct Ctx {
   void* engine = nullptr;   // the cohort engine (engine.hip), created on first use
   // cohort tuning: expansion workgroups per CU; a batch admits new queries
   // only while at most admit_below queries of the cohort are exploring
-  int32_t co_wpc = 8, co_admit_below = 32, co_tile = 1024;
+  int32_t co_wpc = 8, co_admit_below = 32, co_tile = 1024, co_cols = 64;
 
   // timing
   std::atomic<uint32_t> timing{0};   // bit k: timer k is recorded

@@ -84,6 +84,26 @@ def test_cohort_mixed_shapes(raks, name):
         check(c.query_batch(qs), exp, qs)
 
 
+@pytest.mark.parametrize("cols", [16, 32])
+def test_cohort_narrow_widths(raks, cols):
+    """A cohort of 16 or 32 columns (2- or 4-byte reached masks, fewer queries
+    at once), then back to 64 in the same context: same results."""
+    g = synth.make_graph("small")
+    o = oracle.Oracle(g)
+    act = o.activation(g.abar, 0.5)
+    qs = mixed_queries(g, 48, seed=11)
+    exp = [o.query(act, q) for q in qs]
+    with raks.Context(0) as c:
+        c.load_graph(g, alpha=0.5)
+        print(f"[cohort] small, {cols} columns", flush=True)
+        c.set_tuning(cohort_cols=cols)
+        check(c.query_batch(qs), exp, qs)
+        c.set_tuning(cohort_cols=64)
+        check(c.query_batch(qs[:16]), exp[:16], qs[:16])
+        with pytest.raises(raks.RaksError):
+            c.set_tuning(cohort_cols=48)
+
+
 def test_cohort_node_mode(raks):
     g = synth.make_graph("small")
     o = oracle.Oracle(g)
