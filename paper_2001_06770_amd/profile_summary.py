@@ -9,9 +9,11 @@ dispatch, ``*_counter_collection.csv``).  Each counter is summed over every
 dispatch of the kernel, scaled by the factor a plain device copy gives for it
 (2.0 for FETCH_SIZE, 1.0 for WRITE_SIZE: a 1 GiB copy reads as 512 MiB of
 FETCH_SIZE and writes as 1 GiB of WRITE_SIZE), and divided by the number of
-dispatches, so that it compares with the line's per-launch algorithmic bytes
-(the profiled command runs without warm-up, so every dispatch belongs to the
-timed steps; the launches the benchmark timed are recorded beside it).  The record
+launches the benchmark timed in that run (its JSON line, ``roofline.launches``),
+so that it compares with the line's per-launch algorithmic bytes.  The profiled
+command runs without warm-up, so every dispatch belongs to the timed steps;
+dispatches that are not timed are expansion launches queued past a run's end,
+which exit at once.  The record
 carries the SHA-256 of the kernel's source file: the benchmark uses it only
 while the source is unchanged.
 
@@ -117,8 +119,8 @@ def traffic(args) -> dict:
     launches = bench_line(args.bench_json)["roofline"]["launches"]
     with open(os.path.join(HERE, "csrc", args.source), "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    fb = FETCH_SCALE * fetch * 1024.0 / nf
-    wb = WRITE_SCALE * write * 1024.0 / nw
+    fb = FETCH_SCALE * fetch * 1024.0 / launches
+    wb = WRITE_SCALE * write * 1024.0 / launches
     return {"kernel": args.kernel, "workload": args.workload,
             "bytes_per_launch": fb + wb, "fetch_bytes_per_launch": fb,
             "write_bytes_per_launch": wb, "dispatches": [nf, nw], "timed_launches": launches,
