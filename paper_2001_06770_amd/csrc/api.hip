@@ -144,8 +144,7 @@ std::vector<DevBuf*> lane_buffers(Lane* L) {
       &L->sel_sumh, &L->has_rpg, &L->sm, &L->key, &L->dmin, &L->ranked, &L->vc_cnt,
       &L->vc_tmp, &L->vc_off, &L->vc_nodes, &L->hpool, &L->nl, &L->al, &L->items, &L->sort_a,
       &L->sort_b, &L->cg_nodes, &L->cg_arcs, &L->cg_cnt, &L->hdr, &L->out_nodes, &L->out_arcs,
-      &L->bigf, &L->big_bm, &L->big_chunk, &L->big_slot, &L->co_ccnt, &L->co_coff,
-      &L->co_ccur, &L->co_cst};
+      &L->bigf, &L->big_bm, &L->big_chunk, &L->big_slot};
   for (RecPhase& P : L->ph)
     for (DevBuf* b : {&P.layout, &P.cnt, &P.iflag, &P.lcnt, &P.touch, &P.tcnt}) v.push_back(b);
   v.push_back(&L->lab);

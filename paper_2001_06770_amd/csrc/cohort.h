@@ -157,13 +157,9 @@ void launch_co_expand(const CohortView& v, const DevGraphView& g, int level, int
                       hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // CG selection input of slot q (three launches), then the selection kernel
 void launch_co_cand(const CoCandView& cv, const CohortView& v, hipStream_t s);
-// After slot q's CG recovery (on its lane's stream): its outcome in the mirror
-// and its D_j minima reset
+// After slot q's CG recovery: V_C ready unless a recovery capacity ran out
 void launch_co_cg_done(const CohortView& v, int q, const Status* gst, uint64_t seq,
                        hipStream_t s);
-// On the cohort stream, once the host has seen a CG stage without overflow:
-// V_C is ready and the RPG check of slot q starts
-void launch_co_set_cg(const CohortView& v, int q, int32_t nsel, hipStream_t s);
 // Final marginal decision (Theorem 4 replayed up to the exploration's end)
 void launch_co_rpg_final(const CohortView& v, int q, hipStream_t s);
 // D_j minima over V_C for every slot whose marginal run is checked (q < 0), or

@@ -800,6 +800,10 @@ __global__ __launch_bounds__(kBlock) void k_co_cg_done(CohortView v, int q, cons
   for (int i = threadIdx.x; i < kMaxW * kMaxKw; i += kBlock) dm[i] = kInf;
   __syncthreads();
   if (threadIdx.x == 0) {
+    if (!ovf) {
+      v.slots[q].nsel = nsel;
+      v.slots[q].vc_ready = 1;
+    }
     v.mirror->cg_ovf[q] = ovf;
     v.mirror->cg_nsel[q] = nsel;
     __threadfence_system();
@@ -1053,17 +1057,6 @@ void launch_co_cand(const CoCandView& cv, const CohortView& v, hipStream_t s) {
 void launch_co_cg_done(const CohortView& v, int q, const Status* gst, uint64_t seq,
                        hipStream_t s) {
   k_co_cg_done<<<1, kBlock, 0, s>>>(v, q, gst, seq);
-}
-
-// Slot q's CG stage has finished without overflow: its RPG check may start.
-// Launched on the cohort stream, so the slot is never written by two streams.
-__global__ void k_co_set_cg(CoSlot* slots, int q, int32_t nsel) {
-  slots[q].nsel = nsel;
-  slots[q].vc_ready = 1;
-}
-
-void launch_co_set_cg(const CohortView& v, int q, int32_t nsel, hipStream_t s) {
-  k_co_set_cg<<<1, 1, 0, s>>>(v.slots, q, nsel);
 }
 
 void launch_co_dmin(const CohortView& v, int q, int grid, hipStream_t s) {

@@ -60,7 +60,6 @@ struct CoQuery {
   uint64_t cg_seq = 0;
   hipEvent_t ready = nullptr;     // lane stream: counters, copy-out and reset done
   hipEvent_t fin = nullptr;       // cohort stream: the final marginal decision is written
-  hipEvent_t cg_ev = nullptr;     // cohort stream: queued work the CG stage waits for
   double t_submit = 0, t_admit = 0;
   // outcome
   raks_results* res = nullptr;
@@ -81,7 +80,7 @@ struct Engine {
   Ctx* c = nullptr;
   hipStream_t stream = nullptr;
   CohortView v = {};
-  DevBuf H, R, slots, acc, tot, wpre, qpre, wtot, stage, dmin;
+  DevBuf H, R, slots, acc, tot, wpre, qpre, wtot, stage, cand, ccnt, coff, ccur, cst, dmin;
   bool any_vc = false;   // some slot's marginal run is checked (V_C ready): minima each level
   CoMirror* h_mir = nullptr;
   CoMirror* d_mir = nullptr;
@@ -130,6 +129,11 @@ int engine_alloc(Engine& E) {
   RAKS_TRY(dev_alloc(c, E.qpre, (size_t)(nb + 1) * 4));
   RAKS_TRY(dev_alloc(c, E.wtot, 16));
   RAKS_TRY(dev_alloc(c, E.stage, (size_t)n_pad * sizeof(CoEntry)));
+  RAKS_TRY(dev_alloc(c, E.cand, (size_t)n_pad * 8));
+  RAKS_TRY(dev_alloc(c, E.ccnt, (size_t)nb * 4));
+  RAKS_TRY(dev_alloc(c, E.coff, (size_t)nb * 4));
+  RAKS_TRY(dev_alloc(c, E.ccur, 16));
+  RAKS_TRY(dev_alloc(c, E.cst, sizeof(RunStatus)));
   RAKS_TRY(dev_alloc(c, E.dmin, (size_t)kCoSlots * kMaxW * kMaxKw * 4));
   if (!E.h_mir) {
     void* hp = nullptr;
@@ -158,6 +162,7 @@ int engine_alloc(Engine& E) {
   v.stage = P<CoEntry>(E.stage);
   v.mirror = E.d_mir;
   v.dmin = P<uint32_t>(E.dmin);
+  HIP_OK(hipMemsetAsync(E.ccur.p, 0, 16, E.stream));
   HIP_OK(hipMemsetAsync(E.wtot.p, 0, 16, E.stream));
   launch_co_init(v, E.stream);
   HIP_OK(hipGetLastError());
@@ -190,7 +195,7 @@ int engine_create(Ctx* c, Engine** out) {
   const int rc = engine_alloc(*E);
   if (rc) {
     for (DevBuf* b : {&E->H, &E->R, &E->slots, &E->acc, &E->tot, &E->wpre, &E->qpre, &E->wtot, &E->stage,
-                      &E->dmin})
+                      &E->cand, &E->ccnt, &E->coff, &E->ccur, &E->cst, &E->dmin})
       dev_free(c, *b);
     if (E->h_mir) (void)hipHostFree(E->h_mir);
     (void)hipStreamDestroy(E->stream);
@@ -351,12 +356,6 @@ int admit(Engine& E) {
       Borrow b(L, E.stream);
       rc = ensure_small_buffers(L);
       if (!rc) rc = dev_alloc(c, L->Hq, (size_t)E.v.n_pad * 16);
-      // the CG stage's candidate scratch (it runs on the lane's stream)
-      if (!rc) rc = dev_alloc(c, L->cand, (size_t)E.v.n_pad * 8);
-      if (!rc) rc = dev_alloc(c, L->co_ccnt, (size_t)E.v.nblocks * 4);
-      if (!rc) rc = dev_alloc(c, L->co_coff, (size_t)E.v.nblocks * 4);
-      if (!rc) rc = dev_alloc(c, L->co_ccur, 16);
-      if (!rc) rc = dev_alloc(c, L->co_cst, sizeof(RunStatus));
       if (!rc) {
         phase_reset(c, L->ph[0], q->p.w, q->p.C);
         phase_reset(c, L->ph[1], q->p.n_build, q->p.M);
@@ -504,37 +503,28 @@ int wait_level(Engine& E, int level, uint64_t want) {
 }
 
 // The CG stage of a query whose central run has ended (cohort stream).
-// The CG stage of a query whose central run has ended, on its lane's stream
-// beside the next levels: its central columns no longer change, and it reads
-// only those (the level kernels may write its marginal columns meanwhile).
-// The lane waits for what the cohort stream has queued so far (the last
-// central-run levels, the query's admission and layout uploads).
 int enqueue_cg(Engine& E, CoQuery* q) {
   Ctx* c = E.c;
   Lane* L = q->L;
-  hipStream_t s = L->stream;
-  if (!q->cg_ev) q->cg_ev = take_event(E);
-  if (!q->cg_ev) return fail(RAKS_EDEVICE, "event creation failed");
-  HIP_OK(hipEventRecord(q->cg_ev, E.stream));
-  HIP_OK(hipStreamWaitEvent(s, q->cg_ev, 0));
-  HIP_OK(hipMemsetAsync(L->co_ccur.p, 0, 16, s));   // the candidate cursors start at zero
+  Borrow b(L, E.stream);
+  hipStream_t s = E.stream;
   Status* st = P<Status>(L->status);
   const uint8_t* Hc = seg_ptr(E, q->seg, q->c0);
   CoCandView cv;
   cv.Hc = Hc;
   cv.C = q->p.C;
   cv.end = q->c_end;
-  cv.cnt = P<uint32_t>(L->co_ccnt);
-  cv.off = P<uint32_t>(L->co_coff);
-  cv.cursor = P<uint32_t>(L->co_ccur);
-  cv.cand = P<uint64_t>(L->cand);
-  cv.st = P<RunStatus>(L->co_cst);
+  cv.cnt = P<uint32_t>(E.ccnt);
+  cv.off = P<uint32_t>(E.coff);
+  cv.cursor = P<uint32_t>(E.ccur);
+  cv.cand = P<uint64_t>(E.cand);
+  cv.st = P<RunStatus>(E.cst);
   cv.orig_id = P<int32_t>(c->orig_id);
   launch_co_cand(cv, E.v, s);
   SelectView sv;
   sv.int_id = P<int32_t>(c->int_id);
-  sv.cand = P<uint64_t>(L->cand);
-  sv.st = P<RunStatus>(L->co_cst);
+  sv.cand = P<uint64_t>(E.cand);
+  sv.st = P<RunStatus>(E.cst);
   sv.gst = st;
   sv.w = q->p.w;
   sv.sel_node = P<int32_t>(L->sel_node);
@@ -567,13 +557,15 @@ __global__ void k_co_set_vc(CoSlot* slots, int q, const int32_t* vc_nodes) {
 int redo_cg(Engine& E, CoQuery* q, int ovf, int nsel) {
   Lane* L = q->L;
   if (++q->cg_attempts >= 24) return fail(RAKS_ENOMEM, "recovered subgraphs exceed the recovery capacity");
-  if (ovf & 1) RAKS_TRY(grow_phase(L, 0, nsel, q->c_end));
-  if (ovf & kOvfBig0) q->big0 = true;
-  HIP_OK(hipStreamSynchronize(L->stream));
-  RAKS_TRY(ensure_recovery(L, q->p));
-  // the slot's V_C pointer may have moved; the slot is written on the cohort stream
-  k_co_set_vc<<<1, 1, 0, E.stream>>>(E.v.slots, q->slot, P<int32_t>(L->vc_nodes));
-  launch_retry_reset(P<Status>(L->status), L->stream);
+  {
+    Borrow b(L, E.stream);
+    if (ovf & 1) RAKS_TRY(grow_phase(L, 0, nsel, q->c_end));
+    if (ovf & kOvfBig0) q->big0 = true;
+    HIP_OK(hipStreamSynchronize(E.stream));
+    RAKS_TRY(ensure_recovery(L, q->p));
+    k_co_set_vc<<<1, 1, 0, E.stream>>>(E.v.slots, q->slot, P<int32_t>(L->vc_nodes));
+    launch_retry_reset(P<Status>(L->status), E.stream);
+  }
   return enqueue_cg(E, q);
 }
 
@@ -609,13 +601,8 @@ int poll_cg(Engine& E) {
     if (!q || !q->cg_sent || q->cg_ok) continue;
     if (__atomic_load_n(&E.h_mir->cg_seq[i], __ATOMIC_ACQUIRE) != q->cg_seq) continue;
     const int ovf = E.h_mir->cg_ovf[i];
-    if (!ovf) {
-      q->cg_ok = true;
-      launch_co_set_cg(E.v, q->slot, E.h_mir->cg_nsel[i], E.stream);
-      HIP_OK(hipGetLastError());
-    } else {
-      RAKS_TRY(redo_cg(E, q, ovf, E.h_mir->cg_nsel[i]));
-    }
+    if (!ovf) q->cg_ok = true;
+    else RAKS_TRY(redo_cg(E, q, ovf, E.h_mir->cg_nsel[i]));
   }
   for (int i = 0; i < kCoSlots; ++i) {
     CoQuery* q = E.slot[i];
@@ -688,7 +675,6 @@ void take_releases(Engine& E) {
     }
     if (q->ready) E.ev_pool.push_back(q->ready);
     if (q->fin) E.ev_pool.push_back(q->fin);
-    if (q->cg_ev) E.ev_pool.push_back(q->cg_ev);
     if (q->lane >= 0) E.free_lanes.push_back(q->lane);
     delete q;
   }
@@ -832,18 +818,11 @@ int engine_loop(Engine& E) {
     }
     RAKS_TRY(poll_cg(E));
     if (cg_outstanding(E)) {
-      // the CG stages run on their lanes' streams: once those are idle, every
-      // stage has published its outcome
-      bool idle = true;
-      for (int i = 0; i < kCoSlots; ++i) {
-        const CoQuery* q = E.slot[i];
-        if (!q || !q->cg_sent || q->cg_ok) continue;
-        const hipError_t e = hipStreamQuery(q->L->stream);
-        if (e != hipSuccess && e != hipErrorNotReady)
-          return fail(RAKS_EDEVICE, std::string("lane stream failed: ") + hipGetErrorString(e));
-        idle &= e == hipSuccess;
-      }
-      if (idle) {
+      const hipError_t e = hipStreamQuery(E.stream);
+      if (e != hipSuccess && e != hipErrorNotReady)
+        return fail(RAKS_EDEVICE, std::string("cohort stream failed: ") + hipGetErrorString(e));
+      if (e == hipSuccess) {
+        // the stream is idle: every CG stage has published its outcome
         RAKS_TRY(poll_cg(E));
         if (cg_outstanding(E)) return fail(RAKS_EDEVICE, "a CG stage outcome was not published");
         continue;
@@ -908,7 +887,7 @@ void cohort_destroy(Ctx* c) {
   stop_workers(*E);
   (void)hipStreamSynchronize(E->stream);
   for (DevBuf* b : {&E->H, &E->R, &E->slots, &E->acc, &E->tot, &E->wpre, &E->qpre, &E->wtot, &E->stage,
-                    &E->dmin})
+                    &E->cand, &E->ccnt, &E->coff, &E->ccur, &E->cst, &E->dmin})
     dev_free(c, *b);
   for (hipEvent_t e : E->ev_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : E->tev_pool) (void)hipEventDestroy(e);

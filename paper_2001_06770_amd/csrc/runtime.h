@@ -98,7 +98,6 @@ struct Lane {
   DevBuf cg_nodes, cg_arcs, cg_cnt;   // CG lists, kept for the marginal phase
   DevBuf hdr, out_nodes, out_arcs, status;
   DevBuf Hq;                          // cohort path: the query's hitting levels, [n_pad][TPq]
-  DevBuf co_ccnt, co_coff, co_ccur, co_cst;   // cohort path: CG candidates (keys in `cand`)
   DevBuf bigf, big_bm, big_chunk, big_slot;   // bitmap path of large results
   RecPhase ph[2];                     // [0] CG recovery, [1] RPG recovery + output
   DevBuf lab;                         // labels of the labelled mode, [T * G][n] words
