@@ -63,9 +63,9 @@ struct CoSlotMirror {
   uint64_t seq;
 };
 
-// One level's status.  Level l writes section l & 1: the host reads level l
-// while level l+1 already runs, so a single section could be overwritten
-// before the host saw it.
+// One level's status.  Level l writes section l % kCoMirrors: the host reads
+// level l while up to kCoAhead later levels are already queued, so fewer
+// sections could be overwritten before the host saw them.
 struct CoLevelMirror {
   uint32_t W, nq;
   uint32_t pad[2];
@@ -74,8 +74,11 @@ struct CoLevelMirror {
   CoSlotMirror slot[kCoSlots];
 };
 
+constexpr int kCoAhead = 2;     // levels the host keeps queued beyond the one it reads
+constexpr int kCoMirrors = 4;   // > kCoAhead, a power of two
+
 struct CoMirror {
-  CoLevelMirror lvl[2];
+  CoLevelMirror lvl[kCoMirrors];
   // outcome of each slot's central-graph stage (recovery overflow bits, nsel)
   int32_t cg_ovf[kCoSlots];
   int32_t cg_nsel[kCoSlots];

@@ -493,7 +493,7 @@ __global__ __launch_bounds__(kCtlT) void k_co_control(CohortView v, int level, u
     if (threadIdx.x < kCoSlots) v.acc->ncand[(level + 1) & 1][threadIdx.x] = 0;
     __syncthreads();
     if (threadIdx.x == 0) {
-      CoLevelMirror* mir = &v.mirror->lvl[level & 1];
+      CoLevelMirror* mir = &v.mirror->lvl[level & (kCoMirrors - 1)];
       mir->W = tt[1];
       mir->nq = tt[0];
       __threadfence_system();
@@ -556,7 +556,7 @@ __global__ __launch_bounds__(kCtlT) void k_co_control(CohortView v, int level, u
   // query's slot belongs to its post-processing (other streams) until reuse
   if (threadIdx.x == 0) {
     if (s_live) v.slots[q] = s;
-    co_publish_slot(&v.mirror->lvl[level & 1], q, s, seq);
+    co_publish_slot(&v.mirror->lvl[level & (kCoMirrors - 1)], q, s, seq);
   }
 }
 

@@ -479,7 +479,7 @@ int enqueue_level(Engine& E, int level, uint64_t seq) {
 // its status in the level's mirror section.  A stream that failed, or that
 // has finished without the status, ends the wait with an error.
 int wait_level(Engine& E, int level, uint64_t want) {
-  const CoLevelMirror* m = &E.h_mir->lvl[level & 1];
+  const CoLevelMirror* m = &E.h_mir->lvl[level & (kCoMirrors - 1)];
   auto published = [&] {
     bool done = __atomic_load_n(&m->seq, __ATOMIC_ACQUIRE) == want;
     for (int q = 0; done && q < kCoSlots; ++q)
@@ -573,14 +573,14 @@ int process_level(Engine& E, int level) {
   {
     // algorithmic bytes of the level's expansion: per examined arc its
     // neighbour id, its level and the neighbour's reached mask; per entry 24
-    const CoLevelMirror& lm = E.h_mir->lvl[level & 1];
+    const CoLevelMirror& lm = E.h_mir->lvl[level & (kCoMirrors - 1)];
     for (auto& t : E.timed)
       if (t.kind == 0 && t.level == level) t.bytes = (4.0 + 1.0 + 8.0) * lm.W + 24.0 * lm.nq;
   }
   for (int i = 0; i < kCoSlots; ++i) {
     CoQuery* q = E.slot[i];
     if (!q || q->x_done || q->start > level) continue;
-    const CoSlotMirror m = E.h_mir->lvl[level & 1].slot[i];
+    const CoSlotMirror m = E.h_mir->lvl[level & (kCoMirrors - 1)].slot[i];
     if (!q->c_done && !m.c_run) {
       q->c_done = true;
       q->c_end = m.c_end;
@@ -785,9 +785,11 @@ bool posts_busy(Engine& E) {
 int engine_loop(Engine& E) {
   Ctx* c = E.c;
   (void)hipSetDevice(c->device);
-  bool have_prev = false;
-  int prev_level = 0;
-  uint64_t prev_seq = 0;
+  // levels queued and not yet read, oldest first: the host reads level l while
+  // up to kCoAhead later levels are queued, so the device does not wait for
+  // the host's admissions and hand-offs between levels (every run decision is
+  // the control step's, on the device)
+  std::deque<std::pair<int, uint64_t>> inflight;
   for (;;) {
     take_releases(E);
     reap_finished(E);
@@ -798,21 +800,22 @@ int engine_loop(Engine& E) {
         E.any_vc |= E.slot[i] && !E.slot[i]->x_done && E.slot[i]->cg_sent && E.slot[i]->p.M > 0;
       const uint64_t sq = ++E.seq;
       RAKS_TRY(enqueue_level(E, E.level, sq));
-      if (have_prev) {
-        RAKS_TRY(wait_level(E, prev_level, prev_seq));
-        RAKS_TRY(process_level(E, prev_level));
-      }
-      have_prev = true;
-      prev_level = E.level;
-      prev_seq = sq;
+      inflight.emplace_back(E.level, sq);
       ++E.level;
+      if ((int)inflight.size() > kCoAhead) {
+        const auto lv = inflight.front();
+        inflight.pop_front();
+        RAKS_TRY(wait_level(E, lv.first, lv.second));
+        RAKS_TRY(process_level(E, lv.first));
+      }
       RAKS_TRY(poll_cg(E));
       continue;
     }
-    if (have_prev) {
-      RAKS_TRY(wait_level(E, prev_level, prev_seq));
-      RAKS_TRY(process_level(E, prev_level));
-      have_prev = false;
+    if (!inflight.empty()) {
+      const auto lv = inflight.front();
+      inflight.pop_front();
+      RAKS_TRY(wait_level(E, lv.first, lv.second));
+      RAKS_TRY(process_level(E, lv.first));
       RAKS_TRY(poll_cg(E));
       continue;
     }
