@@ -31,7 +31,11 @@ namespace raks {
 
 namespace {
 
-constexpr int kCtlT = 1024;
+// Threads of the one-workgroup-per-slot kernels (control step, final RPG
+// decision, candidate scan): small, so that such a workgroup finds room on a
+// CU beside the recovery kernels of other queries' lanes, which it otherwise
+// waits for on the level loop's critical path.
+constexpr int kCtlT = 256;
 
 __device__ inline uint8_t* seg_base(const CohortView& v, int seg) {
   return v.H + (size_t)seg * v.n_pad * 16;
@@ -466,22 +470,26 @@ __device__ inline void co_publish_slot(CoLevelMirror* mir, int q, const CoSlot& 
 
 __global__ __launch_bounds__(kCtlT) void k_co_control(CohortView v, int level, uint64_t seq) {
   if (blockIdx.x == 0) {
-    // queue prefixes of the level (at most two scan workgroups per thread)
+    // queue prefixes of the level: each thread takes a run of `per` scan
+    // workgroups
     __shared__ uint32_t s_m32[(kCtlT / kWave + 1) * 2];
     const int nb = v.nblocks;
     const int per = (nb + kCtlT - 1) / kCtlT;
     const int b0 = min(nb, (int)threadIdx.x * per), b1 = min(nb, b0 + per);
-    uint2 t[2] = {make_uint2(0, 0), make_uint2(0, 0)};
-    for (int i = 0; i < 2; ++i)
-      if (b0 + i < b1) t[i] = v.tot[b0 + i];
-    uint32_t x[2] = {t[0].x + t[1].x, t[0].y + t[1].y}, tt[2];
+    uint32_t x[2] = {0, 0}, tt[2];
+    for (int b = b0; b < b1; ++b) {
+      const uint2 t = v.tot[b];
+      x[0] += t.x;
+      x[1] += t.y;
+    }
     block_exclusive_scan_multi<2, kCtlT, uint32_t>(x, tt, s_m32);
     uint32_t q = x[0], w = x[1];
-    for (int i = 0; i < 2 && b0 + i < b1; ++i) {
-      v.qpre[b0 + i] = q;
-      v.wpre[b0 + i] = w;
-      q += t[i].x;
-      w += t[i].y;
+    for (int b = b0; b < b1; ++b) {
+      const uint2 t = v.tot[b];
+      v.qpre[b] = q;
+      v.wpre[b] = w;
+      q += t.x;
+      w += t.y;
     }
     if (threadIdx.x == 0) {
       v.qpre[nb] = tt[0];
