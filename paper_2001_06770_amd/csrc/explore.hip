@@ -644,21 +644,34 @@ __global__ __launch_bounds__(kBlock) void k_expand(RunView r, DevGraphView g, in
 #pragma unroll
     for (int k = 0; k < IPT; ++k) s_own[threadIdx.x * IPT + k] = (uint16_t)(pre > loc[k] ? pre : loc[k]);
     __syncthreads();
-#pragma unroll 4
+    // all of the thread's arcs at once: their targets, then the targets'
+    // reached masks, then the writes, so that a wavefront keeps IPT
+    // independent gathers in flight instead of one dependent chain per arc
+    int32_t nbv[IPT];
+    uint32_t wantv[IPT], rv[IPT];
+#pragma unroll
     for (int k = 0; k < IPT; ++k) {
       const uint32_t i = k * kBlock + threadIdx.x;
-      if (w0 + i >= w1) break;
-      const int j = s_own[i];
-      const uint32_t e = s_base[j] + i;
-      const uint32_t mk = s_mask[j];
-      const uint32_t want = (e < s_lo[j]) ? (mk & 0xFFFFu) : ((mk & 0xFFFFu) | (mk >> 16));
-      const int32_t nb = g.col_s[e];
-      // keywords that have not reached nb (as of the start of this level)
-      const uint32_t mm = ~RBits<TP>::get(r.R, nb) & want;
+      wantv[k] = 0;
+      nbv[k] = 0;
+      if (w0 + i < w1) {
+        const int j = s_own[i];
+        const uint32_t e = s_base[j] + i;
+        const uint32_t mk = s_mask[j];
+        wantv[k] = (e < s_lo[j]) ? (mk & 0xFFFFu) : ((mk & 0xFFFFu) | (mk >> 16));
+        nbv[k] = g.col_s[e];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) rv[k] = wantv[k] ? RBits<TP>::get(r.R, nbv[k]) : 0xFFFFFFFFu;
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      // keywords that have not reached the target (as of the start of this level)
+      const uint32_t mm = ~rv[k] & wantv[k];
       if (mm) {
 #pragma unroll
         for (int t = 0; t < TP; ++t)
-          if ((mm >> t) & 1u) r.H[(int64_t)nb * TP + t] = (uint8_t)(level + 1);
+          if ((mm >> t) & 1u) r.H[(int64_t)nbv[k] * TP + t] = (uint8_t)(level + 1);
       }
     }
     __syncthreads();
