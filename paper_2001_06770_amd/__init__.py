@@ -241,7 +241,11 @@ class Context:
 
     def __init__(self, device: int = 0, use_torch: bool = True, mem_budget: int = 0,
                  lanes: int = 1, rec_caps=(0, 0, 0), big_list: int = 0,
-                 batch_mode: int = RAKS_BATCH_COHORT):
+                 batch_mode: int = RAKS_BATCH_COHORT, poison=None):
+        """``poison`` (a byte, with ``use_torch``): every device buffer the
+        library allocates starts filled with it, so that a read of memory the
+        library never wrote gives wrong results instead of the zeros a fresh
+        allocation often happens to hold (a debugging aid)."""
         self._keep = []
         opts = CtxOpts()
         opts.device = device
@@ -257,14 +261,25 @@ class Context:
             stream = torch.cuda.current_stream(dev)
             opts.stream = ctypes.c_void_p(stream.cuda_stream)
 
+            live = {}
+
             def _alloc(size, _user, _torch=torch, _dev=device, _s=stream):
                 try:
-                    return _torch.cuda.caching_allocator_alloc(size, _dev, _s)
+                    if poison is None:
+                        return _torch.cuda.caching_allocator_alloc(size, _dev, _s)
+                    buf = _torch.empty(size, dtype=_torch.uint8, device=dev)
+                    buf.fill_(int(poison) & 0xFF)
+                    _torch.cuda.synchronize(dev)
+                    live[buf.data_ptr()] = buf
+                    return buf.data_ptr()
                 except Exception:
                     return None
 
             def _free(ptr, _size, _user, _torch=torch):
-                _torch.cuda.caching_allocator_delete(ptr)
+                if poison is None:
+                    _torch.cuda.caching_allocator_delete(ptr)
+                else:
+                    live.pop(ptr, None)
 
             opts.alloc = _ALLOC(_alloc)
             opts.free = _FREE(_free)

@@ -867,9 +867,11 @@ int ensure_recovery(Lane* L, const QueryPlan& p) {
   for (const RecPhase* P : {&P0, &P1})
     if (P->labelled) lw = std::max<uint64_t>(lw, (uint64_t)P->T * ((P->n_res + 63) / 64) * c->n);
   if (lw) {
+    // new memory holds anything, also when it comes back at the old address
     const void* before = L->lab.p;
+    const size_t before_bytes = L->lab.bytes;
     RAKS_TRY(dev_alloc(c, L->lab, lw * 8));
-    if (L->lab.p != before) L->lab_dirty = true;
+    if (L->lab.p != before || L->lab.bytes != before_bytes) L->lab_dirty = true;
   }
   return RAKS_OK;
 }
@@ -974,7 +976,10 @@ RecoverView recover_view(Lane* L, int ph, const uint8_t* H, int TP, const int32_
   if (Ph.labelled) {
     v.labelled = 1;
     v.G = (Ph.n_res + 63) / 64;
-    v.wipe = L->lab_dirty ? 1 : 0;
+    // the whole allocation, not only this phase's [T * G][n] words: a later
+    // phase of the same lane may use more columns or result groups, and it
+    // takes every word outside a phase for zero
+    v.wipe_words = L->lab_dirty ? L->lab.bytes / 8 : 0;
     L->lab_dirty = false;   // the launch clears it first
     v.lab = P<uint64_t>(L->lab);
     v.touch = P<uint64_t>(Ph.touch);

@@ -171,7 +171,8 @@ struct RecoverView {
   // labelled mode: one search per keyword column serves up to 64 results
   int32_t labelled;
   int32_t G;                 // label words per node and column (results / 64, rounded up)
-  int32_t wipe;              // clear all of `lab` first (it may hold stale bits)
+  uint64_t wipe_words;       // words of `lab` to clear first: all of its allocation when it
+                             // may hold stale bits (new memory, lost labels), else 0
   uint64_t* lab;             // [T * G][n] result bits per node; zero outside a phase
   uint64_t* touch;           // [tcap] (column group << 32) | node, per labelled node
   uint32_t* tcnt;            // entries of `touch` requested (counted past tcap)

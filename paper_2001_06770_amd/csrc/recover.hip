@@ -915,7 +915,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_vc(const uint32_t* vc_cnt, cons
 void launch_recover(const RecoverView& v, hipStream_t s) {
   if (v.n_inst <= 0) return;
   if (v.labelled) {
-    const size_t wipe = v.wipe ? (size_t)v.T * v.G * (uint32_t)v.g.n : 0;
+    const size_t wipe = (size_t)v.wipe_words;
     const unsigned gc = wipe ? 4096u : 64u;
     k_lr_clear<<<gc, kBlock, 0, s>>>(v, wipe);
     const unsigned grid = 1024;

@@ -48,6 +48,21 @@ def expected(entry):
     return {k: entry[k] for k in ("status", "n_cg", "stats", "results")}
 
 
+def diff_note(got, exp):
+    """The differing fields, compactly: which results differ, and how."""
+    out = [k for k in ("status", "n_cg", "stats") if got[k] != exp[k]]
+    gr, er = got["results"], exp["results"]
+    if len(gr) != len(er):
+        out.append(f"{len(gr)} results, expected {len(er)}")
+    for i, (a, b) in enumerate(zip(gr, er)):
+        d = {k: (a[k], b[k]) for k in ("central", "score_c", "score_m", "key", "n_nodes", "n_arcs")
+             if a[k] != b[k]}
+        same_lists = {k: a[k] == b[k] for k in ("nodes_sha256", "arcs_sha256")}
+        if d or not all(same_lists.values()):
+            out.append(f"result {i} (central {b['central']}): {d} lists equal {same_lists}")
+    return "; ".join(out)
+
+
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("name", ["large", "batch", "serve"])
 def test_full_size_golden(name):
@@ -74,12 +89,13 @@ def test_full_size_golden(name):
         if name != "batch":
             alone = [digest(c.query(q, lean=True)) for q in qs]
             for e, q, r in zip(gold["queries"], qs, alone):
-                assert r == expected(e), (name, "alone", e["index"], q)
+                assert r == expected(e), (name, "alone", e["index"], q, diff_note(r, expected(e)))
         if name in ("large", "batch"):
             print(f"[golden] {name}: cohort batch", flush=True)
             got = c.query_batch(qs, lean=True)
             for e, q, r in zip(gold["queries"], qs, got):
-                assert digest(r) == expected(e), (name, "batch", e["index"], q)
+                d = digest(r)
+                assert d == expected(e), (name, "batch", e["index"], q, diff_note(d, expected(e)))
         if name == "serve":
             print(f"[golden] {name}: served mix", flush=True)
             c.serve_start()
@@ -93,7 +109,7 @@ def test_full_size_golden(name):
                 c.serve_stop()
             for e, q, r, a in zip(gold["queries"], qs, served, alone):
                 d = digest(r)
-                assert d == expected(e), (name, "served", e["index"], q)
+                assert d == expected(e), (name, "served", e["index"], q, diff_note(d, expected(e)))
                 assert d == a, (name, "served != alone", e["index"], q)
         del exp
     finally:
