@@ -136,3 +136,28 @@ def test_medium_node_golden():
             assert digest(c.query(q, lean=True)) == expected(e), ("alone", e["index"], q)
         for e, q, r in zip(gold["queries"], qs, c.query_batch(qs, lean=True)):
             assert digest(r) == expected(e), ("batch", e["index"], q)
+
+
+@pytest.mark.timeout(600)
+def test_batch_golden_poisoned_memory():
+    """All 256 queries of the batch workload as one cohort batch, with every
+    device buffer of the library starting filled with 0xFF: memory the library
+    reads before it writes (a label array cleared only in part once gave
+    results without their recovered nodes and arcs) changes the results."""
+    import paper_2001_06770_amd as raks
+    gold = golden("batch")
+    print("[golden] generating batch (poisoned allocations)", flush=True)
+    g = synth.make_graph("batch")
+    assert g.n_arcs == gold["n_arcs"]
+    c = raks.Context(0, lanes=4, poison=0xFF)
+    try:
+        c.load_graph(g, alpha=gold["alpha"])
+        qs = [synth.Query(tuple(e["central"]), tuple(e["marginal"]), e["k"], e["w"],
+                          e["max_level"]) for e in gold["queries"]]
+        got = c.query_batch(qs, lean=True)
+        for e, q, r in zip(gold["queries"], qs, got):
+            d = digest(r)
+            assert d == expected(e), ("batch poisoned", e["index"], q, diff_note(d, expected(e)))
+    finally:
+        c.close()
+        synth.make_graph.cache_clear()
