@@ -248,7 +248,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the search shards by query across GPUs, see the design notes)", file=sys.stderr)
+              "(queries are independent: several GPUs would each hold the graph and take a "
+              "share of the queries)", file=sys.stderr)
         sys.exit(2)
 
     import torch
