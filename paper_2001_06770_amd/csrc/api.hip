@@ -1447,6 +1447,9 @@ int query_on_lane(Lane* L, const raks_query_desc* q, raks_results** out) {
   RAKS_TRY(acquire_view(L, p.alpha));
   const int rc = query_plan_on_lane(L, p, out, nullptr, t0);
   release_view(L);
+  // a query that failed may have left labels behind (a phase that lost node-log
+  // entries and was not repeated): the lane's next labelled search clears them
+  if (rc != RAKS_OK) L->lab_dirty = true;
   return rc;
 }
 
@@ -1463,6 +1466,7 @@ int query_on_lane_into(Lane* L, const raks_query_desc* q, raks_results_buf* out)
   RAKS_TRY(acquire_view(L, p.alpha));
   const int rc = query_plan_on_lane(L, p, nullptr, out, t0);
   release_view(L);
+  if (rc != RAKS_OK) L->lab_dirty = true;   // as in query_on_lane
   return rc;
 }
 

@@ -311,6 +311,10 @@ bool slots_busy(const Engine& E) {
 void finish(Engine& E, CoQuery* q, int rc, const std::string& err) {
   q->rc = rc;
   q->err = err;
+  // a failed query may have left labels behind on its lane (a phase that lost
+  // node-log entries and was not repeated): the lane's next labelled search
+  // clears the whole label array
+  if (rc != RAKS_OK && q->L) q->L->lab_dirty = true;
   if (E.on_done) E.on_done(q);
 }
 
